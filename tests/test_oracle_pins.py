@@ -1,0 +1,309 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a closed form, a textbook
+construction, a symmetry of the continuous problem, brute force on a tiny
+grid, or an exactness statement of the paper.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from helm_inputs import constant_model, omega_for_ppw, smooth_random_model, workload
+from oracle.direct import SparseLU, relative_error, solve_dense
+from oracle.discretization import (Problem, axis_beta, layer_bounds, layers,
+                                   local_operator, point_source_rhs)
+from oracle.polarized import PolarizedTraces
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def _problem(n, p, ppw=10.0, model="const", seed=7, C=20.0):
+    nx, ny, nz = n if isinstance(n, tuple) else (n, n, n)
+    h = 1.0 / (max(nx, ny, nz) - 1)
+    if model == "const":
+        m = constant_model((nx, ny, nz), 1.0)
+        cmin = 1.0
+    else:
+        m = smooth_random_model((nx, ny, nz), 0.25, 2.0, 0.75, 1.25, seed)
+        cmin = 0.75
+    return Problem(m, h, omega_for_ppw(cmin, h, ppw), p, C)
+
+
+# --------------------------------------------------------------------------
+# operator structure
+# --------------------------------------------------------------------------
+
+def test_operator_is_complex_symmetric():
+    """H = H^T exactly (complex-symmetric divided form, reading R3)."""
+    pb = _problem((9, 8, 7), 2, model="rand")
+    H = pb.operator()
+    assert abs(H - H.T).max() == 0.0
+    # not Hermitian inside the PML
+    assert abs(H - H.conj().T).max() > 0.0
+
+
+def test_no_pml_matches_kronecker_sum_laplacian():
+    """Without PML, H is the textbook Kronecker sum of 1D second differences
+    (Dirichlet one node beyond the grid) plus omega^2 m."""
+    nx, ny, nz = 6, 5, 4
+    pb = _problem((nx, ny, nz), 0, model="rand")
+    h = pb.h
+
+    def d2(n):
+        e = np.ones(n)
+        return sp.diags([e[:-1], -2 * e, e[:-1]], [-1, 0, 1]) / h ** 2
+
+    Ix, Iy, Iz = (sp.identity(k) for k in (nx, ny, nz))
+    # unknown index i + nx (j + ny k): x is the fastest (rightmost) factor
+    lap = (sp.kron(sp.kron(Iz, Iy), d2(nx)) + sp.kron(sp.kron(Iz, d2(ny)), Ix)
+           + sp.kron(sp.kron(d2(nz), Iy), Ix))
+    ref = lap + sp.diags(pb.omega ** 2 * pb.m.ravel())
+    diff = abs(pb.operator() - ref).max()
+    assert diff <= 1e-9 * abs(ref).max()
+
+
+def test_no_pml_sine_modes_are_eigenvectors():
+    """Closed form: sin modes are eigenvectors of the Dirichlet 7-point
+    Laplacian with eigenvalue -(4/h^2) sum sin^2(pi k / (2(n+1)))."""
+    nx, ny, nz = 7, 6, 5
+    pb = _problem((nx, ny, nz), 0)
+    h = pb.h
+    H = pb.operator()
+    for (kx, ky, kz) in [(1, 1, 1), (3, 2, 4), (7, 6, 5)]:
+        vx = np.sin(np.pi * kx * np.arange(1, nx + 1) / (nx + 1))
+        vy = np.sin(np.pi * ky * np.arange(1, ny + 1) / (ny + 1))
+        vz = np.sin(np.pi * kz * np.arange(1, nz + 1) / (nz + 1))
+        v = (vz[:, None, None] * vy[None, :, None] * vx[None, None, :]).ravel()
+        lam = -(4 / h ** 2) * (np.sin(np.pi * kx / (2 * (nx + 1))) ** 2
+                               + np.sin(np.pi * ky / (2 * (ny + 1))) ** 2
+                               + np.sin(np.pi * kz / (2 * (nz + 1))) ** 2) + pb.omega ** 2
+        assert np.abs(H @ v - lam * v).max() <= 1e-9 * abs(lam) * np.abs(v).max()
+
+
+def test_pml_profile_placement():
+    """Reading R2: p PML nodes per face, origin at the half-node, sigma equal to
+    (C/delta)(d/delta)^2 (paper's profile), beta = 1/(1 + i sigma/omega)."""
+    n, p, h, om, C = 20, 4, 0.1, 3.0, 5.0
+    b, bh = axis_beta(n, p, h, om, C)
+    delta = p * h
+    # interior nodes and the two origin half-nodes are unstretched
+    assert np.all(b[p:n - p] == 1.0)
+    assert bh[p] == 1.0 and bh[n - p] == 1.0
+    # innermost PML node sits half a cell past the origin
+    sig = (C / delta) * (0.5 * h / delta) ** 2
+    assert b[p - 1] == pytest.approx(1 / (1 + 1j * sig / om), rel=1e-14)
+    assert b[n - p] == pytest.approx(1 / (1 + 1j * sig / om), rel=1e-14)
+    # outer half-node (where the Dirichlet value lives) is at d = delta
+    assert bh[0] == pytest.approx(1 / (1 + 1j * (C / delta) / om), rel=1e-14)
+    assert bh[n] == pytest.approx(1 / (1 + 1j * (C / delta) / om), rel=1e-14)
+    # profile is mirror symmetric and damps (Im beta < 0 inside the layer)
+    assert np.allclose(b, b[::-1]) and np.allclose(bh, bh[::-1])
+    assert np.all(b[:p].imag < 0)
+
+
+# --------------------------------------------------------------------------
+# the direct solve (the plain definition)
+# --------------------------------------------------------------------------
+
+def test_dense_and_sparse_direct_agree():
+    """Two independent solvers (LAPACK dense, SuperLU) on a tiny grid."""
+    pb = _problem(10, 3, model="rand")
+    H = pb.operator()
+    rng = np.random.default_rng(1)
+    F = rng.standard_normal((H.shape[0], 3)) + 1j * rng.standard_normal((H.shape[0], 3))
+    ud = solve_dense(H, F)
+    us = SparseLU(H).solve(F)
+    assert relative_error(us, ud).max() <= 1e-12
+
+
+def test_manufactured_solution():
+    """f = H u* for a seeded random u*; the direct solve returns u*."""
+    pb = _problem(18, 4, model="rand")
+    H = pb.operator()
+    rng = np.random.default_rng(11)
+    ustar = rng.standard_normal(H.shape[0]) + 1j * rng.standard_normal(H.shape[0])
+    u = SparseLU(H).solve(H @ ustar)
+    assert relative_error(u, ustar)[0] <= 1e-10
+
+
+def test_reciprocity():
+    """u_s(x_r) = u_r(x_s) (H symmetric) in a heterogeneous medium."""
+    pb = _problem(14, 3, model="rand", seed=3)
+    pts = [(4, 5, 6), (9, 7, 3), (6, 10, 9)]
+    F = point_source_rhs(pb.shape, pts, pb.h)
+    U = SparseLU(pb.operator()).solve(F)
+    nx, ny, _ = pb.n
+    idx = [i + nx * (j + ny * k) for (i, j, k) in pts]
+    G = U[idx, :]
+    assert np.abs(G - G.T).max() <= 1e-12 * np.abs(G).max()
+
+
+def test_centred_source_symmetries():
+    """A centred source in constant c gives a field invariant under the cube's
+    reflections and axis swaps."""
+    n = 15
+    pb = _problem(n, 3)
+    c = n // 2
+    u = SparseLU(pb.operator()).solve(point_source_rhs(pb.shape, [(c, c, c)], pb.h))
+    u = u[:, 0].reshape(pb.shape)        # [k, j, i]
+    scale = np.abs(u).max()
+    for v in (u[:, :, ::-1], u[:, ::-1, :], u[::-1], u.transpose(0, 2, 1),
+              u.transpose(2, 1, 0)):
+        assert np.abs(u - v).max() <= 1e-12 * scale
+
+
+def test_point_source_matches_free_space_green_function():
+    """Away from source and PML the field of a unit point source approximates
+    the outgoing free-space Green's function -exp(i omega r / c)/(4 pi r)
+    (Eq. Helmholtz with the e^{-i omega t} convention implied by the PML).
+    At 10 points per wavelength the paper reports about one digit."""
+    wl = workload("homogeneous-25")
+    pb = Problem(wl.m(), wl.h, wl.omega, wl.pml, wl.pml_C)
+    c = wl.n[0] // 2
+    u = SparseLU(pb.operator()).solve(point_source_rhs(pb.shape, [(c, c, c)], wl.h))
+    u = u[:, 0].reshape(pb.shape)
+    errs = []
+    for r in range(2, 6):
+        for (di, dj, dk) in [(r, 0, 0), (0, -r, 0), (0, 0, r), (r, r, 0)]:
+            rr = wl.h * math.sqrt(di * di + dj * dj + dk * dk)
+            g = -np.exp(1j * wl.omega * rr) / (4 * np.pi * rr)
+            errs.append(abs(u[c + dk, c + dj, c + di] / g - 1))
+    assert np.mean(errs) <= 0.1
+    assert max(errs) <= 0.2
+
+
+def test_pml_absorbs():
+    """A larger domain with the same PML gives nearly the same interior field:
+    the absorbing layer (not the grid edge) terminates the problem."""
+    h = 1.0 / 24
+    om = omega_for_ppw(1.0, h, 10.0)
+    small = Problem(constant_model((17, 17, 17)), h, om, 5, 20.0)
+    big = Problem(constant_model((27, 27, 27)), h, om, 5, 20.0)
+    us = SparseLU(small.operator()).solve(point_source_rhs(small.shape, [(8, 8, 8)], h))
+    ub = SparseLU(big.operator()).solve(point_source_rhs(big.shape, [(13, 13, 13)], h))
+    us = us[:, 0].reshape(small.shape)[5:12, 5:12, 5:12]
+    ub = ub[:, 0].reshape(big.shape)[10:17, 10:17, 10:17]
+    assert relative_error(us.ravel(), ub.ravel())[0] <= 0.05
+
+
+# --------------------------------------------------------------------------
+# layer decomposition and the method's exactness statements
+# --------------------------------------------------------------------------
+
+def test_layer_bounds_cover_grid():
+    for nz, p, L in [(25, 6, 3), (200, 15, 20), (100, 10, 10), (31, 4, 7)]:
+        b = layer_bounds(nz, p, L)
+        assert b[0][0] == 0 and b[-1][1] == nz - 1
+        for (s0, e0), (s1, _) in zip(b[:-1], b[1:]):
+            assert s1 == e0 + 1
+        sizes = [e - s + 1 for (s, e) in b]
+        sizes[0] -= p
+        sizes[-1] -= p
+        assert max(sizes) - min(sizes) <= 1 and sum(sizes) == nz - 2 * p
+    assert layer_bounds(25, 6, 3) == [(0, 10), (11, 14), (15, 24)]
+
+
+def test_local_bulk_rows_equal_global_rows():
+    """Reading R6: every bulk row of H^l has exactly the global coefficients."""
+    pb = _problem((8, 7, 22), 3, model="rand")
+    L, alpha = 3, 3
+    H = pb.operator().tocsr()
+    nx, ny, _ = pb.n
+    for g in layers(pb, L, alpha):
+        Hl = local_operator(pb, L, alpha, g.index).tocsr()
+        for z in range(g.s, g.e + 1):
+            for j in range(ny):
+                for i in range(nx):
+                    rg = i + nx * (j + ny * z)
+                    rl = i + nx * (j + ny * (z - g.lo))
+                    cg = H.getrow(rg)
+                    cl = Hl.getrow(rl)
+                    # global column -> local column (shift by the first plane)
+                    vals_g = sorted((c - nx * ny * g.lo, v) for c, v in zip(cg.indices, cg.data))
+                    vals_l = sorted(zip(cl.indices, cl.data))
+                    assert len(vals_g) == len(vals_l)
+                    for (c1, v1), (c2, v2) in zip(vals_g, vals_l):
+                        assert c1 == c2 and v1 == v2
+
+
+@pytest.fixture(scope="module")
+def homog25():
+    wl = workload("homogeneous-25")
+    pb = Problem(wl.m(), wl.h, wl.omega, wl.pml, wl.pml_C)
+    F = point_source_rhs(pb.shape, wl.sources, wl.h)
+    u = SparseLU(pb.operator()).solve(F)[:, 0]
+    pt = PolarizedTraces(pb, wl.n_layers, wl.pml_local)
+    return wl, pb, F[:, 0].reshape(pb.shape), u.reshape(pb.shape), pt
+
+
+def test_green_representation_is_exact(homog25):
+    """Reading R8: local solves with the interface measures reproduce the global
+    solution in each layer's bulk and vanish on its local PML planes
+    (Algorithm 2 lines 10-12; exactness stated in the SIE reduction section)."""
+    wl, pb, f, u, pt = homog25
+    tr = pt.traces_of(u)
+    scale = np.abs(u).max()
+    for l, g in enumerate(pt.geo):
+        src = pt.restrict_source(l, f)
+        if l >= 1:
+            pt.add_J_top(l, src, tr[l - 1])
+        if l <= pt.L - 2:
+            pt.add_J_bot(l, src, tr[l])
+        w = pt.G(l, src)
+        bulk = w[g.local(g.s):g.local(g.e) + 1]
+        assert np.abs(bulk - u[g.s:g.e + 1]).max() <= 1e-12 * scale
+        if g.s > g.lo:
+            assert np.abs(w[:g.local(g.s)]).max() <= 1e-12 * scale
+        if g.e < g.hi:
+            assert np.abs(w[g.local(g.e) + 1:]).max() <= 1e-12 * scale
+
+
+def test_exact_traces_solve_polarized_system(homog25):
+    """The exact traces split into (u_down, u_up) satisfy the polarized SIE:
+    solve D_down u_down = f_down - U u_up with u_up from GMRES, and compare
+    u_down + u_up with the global solution's traces."""
+    wl, pb, f, u, pt = homog25
+    ur, iters, hist = pt.solve(f, tol=1e-12)
+    tr = pt.traces_of(u)
+    assert np.abs(pt.traces_of(ur) - tr).max() <= 1e-10 * np.abs(tr).max()
+
+
+def test_sweeps_invert_forward_blocks(homog25):
+    """Algorithms 4/5 (sweeps) invert Algorithms 8/9 (forward D blocks)."""
+    wl, pb, f, u, pt = homog25
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(pt.zero_pairs().shape) + 1j * rng.standard_normal(pt.zero_pairs().shape)
+    assert np.abs(pt.sweep_down(pt.D_down(x)) - x).max() <= 1e-12 * np.abs(x).max()
+    assert np.abs(pt.sweep_up(pt.D_up(x)) - x).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_polarized_method_matches_direct_homogeneous(homog25):
+    wl, pb, f, u, pt = homog25
+    up, iters, hist = pt.solve(f, tol=1e-10)
+    assert relative_error(up.ravel(), u.ravel())[0] <= 1e-9
+    # iteration count: paper reports 4-6 to 1e-7 (plausibility, parity unpinned)
+    assert 1 <= iters <= 12
+
+
+def test_polarized_method_matches_direct_smooth_random():
+    wl = workload("smooth-24")
+    pb = Problem(wl.m(), wl.h, wl.omega, wl.pml, wl.pml_C)
+    F = point_source_rhs(pb.shape, wl.sources, wl.h)
+    u = SparseLU(pb.operator()).solve(F)[:, 0]
+    pt = PolarizedTraces(pb, wl.n_layers, wl.pml_local)
+    up, iters, _ = pt.solve(F[:, 0].reshape(pb.shape), tol=1e-10)
+    assert relative_error(up.ravel(), u)[0] <= 1e-9
+    assert 1 <= iters <= 15
+
+
+def test_single_layer_is_global_solve():
+    """L = 1: the method reduces to one local solve of the global system."""
+    pb = _problem(12, 3, model="rand")
+    F = point_source_rhs(pb.shape, [(5, 6, 4)], pb.h)
+    u = SparseLU(pb.operator()).solve(F)[:, 0]
+    pt = PolarizedTraces(pb, 1, 4)
+    up, iters, _ = pt.solve(F[:, 0].reshape(pb.shape))
+    assert relative_error(up.ravel(), u)[0] <= 1e-12
