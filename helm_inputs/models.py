@@ -208,6 +208,9 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
                                      src_depth=7, name="smooth-24"),
     "layered-28": lambda: _wl_layered(n=28, pml=5, L=4, alpha=3, n_side=2,
                                        depth=6, ppw=8.0, name="layered-28"),
+    # the headline recipe shrunk until the oracle's direct solve takes seconds
+    "layered-32": lambda: _wl_layered(n=32, pml=5, L=4, alpha=3, n_side=8,
+                                       depth=6, ppw=8.0, name="layered-32"),
 }
 
 

@@ -1,0 +1,212 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) solver for the 3D constant-density
+ * Helmholtz equation by the method of polarized traces.
+ *
+ * Problem (Eq. "Helmholtz" and Eq. "discrete_Helmholtz" of the paper):
+ *     Laplacian(u) + omega^2 m(x) u = f_s,  s = 1..R,  m = 1/c^2,
+ * discretised with second-order 7-point finite differences on a regular grid
+ * (Section "Formulation"), with absorbing layers made by complex coordinate
+ * stretching beta = 1/(1 + i sigma/omega), sigma = (C/delta)(d/delta)^2
+ * (Eq. "appendix:eq:def_alpha").  The grid is decomposed into L layers in z;
+ * every internal side of a layer is padded with `pml_local` extra absorbing
+ * planes (Fig. "DDM_sketch_PML").
+ *
+ * Offline stage (Algorithm 1, "Factorization(m, omega)"): helm_factorize
+ * builds and factors every local layer operator H^l and keeps the factors
+ * resident in device memory.  Online stage (Algorithm 2, "Helmholtz
+ * solver(f)"): helm_solve* returns u = H^{-1} f for a batch of right-hand
+ * sides by GMRES on the preconditioned polarized interface system (Eqs.
+ * "polarized_SIE", "preconditioner_GS", "precond_polarized_SIE") followed by
+ * the local reconstruction.
+ *
+ * Conventions shared by every entry point:
+ *   - grid nodes (i, j, k), 0 <= i < nx, ..., at (i h, j h, k h); the grid
+ *     INCLUDES the global absorbing layer of `pml_width` nodes per face;
+ *   - volume arrays are plane-major: index i + nx*(j + ny*k) ("x fastest");
+ *   - batches of volumes are RHS-major: column r starts at r*nx*ny*nz;
+ *   - complex numbers are interleaved (re, im) pairs of double;
+ *   - the operator is assembled in the complex-symmetric form (H = H^T);
+ *     a unit point source is f = 1/h^3 at one node.
+ * All entry points return a status code (HELM_OK on success) and never throw.
+ * helm_last_error() gives a human-readable description of the last failure
+ * on the calling thread.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define HELM_OK          0
+#define HELM_EINVAL      1  /* null pointer, bad size, non-finite input      */
+#define HELM_ENOMEM      2  /* plan exceeds the memory budget / alloc failed */
+#define HELM_EZEROPIVOT  3  /* exact zero or non-finite pivot in a front      */
+#define HELM_ENOCONV     4  /* GMRES / refinement hit its iteration limit     */
+#define HELM_EHIP        5  /* HIP runtime error                              */
+
+/* ---- option flags ------------------------------------------------------ */
+#define HELM_FLAG_PROFILE 1  /* time every substitution / sweep kernel launch with
+                                HIP events on the handle's stream            */
+
+/* ---- precision of the local factors ----------------------------------- */
+#define HELM_FP64   0   /* complex128 fronts and substitutions              */
+#define HELM_MIXED  1   /* complex64 fronts on MFMA + FP64 refinement       */
+
+typedef struct helm_handle helm_handle;   /* opaque */
+
+typedef struct {
+  int nx, ny, nz;   /* nodes per axis, absorbing layer included */
+  double h;         /* grid spacing */
+} helm_grid;
+
+typedef struct {
+  int    pml_local;        /* absorbing planes added at internal sides (>=1) */
+  double pml_C;            /* PML strength C; <= 0 selects 20 * max(c)       */
+  int    precision;        /* HELM_FP64 or HELM_MIXED                        */
+  double gmres_tol;        /* stop on |P(f - M x)| <= tol |P f|              */
+  int    gmres_max_iter;   /* max GMRES iterations (no restart below this)   */
+  double ir_tol;           /* mixed: stop refinement at |f-Hu| <= ir_tol |f| */
+  int    ir_max_steps;     /* mixed: max refinement steps                    */
+  double inner_tol;        /* mixed: GMRES tolerance of each refinement step */
+  size_t hbm_budget_bytes; /* 0 = 90% of free device memory                  */
+  int    device;           /* HIP device ordinal                             */
+  void*  stream;           /* hipStream_t for the *_dev entry points (NULL = default) */
+  int    max_rhs;          /* widest RHS batch one internal launch carries   */
+  int    leaf_size;        /* nested-dissection leaf size (DOFs), 0 = default */
+  int    flags;            /* HELM_FLAG_* bits, 0 by default */
+} helm_options;
+
+typedef struct {
+  int    n_rhs;
+  int    gmres_iters;        /* total GMRES iterations (max over columns)   */
+  int    ir_steps;           /* refinement steps taken (1 for FP64)          */
+  double rel_residual_max;   /* max over columns of |f - H u| / |f| (FP64)   */
+  double t_setup_ms;         /* local solves of the partitioned source       */
+  double t_gmres_ms;         /* GMRES on the interface system                */
+  double t_reconstruct_ms;   /* final local solves                           */
+  double t_residual_ms;      /* FP64 residual / refinement updates           */
+  double t_total_ms;
+  long long layer_solves;    /* number of single-layer multi-RHS solves      */
+  double factor_bytes_read;  /* factor bytes streamed by the substitutions   */
+} helm_solve_info;
+
+/* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,
+ * gmres_tol 1e-10, gmres_max_iter 40, ir_tol 1e-9, ir_max_steps 6,
+ * inner_tol 1e-5, hbm_budget 0 (auto), device 0, stream NULL, max_rhs 64,
+ * leaf_size 64, flags 0. */
+void helm_default_options(helm_options* opt);
+
+/* Planner (no device memory is touched).  Exact sizes from the symbolic
+ * nested-dissection analysis of all layers:
+ *   factor_bytes  -- resident factors for the chosen precision;
+ *   bytes_per_rhs -- device memory one more RHS column costs in helm_solve;
+ *   max_front     -- largest frontal matrix dimension s + b.
+ * Any output pointer may be NULL.  Returns HELM_EINVAL for impossible
+ * geometries (layers thinner than one plane, pml_width too large). */
+int helm_plan(const helm_grid* g, int pml_width, int n_layers,
+              const helm_options* opt, size_t* factor_bytes,
+              size_t* bytes_per_rhs, size_t* max_front);
+
+/* Offline stage (Algorithm 1).  `m` is the squared slowness 1/c^2 on the
+ * full grid (host pointer, nx*ny*nz doubles, copied).  `omega` > 0 is the
+ * angular frequency, `pml_width` the global absorbing nodes per face,
+ * `n_layers` >= 1 the number of layers L.  On success *out owns the device
+ * factors until helm_free.  opt == NULL selects the defaults. */
+int helm_factorize(const helm_grid* g, const double* m, double omega,
+                   int pml_width, int n_layers, const helm_options* opt,
+                   helm_handle** out);
+
+/* Same with `m_dev` a device pointer (read during the call only). */
+int helm_factorize_dev(const helm_grid* g, const double* m_dev, double omega,
+                       int pml_width, int n_layers, const helm_options* opt,
+                       helm_handle** out);
+
+/* Online stage (Algorithm 2) for host arrays: f and u hold n_rhs volumes
+ * of complex doubles (2*nx*ny*nz*n_rhs doubles, RHS-major).  u is written,
+ * f is not modified.  info may be NULL.  Returns HELM_ENOCONV (u then holds
+ * the last iterate and info is filled) when a tolerance was not met. */
+int helm_solve(helm_handle* h, int n_rhs, const double* f, double* u,
+               helm_solve_info* info);
+
+/* Same with device pointers; work is enqueued on opt->stream of the handle
+ * and the call returns after the stream has completed. */
+int helm_solve_dev(helm_handle* h, int n_rhs, const double* f_dev,
+                   double* u_dev, helm_solve_info* info);
+
+/* Point sources: column r is amplitude[r] / h^3 at node node_index[r]
+ * (index i + nx*(j + ny*k)); arrays are host pointers of length n_rhs
+ * (amplitude: 2*n_rhs doubles, complex).  u_dev is a device array of
+ * n_rhs volumes. */
+int helm_solve_points(helm_handle* h, int n_rhs, const int64_t* node_index,
+                      const double* amplitude, double* u_dev,
+                      helm_solve_info* info);
+
+/* Per-kernel-class launch statistics gathered while HELM_FLAG_PROFILE is set:
+ * launch count, summed event-timed duration, and the algorithmic flops and
+ * HBM bytes of those launches (complex work counted as 8 real flops per
+ * multiply-add; bytes = factor blocks read once plus the right-hand-side
+ * rows read and written).  Writes up to `max` records, the number of
+ * classes to *count; `reset` != 0 clears the counters afterwards. */
+typedef struct {
+  char      name[32];
+  long long launches;
+  double    total_ms;
+  double    flops;
+  double    bytes;
+} helm_kernel_stat;
+
+int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count,
+                      int reset);
+
+/* Release the factors and all device memory owned by the handle. */
+int helm_free(helm_handle* h);
+
+/* Static description of a status code; thread-local detail of the last
+ * failure. */
+const char* helm_strerror(int status);
+const char* helm_last_error(void);
+
+/* ---- inspection entry points (used by the tests) ------------------------
+ * They expose single steps of the online stage so that each can be
+ * compared with an independent implementation. */
+
+/* Number of layers and the plane range of layer l: bulk [s, e] and the
+ * extended range [lo, hi] (global plane indices). */
+int helm_layer_info(const helm_handle* h, int l, int* s, int* e, int* lo,
+                    int* hi);
+
+/* One multi-RHS local solve w = (H^l)^{-1} r of Eq. "discrete_local_Helmholtz"
+ * (the forward and backward substitutions over the layer's front tree).
+ * r_dev, w_dev: device arrays of k local volumes, RHS-major, natural order
+ * (i + nx*(j + ny*(z - lo))), complex double.  In HELM_MIXED the substitution
+ * runs in complex64. */
+int helm_layer_solve_dev(helm_handle* h, int l, int k, const double* r_dev,
+                         double* w_dev);
+
+/* FP64 residual r = f - H u of the global 7-point operator (device arrays of
+ * k volumes, RHS-major).  With f_dev == NULL it returns H u. */
+int helm_apply_operator_dev(helm_handle* h, int k, const double* f_dev,
+                            const double* u_dev, double* r_dev);
+
+/* Polarized interface operators on pair vectors.  A pair vector holds, for
+ * interfaces j = 0..L-2, the two planes (u(e_j), u(e_j + 1)); layout
+ * [j][plane 0/1][y][x][column], complex double, device memory.
+ *   op 0: the preconditioner P applied to (x_down, x_up)  (Algs. 4-6),
+ *   op 1: P M x = x + P (U x_up, 0)                        (Alg. 7 + P),
+ *   op 2: U x_up                                            (Alg. 10),
+ *   op 3: the polarized right-hand side (f_down, f_up) of a volume source
+ *         (Alg. 2 lines 2-8); `in_dev` is then k volumes (RHS-major).
+ * For ops 0-1 `in_dev`/`out_dev` hold [x_down | x_up], each a pair vector. */
+int helm_polarized_op_dev(helm_handle* h, int op, int k, const double* in_dev,
+                          double* out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

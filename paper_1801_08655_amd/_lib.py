@@ -1,0 +1,145 @@
+"""ctypes binding of ``libhelm.so`` (argument marshalling only).
+
+Every step of the solver runs in the HIP library; this module converts
+arguments (NumPy arrays, torch device tensors) into the plain pointers and
+sizes of the C ABI declared in ``include/helm.h``.  Loading fails loudly if
+the library has not been built: there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhelm.so")
+
+HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EZEROPIVOT, HELM_ENOCONV, HELM_EHIP = range(6)
+HELM_FP64, HELM_MIXED = 0, 1
+
+EXPORTED = [
+    "helm_default_options", "helm_plan", "helm_factorize", "helm_factorize_dev",
+    "helm_solve", "helm_solve_dev", "helm_solve_points", "helm_free",
+    "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
+    "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
+]
+HELM_FLAG_PROFILE = 1
+
+
+class helm_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("h", ctypes.c_double)]
+
+
+class helm_options(ctypes.Structure):
+    _fields_ = [
+        ("pml_local", ctypes.c_int),
+        ("pml_C", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("gmres_tol", ctypes.c_double),
+        ("gmres_max_iter", ctypes.c_int),
+        ("ir_tol", ctypes.c_double),
+        ("ir_max_steps", ctypes.c_int),
+        ("inner_tol", ctypes.c_double),
+        ("hbm_budget_bytes", ctypes.c_size_t),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("max_rhs", ctypes.c_int),
+        ("leaf_size", ctypes.c_int),
+        ("flags", ctypes.c_int),
+    ]
+
+
+class helm_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("n_rhs", ctypes.c_int),
+        ("gmres_iters", ctypes.c_int),
+        ("ir_steps", ctypes.c_int),
+        ("rel_residual_max", ctypes.c_double),
+        ("t_setup_ms", ctypes.c_double),
+        ("t_gmres_ms", ctypes.c_double),
+        ("t_reconstruct_ms", ctypes.c_double),
+        ("t_residual_ms", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double),
+        ("layer_solves", ctypes.c_longlong),
+        ("factor_bytes_read", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class helm_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_longlong),
+                ("total_ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` or "
+            "`python paper_1801_08655_amd/build.py`")
+    # PyTorch ships its own HIP runtime with the same SONAME as the system one;
+    # loading torch first makes the library bind to that runtime, so that one
+    # process never holds two HIP runtimes (device memory and streams are
+    # shared with torch).
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    H = ctypes.c_void_p
+    L.helm_default_options.argtypes = [ctypes.POINTER(helm_options)]
+    L.helm_default_options.restype = None
+    L.helm_plan.argtypes = [ctypes.POINTER(helm_grid), I, I, ctypes.POINTER(helm_options),
+                            ctypes.POINTER(S), ctypes.POINTER(S), ctypes.POINTER(S)]
+    L.helm_plan.restype = I
+    for fn in (L.helm_factorize, L.helm_factorize_dev):
+        fn.argtypes = [ctypes.POINTER(helm_grid), P, D, I, I,
+                       ctypes.POINTER(helm_options), ctypes.POINTER(H)]
+        fn.restype = I
+    for fn in (L.helm_solve, L.helm_solve_dev):
+        fn.argtypes = [H, I, P, P, ctypes.POINTER(helm_solve_info)]
+        fn.restype = I
+    L.helm_solve_points.argtypes = [H, I, P, P, P, ctypes.POINTER(helm_solve_info)]
+    L.helm_solve_points.restype = I
+    L.helm_free.argtypes = [H]
+    L.helm_free.restype = I
+    L.helm_strerror.argtypes = [I]
+    L.helm_strerror.restype = ctypes.c_char_p
+    L.helm_last_error.argtypes = []
+    L.helm_last_error.restype = ctypes.c_char_p
+    L.helm_layer_info.argtypes = [H, I] + [ctypes.POINTER(I)] * 4
+    L.helm_layer_info.restype = I
+    L.helm_layer_solve_dev.argtypes = [H, I, I, P, P]
+    L.helm_layer_solve_dev.restype = I
+    L.helm_apply_operator_dev.argtypes = [H, I, P, P, P]
+    L.helm_apply_operator_dev.restype = I
+    L.helm_polarized_op_dev.argtypes = [H, I, I, P, P]
+    L.helm_polarized_op_dev.restype = I
+    L.helm_kernel_stats.argtypes = [H, ctypes.POINTER(helm_kernel_stat), I,
+                                    ctypes.POINTER(I), I]
+    L.helm_kernel_stats.restype = I
+    _lib = L
+    return L
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        msg = L.helm_strerror(status).decode()
+        detail = L.helm_last_error().decode()
+        super().__init__(f"{where}: {msg} ({detail})")
+        self.status = status
+
+
+def check(status, where):
+    if status not in (HELM_OK,):
+        raise HelmError(status, where)

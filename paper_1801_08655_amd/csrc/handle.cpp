@@ -1,0 +1,545 @@
+// Offline stage (Algorithm 1): device geometry, memory plan, factorization
+// driver, and the level-by-level multi-RHS local solve used by the online
+// stage.
+#include "handle.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+namespace helm {
+
+DevMem::~DevMem() { release(); }
+void DevMem::alloc(size_t b) {
+  release();
+  if (b == 0) return;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error{HELM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+  }
+  bytes = b;
+}
+void DevMem::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+namespace {
+
+template <typename V>
+void upload(DevMem& d, const std::vector<V>& h, hipStream_t st) {
+  d.alloc(h.size() * sizeof(V));
+  if (!h.empty())
+    HELM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, st));
+}
+
+std::vector<double2> to_d2(const std::vector<cd>& v) {
+  std::vector<double2> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2(v[i].real(), v[i].imag());
+  return o;
+}
+
+int tiles64(long long n) { return (int)((n + 63) / 64); }
+
+}  // namespace
+
+Handle::~Handle() {
+  if (st) (void)hipStreamSynchronize(st);
+  for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : ev_free) (void)hipEventDestroy(e);
+  sets.clear();
+  if (own_stream && st) (void)hipStreamDestroy(st);
+}
+
+void Handle::init_device(const helm_options& o) {
+  opt = o;
+  device = o.device;
+  HELM_HIP(hipSetDevice(device));
+  if (o.stream) {
+    st = reinterpret_cast<hipStream_t>(o.stream);
+    own_stream = false;
+  } else {
+    HELM_HIP(hipStreamCreate(&st));
+    own_stream = true;
+  }
+  prec = o.precision == HELM_FP64 ? HELM_FP64 : HELM_MIXED;
+  elem = prec == HELM_FP64 ? 16 : 8;
+  profile = (o.flags & HELM_FLAG_PROFILE) != 0;
+}
+
+hipEvent_t Handle::prof_begin() {
+  if (!profile) return nullptr;
+  hipEvent_t e;
+  if (!ev_free.empty()) {
+    e = ev_free.back();
+    ev_free.pop_back();
+  } else {
+    HELM_HIP(hipEventCreate(&e));
+  }
+  HELM_HIP(hipEventRecord(e, st));
+  return e;
+}
+
+void Handle::prof_end(int cls, hipEvent_t a, double flops, double bytes) {
+  if (!a) return;
+  hipEvent_t b = prof_begin();
+  pending.push_back(PendingEvent{cls, a, b, flops, bytes});
+}
+
+void Handle::collect_profile() {
+  if (pending.empty()) return;
+  HELM_HIP(hipStreamSynchronize(st));
+  for (auto& p : pending) {
+    float ms = 0;
+    HELM_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    KStat& k = kstats[p.cls];
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += p.flops;
+    k.bytes += p.bytes;
+    ev_free.push_back(p.a);
+    ev_free.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void Handle::upload_geometry(const double* m_src, bool m_on_device) {
+  const long long N = (long long)G.nx * G.ny * G.nz;
+  m.alloc(N * sizeof(double));
+  HELM_HIP(hipMemcpyAsync(m.p, m_src, N * sizeof(double),
+                          m_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  upload(bx, to_d2(G.bx), st);
+  upload(bxh, to_d2(G.bxh), st);
+  upload(by, to_d2(G.by), st);
+  upload(byh, to_d2(G.byh), st);
+  upload(bz, to_d2(G.bz), st);
+  upload(bzh, to_d2(G.bzh), st);
+  // B(j, i) = 1 / (h^2 beta_x(i) beta_y(j)): matrix coupling across an
+  // interior interface, the scale of the interface sources
+  std::vector<double2> B((size_t)G.nx * G.ny);
+  for (int j = 0; j < G.ny; ++j)
+    for (int i = 0; i < G.nx; ++i) {
+      cd v = 1.0 / (G.h * G.h * G.bx[i] * G.by[j]);
+      B[(size_t)i + (size_t)G.nx * j] = make_double2(v.real(), v.imag());
+    }
+  upload(Bcoef, B, st);
+  const int L = G.L;
+  lbz.clear(); lbzh.clear(); nat2nd.clear(); nd2nat.clear(); bidx.clear(); inv.clear();
+  for (int l = 0; l < L; ++l) {
+    const LayerPlan& P = G.layers[l];
+    lbz.emplace_back(new DevMem); upload(*lbz.back(), to_d2(G.lbz[l]), st);
+    lbzh.emplace_back(new DevMem); upload(*lbzh.back(), to_d2(G.lbzh[l]), st);
+    nat2nd.emplace_back(new DevMem); upload(*nat2nd.back(), P.nat2nd, st);
+    nd2nat.emplace_back(new DevMem); upload(*nd2nat.back(), P.nd2nat, st);
+    bidx.emplace_back(new DevMem); upload(*bidx.back(), P.bidx, st);
+    inv.emplace_back(new DevMem); upload(*inv.back(), P.inv, st);
+  }
+  grid.nx = G.nx; grid.ny = G.ny; grid.nz = G.nz;
+  grid.h = G.h; grid.omega = G.omega;
+  grid.m = m.as<double>();
+  grid.bx = bx.as<double2>(); grid.bxh = bxh.as<double2>();
+  grid.by = by.as<double2>(); grid.byh = byh.as<double2>();
+  grid.bz = bz.as<double2>(); grid.bzh = bzh.as<double2>();
+}
+
+void Handle::build_fronts() {
+  const int L = G.L;
+  front_base.assign(L + 1, 0);
+  for (int l = 0; l < L; ++l)
+    front_base[l + 1] = front_base[l] + (int)G.layers[l].fronts.size();
+  n_fronts = front_base[L];
+  fronts_h.assign(n_fronts, FrontDev{});
+  for (int l = 0; l < L; ++l) {
+    const LayerPlan& P = G.layers[l];
+    for (size_t q = 0; q < P.fronts.size(); ++q) {
+      const FrontHost& F = P.fronts[q];
+      FrontDev& d = fronts_h[front_base[l] + q];
+      d.s = F.s;
+      d.b = F.b;
+      d.off = F.off;
+      d.layer = l;
+      d.fac = P.fac_off[q];
+      d.ws = 0;
+      d.ws_parity = F.depth & 1;
+      d.bidx = P.bidx_off[q];
+      for (int c = 0; c < 2; ++c) {
+        d.inv[c] = P.inv_off[2 * q + c];
+        d.child[c] = F.child[c] >= 0 ? front_base[l] + F.child[c] : -1;
+      }
+      d.wt = P.wt_off[q];
+      d.ub = P.ub_off[q];
+      d.ub_parity = F.depth & 1;
+    }
+  }
+  layers_h.assign(L, LayerDev{});
+  for (int l = 0; l < L; ++l) {
+    const LayerPlan& P = G.layers[l];
+    LayerDev& d = layers_h[l];
+    d.bidx = bidx[l]->as<int>();
+    d.inv = inv[l]->as<int>();
+    d.nat2nd = nat2nd[l]->as<int>();
+    d.nd2nat = nd2nat[l]->as<int>();
+    d.bz = lbz[l]->as<double2>();
+    d.bzh = lbzh[l]->as<double2>();
+    d.n_loc = P.n_loc;
+    d.t = P.t;
+    d.lo = P.lo;
+    d.s = P.s;
+    d.e = P.e;
+  }
+}
+
+void Handle::upload_layers() {
+  if (!layers_d.p || layers_d.bytes < layers_h.size() * sizeof(LayerDev))
+    layers_d.alloc(layers_h.size() * sizeof(LayerDev));
+  HELM_HIP(hipMemcpyAsync(layers_d.p, layers_h.data(), layers_h.size() * sizeof(LayerDev),
+                          hipMemcpyHostToDevice, st));
+  HELM_HIP(hipStreamSynchronize(st));
+}
+
+size_t plan_factor_elems(const Geometry& G) {
+  size_t s = 0;
+  for (const auto& P : G.layers) s += (size_t)P.fac_elems;
+  return s;
+}
+
+size_t plan_bytes_per_rhs(const Geometry& G, size_t elem) {
+  // local solve vectors of every layer (X, Wt, Ub even/odd)
+  size_t per = 0;
+  for (const auto& P : G.layers)
+    per += ((size_t)P.n_loc + P.wt_rows + P.ub_rows[0] + P.ub_rows[1]) * elem;
+  // FP64 interface vectors: Krylov basis (up to 16 + 2 vectors) and sweep
+  // temporaries (about 8), each 2 pair vectors of (L-1) x 2 planes
+  size_t pv = (size_t)std::max(G.L - 1, 0) * 2 * G.nx * G.ny * 16;
+  per += pv * 2 * (18 + 8);
+  // FP64 volumes: f, u, r, correction
+  per += (size_t)G.nx * G.ny * G.nz * 16 * 4;
+  return per;
+}
+
+// ---------------------------------------------------------------------------
+// factorization
+// ---------------------------------------------------------------------------
+void Handle::factorize() {
+  auto t0 = std::chrono::steady_clock::now();
+  if (prec == HELM_FP64) factorize_t<double>(); else factorize_t<float>();
+  factor_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+template <typename T>
+void Handle::factorize_t() {
+  const int L = G.L;
+  // factor store, one buffer per layer
+  fac.clear();
+  bytes_factors = 0;
+  factor_flops = 0;
+  for (int l = 0; l < L; ++l) {
+    fac.emplace_back(new DevMem);
+    fac.back()->alloc((size_t)G.layers[l].fac_elems * elem);
+    layers_h[l].fac = fac.back()->p;
+    bytes_factors += (size_t)G.layers[l].fac_elems * elem;
+    factor_flops += G.layers[l].factor_flops;
+  }
+  // memory left for frontal workspaces: choose groups of consecutive layers
+  size_t free_b = 0, total_b = 0;
+  HELM_HIP(hipMemGetInfo(&free_b, &total_b));
+  size_t budget = opt.hbm_budget_bytes ? opt.hbm_budget_bytes : (size_t)(0.9 * total_b);
+  size_t used_now = total_b - free_b;
+  size_t avail = budget > used_now ? budget - used_now : 0;
+  // leave room for the solve workspace of the default batch
+  size_t reserve = plan_bytes_per_rhs(G, elem) * (size_t)std::max(1, opt.max_rhs);
+  size_t ws_budget = avail > reserve ? (avail - reserve) : avail / 2;
+  auto layer_ws = [&](int l) {
+    const LayerPlan& P = G.layers[l];
+    std::vector<long long> sum(P.max_depth + 1, 0), pan(P.max_depth + 1, 0);
+    for (const auto& F : P.fronts) {
+      sum[F.depth] += (long long)(F.s + F.b) * (F.s + F.b);
+      pan[F.depth] += (long long)F.s * nb;
+    }
+    return std::make_pair(sum, pan);
+  };
+  std::vector<std::vector<int>> groups;
+  {
+    std::vector<int> cur;
+    std::vector<long long> acc;
+    std::vector<long long> accp;
+    auto cost = [&](const std::vector<long long>& a, const std::vector<long long>& p) {
+      long long m0 = 0, m1 = 0, mp = 0;
+      for (size_t d = 0; d < a.size(); ++d) {
+        if (d & 1) m1 = std::max(m1, a[d]); else m0 = std::max(m0, a[d]);
+        mp = std::max(mp, p[d]);
+      }
+      return (size_t)(m0 + m1 + 2 * mp) * elem;
+    };
+    for (int l = 0; l < L; ++l) {
+      auto w = layer_ws(l);
+      std::vector<long long> na = acc, np = accp;
+      if (na.size() < w.first.size()) { na.resize(w.first.size(), 0); np.resize(w.first.size(), 0); }
+      for (size_t d = 0; d < w.first.size(); ++d) { na[d] += w.first[d]; np[d] += w.second[d]; }
+      if (!cur.empty() && cost(na, np) > ws_budget) {
+        groups.push_back(cur);
+        cur.clear();
+        acc.assign(w.first.begin(), w.first.end());
+        accp.assign(w.second.begin(), w.second.end());
+        HELM_REQUIRE(cost(acc, accp) <= ws_budget, HELM_ENOMEM,
+                     "frontal workspace of one layer exceeds the memory budget");
+      } else {
+        acc = na;
+        accp = np;
+      }
+      cur.push_back(l);
+    }
+    if (!cur.empty()) groups.push_back(cur);
+  }
+
+  DevMem status;
+  status.alloc(sizeof(int));
+  HELM_HIP(hipMemsetAsync(status.p, 0, sizeof(int), st));
+
+  for (const auto& grp : groups) {
+    int maxd = 0;
+    for (int l : grp) maxd = std::max(maxd, G.layers[l].max_depth);
+    // per-depth lists, workspace offsets
+    std::vector<std::vector<int>> dl(maxd + 1);
+    for (int l : grp)
+      for (int d = 0; d <= G.layers[l].max_depth; ++d)
+        for (int q : G.layers[l].by_depth[d]) dl[d].push_back(front_base[l] + q);
+    long long wsz[2] = {0, 0}, pmax = 0, smax_sum = 0;
+    for (int d = 0; d <= maxd; ++d) {
+      auto& v = dl[d];
+      std::stable_sort(v.begin(), v.end(),
+                       [&](int a, int b) { return fronts_h[a].s > fronts_h[b].s; });
+      long long off = 0, pan = 0, ss = 0;
+      for (int f : v) {
+        fronts_h[f].ws = off;
+        long long n = fronts_h[f].s + fronts_h[f].b;
+        off += n * n;
+        pan += (long long)fronts_h[f].s * nb;
+        ss += fronts_h[f].s;
+      }
+      wsz[d & 1] = std::max(wsz[d & 1], off);
+      pmax = std::max(pmax, pan);
+      smax_sum = std::max(smax_sum, ss);
+    }
+    upload(fronts, fronts_h, st);
+    upload_layers();
+    DevMem ws0, ws1, panel, Dbuf, ipiv, perm;
+    ws0.alloc(std::max<long long>(wsz[0], 1) * elem);
+    ws1.alloc(std::max<long long>(wsz[1], 1) * elem);
+    panel.alloc(std::max<long long>(pmax, 1) * elem);
+    Dbuf.alloc(std::max<long long>(pmax, 1) * elem);
+    ipiv.alloc(std::max<long long>(smax_sum, 1) * sizeof(int));
+    perm.alloc(std::max<long long>(smax_sum, 1) * sizeof(int));
+
+    for (int d = maxd; d >= 0; --d) {
+      const auto& v = dl[d];
+      if (v.empty()) continue;
+      FactorDepth fd;
+      fd.n = (int)v.size();
+      std::vector<int> pRow(fd.n + 1, 0), pStore(fd.n + 1, 0);
+      std::vector<long long> poff(fd.n + 1, 0), roff(fd.n + 1, 0);
+      fd.pFull_h.assign(fd.n + 1, 0);
+      fd.pCol_h.assign(fd.n + 1, 0);
+      for (int a = 0; a < fd.n; ++a) {
+        const FrontDev& F = fronts_h[v[a]];
+        int n = F.s + F.b;
+        fd.s_sorted.push_back(F.s);
+        fd.pFull_h[a + 1] = fd.pFull_h[a] + tiles64(n) * tiles64(n);
+        fd.pCol_h[a + 1] = fd.pCol_h[a] + tiles64(n);
+        pRow[a + 1] = pRow[a] + (F.s + 255) / 256;
+        pStore[a + 1] = pStore[a] + tiles64(n) * tiles64(F.s);
+        poff[a + 1] = poff[a] + (long long)F.s * nb;
+        roff[a + 1] = roff[a] + F.s;
+      }
+      upload(fd.ids, v, st);
+      upload(fd.pFull, fd.pFull_h, st);
+      upload(fd.pCol, fd.pCol_h, st);
+      upload(fd.pRow, pRow, st);
+      upload(fd.pStore, pStore, st);
+      upload(fd.panel_off, poff, st);
+      upload(fd.perm_off, roff, st);
+      const FrontDev* fr = fronts.as<FrontDev>();
+      const LayerDev* ld = layers_d.as<LayerDev>();
+      const int* ids = fd.ids.as<int>();
+      double front_elems = 0;
+      for (int a = 0; a < fd.n; ++a) {
+        double n = fronts_h[v[a]].s + fronts_h[v[a]].b;
+        front_elems += n * n;
+      }
+      hipEvent_t e0 = prof_begin();
+      kern::launch_extend_add<T>(fr, ids, fd.n, fd.pFull.as<int>(), fd.pFull_h[fd.n], ld,
+                                 ws0.p, ws1.p, st);
+      prof_end(K_EXTEND_ADD, e0, 0, 2 * front_elems * elem);
+      e0 = prof_begin();
+      kern::launch_orig_entries<T>(fr, ids, fd.n, fd.pRow.as<int>(), pRow[fd.n], ld,
+                                   ws0.p, ws1.p, grid, st);
+      prof_end(K_ORIG, e0, 0, 0);
+      const int smax = fd.s_sorted[0];
+      for (int k = 0; k < smax; k += nb) {
+        int n_act = 0;
+        while (n_act < fd.n && fd.s_sorted[n_act] > k) ++n_act;
+        double sw_flops = 0, sw_bytes = 0;
+        if (profile)
+          for (int a = 0; a < n_act; ++a) {
+            double n = fronts_h[v[a]].s + fronts_h[v[a]].b;
+            double nbf = std::min(nb, fronts_h[v[a]].s - k);
+            sw_flops += 8.0 * n * n * nbf;
+            sw_bytes += (2.0 * n * n + 2.0 * n * nbf) * elem;
+          }
+        hipEvent_t e1 = prof_begin();
+        kern::launch_panel<T>(fr, ids, n_act, k, nb, ws0.p, ws1.p, panel.p,
+                              fd.panel_off.as<long long>(), Dbuf.p, ipiv.as<int>(),
+                              perm.as<int>(), fd.perm_off.as<long long>(),
+                              status.as<int>(), st);
+        prof_end(K_PANEL, e1, 0, 0);
+        e1 = prof_begin();
+        kern::launch_swap_JO<T>(fr, ids, n_act, fd.pCol.as<int>(), fd.pCol_h[n_act], k,
+                                nb, ws0.p, ws1.p, Dbuf.p, ipiv.as<int>(),
+                                fd.panel_off.as<long long>(), fd.perm_off.as<long long>(),
+                                st);
+        prof_end(K_SWAP_JO, e1, 0, 0);
+        e1 = prof_begin();
+        kern::launch_sweep_gemm<T>(fr, ids, n_act, fd.pFull.as<int>(), fd.pFull_h[n_act],
+                                   k, nb, ws0.p, ws1.p, st);
+        prof_end(K_SWEEP_GEMM, e1, sw_flops, sw_bytes);
+        e1 = prof_begin();
+        kern::launch_update_OJ<T>(fr, ids, n_act, fd.pCol.as<int>(), fd.pCol_h[n_act], k,
+                                  nb, ws0.p, ws1.p, Dbuf.p, fd.panel_off.as<long long>(),
+                                  st);
+        prof_end(K_UPDATE_OJ, e1, 0, 0);
+      }
+      hipEvent_t e2 = prof_begin();
+      kern::launch_store_factor<T>(fr, ids, fd.n, fd.pStore.as<int>(), pStore[fd.n], ld,
+                                   ws0.p, ws1.p, perm.as<int>(),
+                                   fd.perm_off.as<long long>(), st);
+      prof_end(K_STORE, e2, 0, 0);
+      HELM_HIP(hipGetLastError());
+      collect_profile();
+      // the lists of this depth must outlive the kernels that read them
+      HELM_HIP(hipStreamSynchronize(st));
+    }
+  }
+  int st_h = 0;
+  HELM_HIP(hipMemcpyAsync(&st_h, status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HELM_HIP(hipStreamSynchronize(st));
+  HELM_REQUIRE(st_h == 0, HELM_EZEROPIVOT, "zero or non-finite pivot in a frontal matrix");
+  upload(fronts, fronts_h, st);
+  upload_layers();
+}
+
+template void Handle::factorize_t<float>();
+template void Handle::factorize_t<double>();
+
+// ---------------------------------------------------------------------------
+// solve workspace and launch lists
+// ---------------------------------------------------------------------------
+void Handle::ensure_workspace(int k) {
+  if (k <= kcap) return;
+  HELM_HIP(hipStreamSynchronize(st));
+  const int L = G.L;
+  X.clear(); Wt.clear(); Ub0.clear(); Ub1.clear();
+  for (int l = 0; l < L; ++l) {
+    const LayerPlan& P = G.layers[l];
+    X.emplace_back(new DevMem); X.back()->alloc((size_t)P.n_loc * k * elem);
+    Wt.emplace_back(new DevMem); Wt.back()->alloc(std::max<size_t>(P.wt_rows, 1) * k * elem);
+    Ub0.emplace_back(new DevMem); Ub0.back()->alloc(std::max<size_t>(P.ub_rows[0], 1) * k * elem);
+    Ub1.emplace_back(new DevMem); Ub1.back()->alloc(std::max<size_t>(P.ub_rows[1], 1) * k * elem);
+    layers_h[l].X = X[l]->p;
+    layers_h[l].Wt = Wt[l]->p;
+    layers_h[l].Ub[0] = Ub0[l]->p;
+    layers_h[l].Ub[1] = Ub1[l]->p;
+  }
+  kcap = k;
+  upload_layers();
+}
+
+const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
+  auto it = sets.find(layers);
+  if (it != sets.end()) return *it->second;
+  auto S = std::make_unique<LayerSet>();
+  S->layers = layers;
+  int maxd = 0;
+  for (int l : layers) maxd = std::max(maxd, G.layers[l].max_depth);
+  S->max_depth = maxd;
+  for (int d = 0; d <= maxd; ++d) {
+    auto D = std::make_unique<DepthList>();
+    std::vector<int> ids;
+    for (int l : layers)
+      if (d <= G.layers[l].max_depth)
+        for (int q : G.layers[l].by_depth[d]) ids.push_back(front_base[l] + q);
+    std::vector<int> pSB(ids.size() + 1, 0), pB(ids.size() + 1, 0), pS(ids.size() + 1, 0);
+    for (size_t a = 0; a < ids.size(); ++a) {
+      const FrontDev& F = fronts_h[ids[a]];
+      D->sum_s += F.s;
+      D->sum_b += F.b;
+      D->sum_sbs += (double)(F.s + F.b) * F.s;
+      D->sum_bs += (double)F.b * F.s;
+      pSB[a + 1] = pSB[a] + tiles64(F.s + F.b);
+      pB[a + 1] = pB[a] + tiles64(F.b);
+      pS[a + 1] = pS[a] + tiles64(F.s);
+    }
+    D->n = (int)ids.size();
+    upload(D->ids, ids, st);
+    upload(D->pSB, pSB, st);
+    upload(D->pB, pB, st);
+    upload(D->pS, pS, st);
+    D->tSB = pSB.back();
+    D->tB = pB.back();
+    D->tS = pS.back();
+    S->depth.push_back(std::move(D));
+  }
+  HELM_HIP(hipStreamSynchronize(st));
+  auto& ref = *S;
+  sets[layers] = std::move(S);
+  return ref;
+}
+
+double Handle::solve_elems(const LayerSet& set) const {
+  double e = 0;
+  for (int l : set.layers) e += G.layers[l].solve_elems;
+  return e;
+}
+
+void Handle::solve_layers(const LayerSet& set, int k) {
+  if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
+  layer_solves += (long long)set.layers.size();
+  solve_bytes += solve_elems(set) * (double)elem;
+}
+
+template <typename T>
+void Handle::solve_layers_t(const LayerSet& set, int k) {
+  const FrontDev* fr = fronts.as<FrontDev>();
+  const LayerDev* ld = layers_d.as<LayerDev>();
+  const double e = (double)elem, kk = (double)k;
+  for (int d = set.max_depth; d >= 0; --d) {
+    const DepthList& D = *set.depth[d];
+    if (D.n == 0) continue;
+    hipEvent_t a = prof_begin();
+    kern::launch_fwd_gather<T>(fr, D.ids.as<int>(), D.n, D.pSB.as<int>(), D.tSB, ld, k, st);
+    prof_end(K_FWD_GATHER, a, 0, 2.0 * (D.sum_s + D.sum_b) * kk * e);
+    a = prof_begin();
+    kern::launch_fwd_gemm<T>(fr, D.ids.as<int>(), D.n, D.pSB.as<int>(), D.tSB, ld, k, st);
+    prof_end(K_FWD_GEMM, a, 8.0 * D.sum_sbs * kk,
+             D.sum_sbs * e + (2.0 * D.sum_s + 2.0 * D.sum_b) * kk * e);
+  }
+  for (int d = 0; d <= set.max_depth; ++d) {
+    const DepthList& D = *set.depth[d];
+    if (D.n == 0) continue;
+    hipEvent_t a = prof_begin();
+    kern::launch_bwd_gather<T>(fr, D.ids.as<int>(), D.n, D.pB.as<int>(), D.tB, ld, k, st);
+    prof_end(K_BWD_GATHER, a, 0, 2.0 * D.sum_b * kk * e);
+    a = prof_begin();
+    kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.n, D.pS.as<int>(), D.tS, ld, k, st);
+    prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
+             D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
+  }
+}
+
+template void Handle::solve_layers_t<float>(const LayerSet&, int);
+template void Handle::solve_layers_t<double>(const LayerSet&, int);
+
+}  // namespace helm

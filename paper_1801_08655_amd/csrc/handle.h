@@ -1,0 +1,126 @@
+// The factorization handle: resident factors, plans and launch lists.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "helm_internal.h"
+#include "kernels.h"
+
+namespace helm {
+
+// Device allocation owned by the handle.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem();
+  void alloc(size_t b);
+  void release();
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Fronts of one depth over a set of layers, for the substitutions.
+struct DepthList {
+  int n = 0;
+  DevMem ids;                 // global front ids
+  DevMem pSB, pB, pS;         // prefix sums of 64-row tiles of s+b, b, s
+  int tSB = 0, tB = 0, tS = 0;
+  double sum_s = 0, sum_b = 0, sum_sbs = 0, sum_bs = 0;  // work counts
+};
+
+// Kernel classes timed with HIP events when HELM_FLAG_PROFILE is set.
+enum KClass {
+  K_FWD_GATHER, K_FWD_GEMM, K_BWD_GATHER, K_BWD_GEMM, K_SWEEP_GEMM, K_PANEL,
+  K_SWAP_JO, K_UPDATE_OJ, K_EXTEND_ADD, K_ORIG, K_STORE, K_NCLASS
+};
+struct KStat {
+  long long launches = 0;
+  double ms = 0, flops = 0, bytes = 0;
+};
+struct PendingEvent {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+struct LayerSet {
+  std::vector<int> layers;
+  int max_depth = 0;
+  std::vector<std::unique_ptr<DepthList>> depth;
+};
+
+// Fronts of one depth of a factorization group, sorted by s (descending),
+// so that the fronts still active at block step k are a prefix of the list.
+struct FactorDepth {
+  int n = 0;
+  std::vector<int> s_sorted;
+  std::vector<int> pFull_h, pCol_h;
+  DevMem ids, pFull, pCol, pRow, pStore, panel_off, perm_off;
+  int tRow = 0, tStore = 0;
+  long long panel_total = 0, perm_total = 0;
+};
+
+struct Handle {
+  Geometry G;
+  helm_options opt{};
+  int prec = HELM_MIXED;          // HELM_FP64: complex128 fronts, else complex64
+  size_t elem = 8;                // bytes of one complex element of the factors
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int nb = 64;                    // pivot block of the Gauss-Jordan sweep
+
+  // geometry on device
+  DevMem m, bx, bxh, by, byh, bz, bzh, Bcoef;
+  std::vector<std::unique_ptr<DevMem>> lbz, lbzh, nat2nd, nd2nat, bidx, inv, fac;
+  std::vector<int> front_base;   // global id of each layer's first front
+  int n_fronts = 0;
+  DevMem fronts;                 // FrontDev[n_fronts]
+  std::vector<FrontDev> fronts_h;
+  std::vector<LayerDev> layers_h;
+  DevMem layers_d;
+  GridDev grid{};
+
+  // solve workspace (per layer) for up to kcap columns
+  int kcap = 0;
+  std::vector<std::unique_ptr<DevMem>> X, Wt, Ub0, Ub1;
+  std::map<std::vector<int>, std::unique_ptr<LayerSet>> sets;
+
+  // kernel timing (HELM_FLAG_PROFILE)
+  bool profile = false;
+  KStat kstats[K_NCLASS];
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> ev_free;
+  hipEvent_t prof_begin();
+  void prof_end(int cls, hipEvent_t a, double flops, double bytes);
+  void collect_profile();
+
+  // statistics
+  double factor_seconds = 0;
+  double factor_flops = 0;
+  long long layer_solves = 0;
+  double solve_bytes = 0;
+  size_t bytes_factors = 0;
+
+  ~Handle();
+  void init_device(const helm_options& o);
+  void upload_geometry(const double* m_src, bool m_on_device);
+  void build_fronts();
+  void factorize();
+  template <typename T> void factorize_t();
+  void ensure_workspace(int k);
+  const LayerSet& layer_set(const std::vector<int>& layers);
+  // multi-RHS solve of the layers in `set` on their X buffers (k columns)
+  void solve_layers(const LayerSet& set, int k);
+  template <typename T> void solve_layers_t(const LayerSet& set, int k);
+  void upload_layers();
+  double solve_elems(const LayerSet& set) const;
+};
+
+size_t plan_factor_elems(const Geometry& G);
+size_t plan_bytes_per_rhs(const Geometry& G, size_t elem);
+
+}  // namespace helm

@@ -1,0 +1,102 @@
+// Host-side declarations of the kernel launchers (definitions in *.hip).
+#pragma once
+
+#include "helm_internal.h"
+
+namespace helm {
+namespace kern {
+
+// out(a|b) = sx * R(X)(a|b) + sum_i (ca_i in_i(a), cb_i in_i(b))
+struct ReadTerms {
+  const double2* in[3];
+  double ca[3], cb[3];
+};
+
+// --- factorization (kernels_factor.hip) -------------------------------------
+template <typename T>
+void launch_extend_add(const FrontDev* fronts, const int* ids, int n_ids,
+                       const int* prefix, int total, const LayerDev* layers,
+                       void* ws0, void* ws1, hipStream_t st);
+template <typename T>
+void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
+                         const int* prefix, int total, const LayerDev* layers,
+                         void* ws0, void* ws1, const GridDev& g, hipStream_t st);
+template <typename T>
+void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
+                  int nb, void* ws0, void* ws1, void* panel,
+                  const long long* panel_off, void* D, int* ipiv, int* perm,
+                  const long long* perm_off, int* status, hipStream_t st);
+template <typename T>
+void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
+                    const int* prefix, int total, int k, int nb, void* ws0,
+                    void* ws1, const void* D, const int* ipiv,
+                    const long long* panel_off, const long long* perm_off,
+                    hipStream_t st);
+template <typename T>
+void launch_sweep_gemm(const FrontDev* fronts, const int* ids, int n_active,
+                       const int* prefix, int total, int k, int nb, void* ws0,
+                       void* ws1, hipStream_t st);
+template <typename T>
+void launch_update_OJ(const FrontDev* fronts, const int* ids, int n_active,
+                      const int* prefix, int total, int k, int nb, void* ws0,
+                      void* ws1, const void* D, const long long* panel_off,
+                      hipStream_t st);
+template <typename T>
+void launch_store_factor(const FrontDev* fronts, const int* ids, int n_ids,
+                         const int* prefix, int total, const LayerDev* layers,
+                         void* ws0, void* ws1, const int* perm,
+                         const long long* perm_off, hipStream_t st);
+
+// --- substitutions (kernels_solve.hip) --------------------------------------
+template <typename T>
+void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
+                       int total, const LayerDev* layers, int k, hipStream_t st);
+template <typename T>
+void launch_fwd_gemm(const FrontDev* fr, const int* ids, int n, const int* prefix,
+                     int total_mtiles, const LayerDev* layers, int k, hipStream_t st);
+template <typename T>
+void launch_bwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
+                       int total, const LayerDev* layers, int k, hipStream_t st);
+template <typename T>
+void launch_bwd_gemm(const FrontDev* fr, const int* ids, int n, const int* prefix,
+                     int total_mtiles, const LayerDev* layers, int k, hipStream_t st);
+
+// --- volumes, traces, Krylov (kernels_volume.hip) ---------------------------
+template <typename T>
+void launch_scatter_source(const LayerDev& L, const double2* f, int nx, int ny,
+                           long long N, int k, hipStream_t st);
+template <typename T>
+void launch_gather_volume(const LayerDev& L, double2* u, int nx, int ny,
+                          long long N, int k, hipStream_t st);
+template <typename T>
+void launch_local_to_X(const LayerDev& L, const double2* r, int k, hipStream_t st);
+template <typename T>
+void launch_X_to_local(const LayerDev& L, double2* w, int k, hipStream_t st);
+template <typename T>
+void launch_jump(const LayerDev& L, const double2* in0, const double2* in1,
+                 const double2* B, int bottom, int nx, int ny, int k, hipStream_t st);
+template <typename T>
+void launch_readout(const LayerDev& L, int bottom, double sx, const ReadTerms& terms,
+                    double2* out, int nx, int ny, int k, hipStream_t st);
+
+void launch_dot(const double2* x, const double2* y, long long V, int k,
+                double2* partial, double2* out, hipStream_t st);
+void launch_axpy_cols(double2* y, const double2* x, const double2* alpha,
+                      double sign, long long V, int k, hipStream_t st);
+void launch_scale_cols(double2* y, const double2* x, const double* s, long long V,
+                       int k, hipStream_t st);
+void launch_add(double2* y, const double2* x, const double2* z, long long n,
+                hipStream_t st);
+void launch_residual(const GridDev& g, const double2* f, const double2* u,
+                     double2* r, int k, hipStream_t st);
+void launch_point_sources(double2* f, const long long* node, const double2* amp,
+                          double inv_h3, long long N, int k, hipStream_t st);
+void launch_accumulate(double2* u, const double2* d, long long n, hipStream_t st);
+void launch_volume_norm2(const double2* x, long long N, int k, double* partial,
+                         double* out, hipStream_t st);
+
+constexpr int DOT_PARTIAL_BLOCKS = 256;   // partial buffer: k * 256 double2
+constexpr int NORM_PARTIAL_BLOCKS = 128;  // partial buffer: k * 128 double
+
+}  // namespace kern
+}  // namespace helm

@@ -1,0 +1,487 @@
+// Online stage (Algorithm 2): polarized interface system, preconditioned
+// GMRES, reconstruction, and FP64 iterative refinement for complex64 factors.
+//
+// Pair vectors (interface traces) hold, for every interface j = 0..L-2
+// between layers j and j+1, the planes (u(e_j), u(e_j + 1)); polarized
+// vectors are [x_down | x_up].  With G^l = (H^l)^-1, the interface sources
+// J_top/J_bot and the read-outs R_top(w) = (w(s-1), w(s)), R_bot(w) =
+// (w(e), w(e+1)), the blocks of Eq. polarized_SIE are
+//   (D_down x)_0 = -x_0,      (D_down x)_j = R_bot^j G^j J_top^j(x_{j-1}) - x_j
+//   (D_up x)_{L-2} = -x_{L-2}, (D_up x)_j = R_top^{j+1} G^{j+1} J_bot^{j+1}(x_{j+1}) - x_j
+//   (L x)_j = R_top^{j+1} G^{j+1}[J_top^{j+1}(x_j) + J_bot^{j+1}(x_{j+1})] - (0, x_{j,b})
+//   (U x)_j = R_bot^j G^j [J_top^j(x_{j-1}) + J_bot^j(x_j)] - (x_{j,a}, 0)
+// (terms with an index outside 0..L-2 dropped), and the right-hand side is
+//   f_down_j = -R_bot^j G^j f^j,  f_up_j = -R_top^{j+1} G^{j+1} f^{j+1}.
+// P of Eq. preconditioner_GS is the block Gauss-Seidel inverse, applied by the
+// downward sweep (Algorithm 4), the reflections L (Algorithm 6) and the
+// upward sweep (Algorithm 5).  As the paper notes, D_down and L can be
+// applied together: the solve of the downward sweep at layer l also yields
+// the first term of (L x)_{l-1}, and the two solves of the upward step at
+// layer j+1 (sweep and the second L term) share one right-hand side by
+// linearity.  One application of P costs 2L - 3 sequential layer solves.
+// Since P inverts the block lower-triangular part exactly,
+//   P M x = x + P (U x_up, 0),
+// so every GMRES iteration costs one batched solve over the layers (U) plus
+// the two sweeps.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "handle.h"
+#include "method.h"
+
+namespace helm {
+
+namespace {
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+Method::Method(Handle& h, int k_) : H(h), k(k_) {
+  const int L = H.G.L;
+  plane = (long long)H.G.nx * H.G.ny;
+  pair_elems = 2 * plane * k;
+  Vp = (long long)std::max(L - 1, 0) * pair_elems;   // one pair vector
+  N = (long long)H.G.nx * H.G.ny * H.G.nz;
+  H.ensure_workspace(k);
+  auto a = [&](DevMem& d, long long n) { d.alloc((size_t)std::max<long long>(n, 1) * sizeof(double2)); };
+  a(y, Vp); a(zd, Vp); a(zu, Vp); a(keep, Vp);
+  a(dot_partial, (long long)k * kern::DOT_PARTIAL_BLOCKS);
+  a(hcol, (long long)k * 64);
+  norm_partial.alloc((size_t)k * kern::NORM_PARTIAL_BLOCKS * sizeof(double));
+  norm_out.alloc((size_t)k * sizeof(double));
+  scale.alloc((size_t)k * sizeof(double));
+  std::vector<int> all, lower;
+  for (int l = 0; l < L; ++l) all.push_back(l);
+  for (int l = 0; l + 1 < L; ++l) lower.push_back(l);
+  set_all = &H.layer_set(all);
+  set_lower = L > 1 ? &H.layer_set(lower) : nullptr;
+  for (int l = 0; l < L; ++l) single.push_back(&H.layer_set({l}));
+}
+
+double2* Method::pair(double2* v, int j) const { return v + (long long)j * pair_elems; }
+const double2* Method::pair(const double2* v, int j) const {
+  return v + (long long)j * pair_elems;
+}
+
+void Method::zero_X(int l) {
+  HELM_HIP(hipMemsetAsync(H.layers_h[l].X, 0,
+                          (size_t)H.layers_h[l].n_loc * k * H.elem, H.st));
+}
+
+template <typename T>
+void Method::jump_t(int l, const double2* a, const double2* b, int bottom) {
+  kern::launch_jump<T>(H.layers_h[l], a, b, H.Bcoef.as<double2>(), bottom, H.G.nx,
+                       H.G.ny, k, H.st);
+}
+void Method::jump(int l, const double2* a, const double2* b, int bottom) {
+  if (H.prec == HELM_FP64) jump_t<double>(l, a, b, bottom); else jump_t<float>(l, a, b, bottom);
+}
+
+void Method::readout(int l, int bottom, double sx, const kern::ReadTerms& t, double2* out) {
+  if (H.prec == HELM_FP64)
+    kern::launch_readout<double>(H.layers_h[l], bottom, sx, t, out, H.G.nx, H.G.ny, k, H.st);
+  else
+    kern::launch_readout<float>(H.layers_h[l], bottom, sx, t, out, H.G.nx, H.G.ny, k, H.st);
+}
+
+kern::ReadTerms Method::terms(const double2* a, double ca, double cb, const double2* b,
+                              double cb_a, double cb_b, const double2* c, double cc_a,
+                              double cc_b) {
+  kern::ReadTerms t{};
+  t.in[0] = a; t.ca[0] = ca; t.cb[0] = cb;
+  t.in[1] = b; t.ca[1] = cb_a; t.cb[1] = cb_b;
+  t.in[2] = c; t.ca[2] = cc_a; t.cb[2] = cc_b;
+  return t;
+}
+
+void Method::solve_single(int l) { H.solve_layers(*single[l], k); }
+
+// (zd, zu) = P (vd, vu); vu may be null (zero)
+void Method::apply_P(const double2* vd, const double2* vu, double2* od, double2* ou) {
+  const int L = H.G.L;
+  double2* kp = keep.as<double2>();
+  // z_down_0 = -v_down_0
+  readout(0, 1, 0.0, terms(pair(vd, 0), -1, -1), pair(od, 0));
+  for (int l = 1; l <= L - 2; ++l) {
+    zero_X(l);
+    jump(l, pair(od, l - 1), nullptr, 0);
+    solve_single(l);
+    readout(l, 1, 1.0, terms(pair(vd, l), -1, -1), pair(od, l));
+    readout(l, 0, 1.0, terms(), pair(kp, l - 1));
+  }
+  // last layer: only the reflection term is needed
+  zero_X(L - 1);
+  jump(L - 1, pair(od, L - 2), nullptr, 0);
+  solve_single(L - 1);
+  readout(L - 1, 0, 1.0, terms(), pair(kp, L - 2));
+  // upward: z_up_{L-2} = keep_{L-1} - (0, z_down_{L-2,b}) - v_up_{L-2}
+  readout(L - 1, 0, 0.0,
+          terms(pair(kp, L - 2), 1, 1, pair(od, L - 2), 0, -1,
+                vu ? pair(vu, L - 2) : nullptr, -1, -1),
+          pair(ou, L - 2));
+  for (int j = L - 3; j >= 0; --j) {
+    zero_X(j + 1);
+    jump(j + 1, pair(ou, j + 1), pair(od, j + 1), 1);
+    solve_single(j + 1);
+    readout(j + 1, 0, 1.0,
+            terms(pair(kp, j), 1, 1, pair(od, j), 0, -1, vu ? pair(vu, j) : nullptr, -1, -1),
+            pair(ou, j));
+  }
+}
+
+// y = U x_up
+void Method::apply_U(const double2* xu, double2* out) {
+  const int L = H.G.L;
+  for (int l = 0; l <= L - 2; ++l) {
+    zero_X(l);
+    if (l >= 1) jump(l, pair(xu, l - 1), nullptr, 0);
+    jump(l, pair(xu, l), nullptr, 1);
+  }
+  H.solve_layers(*set_lower, k);
+  for (int l = 0; l <= L - 2; ++l)
+    readout(l, 1, 1.0, terms(pair(xu, l), -1, 0), pair(out, l));
+}
+
+// out = P M x = x + P (U x_up, 0)
+void Method::apply_A(const double2* x, double2* out) {
+  const double2* xd = x;
+  const double2* xu = x + Vp;
+  apply_U(xu, y.as<double2>());
+  apply_P(y.as<double2>(), nullptr, zd.as<double2>(), zu.as<double2>());
+  kern::launch_add(out, xd, zd.as<double2>(), Vp, H.st);
+  kern::launch_add(out + Vp, xu, zu.as<double2>(), Vp, H.st);
+}
+
+void Method::scatter_sources(const double2* f) {
+  for (int l = 0; l < H.G.L; ++l) {
+    zero_X(l);
+    if (H.prec == HELM_FP64)
+      kern::launch_scatter_source<double>(H.layers_h[l], f, H.G.nx, H.G.ny, N, k, H.st);
+    else
+      kern::launch_scatter_source<float>(H.layers_h[l], f, H.G.nx, H.G.ny, N, k, H.st);
+  }
+}
+
+// (f_down, f_up) from the volume source f (Algorithm 2, lines 2-8)
+void Method::polarized_rhs(const double2* f, double2* fd, double2* fu) {
+  const int L = H.G.L;
+  scatter_sources(f);
+  H.solve_layers(*set_all, k);
+  for (int l = 0; l < L; ++l) {
+    if (l <= L - 2) readout(l, 1, -1.0, terms(), pair(fd, l));
+    if (l >= 1) readout(l, 0, -1.0, terms(), pair(fu, l - 1));
+  }
+}
+
+// u = volume from traces (Algorithm 2, lines 10-14)
+void Method::reconstruct(const double2* f, const double2* tr, double2* u) {
+  const int L = H.G.L;
+  scatter_sources(f);
+  for (int l = 0; l < L; ++l) {
+    if (l >= 1) jump(l, pair(tr, l - 1), nullptr, 0);
+    if (l <= L - 2) jump(l, pair(tr, l), nullptr, 1);
+  }
+  H.solve_layers(*set_all, k);
+  for (int l = 0; l < L; ++l) {
+    if (H.prec == HELM_FP64)
+      kern::launch_gather_volume<double>(H.layers_h[l], u, H.G.nx, H.G.ny, N, k, H.st);
+    else
+      kern::launch_gather_volume<float>(H.layers_h[l], u, H.G.nx, H.G.ny, N, k, H.st);
+  }
+}
+
+void Method::dot(const double2* a, const double2* b, long long V, double2* out) {
+  kern::launch_dot(a, b, V, k, dot_partial.as<double2>(), out, H.st);
+}
+
+// Batched GMRES (one independent Krylov space per column) on P M x = b.
+// Arnoldi (modified Gram-Schmidt), norms and basis updates in FP64 on the
+// device; the (j+2) x k Hessenberg column is copied to the host where the
+// Givens rotations and the stopping test are applied per column.
+int Method::gmres(const double2* b, double2* x, double tol, int max_iter, int restart,
+                  int* iters_out) {
+  const long long V = 2 * Vp / k;             // polarized vector length per column
+  const int m = std::max(1, std::min(restart, max_iter));
+  if (!gw.p) {
+    gw.alloc((size_t)V * k * sizeof(double2));
+    gr.alloc((size_t)V * k * sizeof(double2));
+  }
+  DevMem& w = gw;
+  DevMem& r = gr;
+  HELM_HIP(hipMemsetAsync(x, 0, (size_t)V * k * sizeof(double2), H.st));
+  std::vector<double2> hh((size_t)(m + 2) * k);
+  std::vector<double> bnorm(k), scl(k);
+  // |b| per column
+  dot(b, b, V, hcol.as<double2>());
+  HELM_HIP(hipMemcpyAsync(hh.data(), hcol.p, k * sizeof(double2), hipMemcpyDeviceToHost, H.st));
+  HELM_HIP(hipStreamSynchronize(H.st));
+  for (int c = 0; c < k; ++c) bnorm[c] = std::sqrt(std::max(hh[c].x, 0.0));
+  std::vector<char> active(k, 1);
+  int total = 0;
+  bool first = true;
+  int status = HELM_OK;
+  std::vector<double> resid(k, 1.0);
+  while (true) {
+    // r = b - A x  (first cycle: x = 0, r = b)
+    const double2* r0 = b;
+    if (!first) {
+      apply_A(x, w.as<double2>());
+      HELM_HIP(hipMemcpyAsync(r.p, b, (size_t)V * k * sizeof(double2),
+                              hipMemcpyDeviceToDevice, H.st));
+      HELM_HIP(hipMemsetAsync(hcol.p, 0, k * sizeof(double2), H.st));
+      // r -= w  (alpha = 1 per column)
+      std::vector<double2> ones(k, make_double2(1.0, 0.0));
+      HELM_HIP(hipMemcpyAsync(hcol.p, ones.data(), k * sizeof(double2),
+                              hipMemcpyHostToDevice, H.st));
+      kern::launch_axpy_cols(r.as<double2>(), w.as<double2>(), hcol.as<double2>(), -1.0, V, k,
+                             H.st);
+      r0 = r.as<double2>();
+    }
+    first = false;
+    dot(r0, r0, V, hcol.as<double2>());
+    HELM_HIP(hipMemcpyAsync(hh.data(), hcol.p, k * sizeof(double2), hipMemcpyDeviceToHost, H.st));
+    HELM_HIP(hipStreamSynchronize(H.st));
+    std::vector<double> beta(k);
+    for (int c = 0; c < k; ++c) {
+      beta[c] = std::sqrt(std::max(hh[c].x, 0.0));
+      double rel = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
+      resid[c] = rel;
+      active[c] = (bnorm[c] > 0 && rel > tol) ? 1 : 0;
+      scl[c] = active[c] ? 1.0 / beta[c] : 0.0;
+    }
+    bool any = false;
+    for (int c = 0; c < k; ++c) any |= active[c];
+    if (!any) break;
+    if (total >= max_iter) { status = HELM_ENOCONV; break; }
+    HELM_HIP(hipMemcpyAsync(scale.p, scl.data(), k * sizeof(double), hipMemcpyHostToDevice, H.st));
+    kern::launch_scale_cols(basis_vec(0), r0, scale.as<double>(), V, k, H.st);
+    // per-column Hessenberg, rotations and rhs
+    std::vector<std::vector<cd>> Hm(k, std::vector<cd>((size_t)(m + 1) * m, 0.0));
+    std::vector<std::vector<cd>> cs(k, std::vector<cd>(m)), sn(k, std::vector<cd>(m));
+    std::vector<std::vector<cd>> g(k, std::vector<cd>(m + 1, 0.0));
+    std::vector<int> kd(k, 0);
+    std::vector<char> run = active;
+    for (int c = 0; c < k; ++c) g[c][0] = beta[c];
+    int j = 0;
+    for (; j < m && total < max_iter; ++j) {
+      double2* vj = basis_vec(j);
+      apply_A(vj, w.as<double2>());
+      for (int i = 0; i <= j; ++i) {
+        dot(basis_vec(i), w.as<double2>(), V, hcol.as<double2>() + (long long)i * k);
+        kern::launch_axpy_cols(w.as<double2>(), basis_vec(i),
+                               hcol.as<double2>() + (long long)i * k, -1.0, V, k, H.st);
+      }
+      dot(w.as<double2>(), w.as<double2>(), V, hcol.as<double2>() + (long long)(j + 1) * k);
+      HELM_HIP(hipMemcpyAsync(hh.data(), hcol.p, (size_t)(j + 2) * k * sizeof(double2),
+                              hipMemcpyDeviceToHost, H.st));
+      HELM_HIP(hipStreamSynchronize(H.st));
+      ++total;
+      bool any_run = false;
+      for (int c = 0; c < k; ++c) {
+        if (!run[c]) { scl[c] = 0.0; continue; }
+        std::vector<cd>& Hc = Hm[c];
+        auto Hat = [&](int r_, int c_) -> cd& { return Hc[(size_t)r_ * m + c_]; };
+        for (int i = 0; i <= j; ++i) {
+          double2 v = hh[(size_t)i * k + c];
+          Hat(i, j) = cd(v.x, v.y);
+        }
+        double hn = std::sqrt(std::max(hh[(size_t)(j + 1) * k + c].x, 0.0));
+        Hat(j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+          cd t = cs[c][i] * Hat(i, j) + sn[c][i] * Hat(i + 1, j);
+          Hat(i + 1, j) = -std::conj(sn[c][i]) * Hat(i, j) + std::conj(cs[c][i]) * Hat(i + 1, j);
+          Hat(i, j) = t;
+        }
+        cd av = Hat(j, j), bv = Hat(j + 1, j);
+        double den = std::sqrt(std::norm(av) + std::norm(bv));
+        if (den == 0.0) { cs[c][j] = 1.0; sn[c][j] = 0.0; }
+        else { cs[c][j] = std::conj(av) / den; sn[c][j] = std::conj(bv) / den; }
+        Hat(j, j) = cs[c][j] * av + sn[c][j] * bv;
+        Hat(j + 1, j) = 0.0;
+        g[c][j + 1] = -std::conj(sn[c][j]) * g[c][j];
+        g[c][j] = cs[c][j] * g[c][j];
+        kd[c] = j + 1;
+        double rel = bnorm[c] > 0 ? std::abs(g[c][j + 1]) / bnorm[c] : 0.0;
+        resid[c] = rel;
+        // stop this column on convergence or (lucky) breakdown
+        if (rel <= tol || hn <= 1e-300 || !(std::isfinite(rel))) {
+          run[c] = 0;
+          scl[c] = 0.0;
+        } else {
+          scl[c] = 1.0 / hn;
+          any_run = true;
+        }
+      }
+      if (j + 1 <= m) {
+        HELM_HIP(hipMemcpyAsync(scale.p, scl.data(), k * sizeof(double), hipMemcpyHostToDevice,
+                                H.st));
+        kern::launch_scale_cols(basis_vec(j + 1), w.as<double2>(),
+                                scale.as<double>(), V, k, H.st);
+      }
+      if (!any_run) { ++j; break; }
+    }
+    // x += V y, y from the triangular systems of each column
+    const int jmax = *std::max_element(kd.begin(), kd.end());
+    std::vector<double2> ycoef((size_t)std::max(jmax, 1) * k, make_double2(0, 0));
+    for (int c = 0; c < k; ++c) {
+      int kc = kd[c];
+      std::vector<cd> yv(kc, 0.0);
+      for (int i = kc - 1; i >= 0; --i) {
+        cd s = g[c][i];
+        for (int q = i + 1; q < kc; ++q) s -= Hm[c][(size_t)i * m + q] * yv[q];
+        cd d = Hm[c][(size_t)i * m + i];
+        yv[i] = d != 0.0 ? s / d : 0.0;
+      }
+      for (int i = 0; i < kc; ++i)
+        ycoef[(size_t)i * k + c] = make_double2(yv[i].real(), yv[i].imag());
+    }
+    if (jmax > 0) {
+      HELM_HIP(hipMemcpyAsync(hcol.p, ycoef.data(), (size_t)jmax * k * sizeof(double2),
+                              hipMemcpyHostToDevice, H.st));
+      for (int i = 0; i < jmax; ++i)
+        kern::launch_axpy_cols(x, basis_vec(i), hcol.as<double2>() + (long long)i * k,
+                               1.0, V, k, H.st);
+      HELM_HIP(hipStreamSynchronize(H.st));
+    }
+    bool conv = true;
+    for (int c = 0; c < k; ++c) conv &= !(active[c] && resid[c] > tol);
+    if (conv) break;
+    if (total >= max_iter) { status = HELM_ENOCONV; break; }
+  }
+  last_resid = resid;
+  if (iters_out) *iters_out = total;
+  return status;
+}
+
+double2* Method::basis_vec(int i) {
+  while ((int)basis.size() <= i) {
+    basis.emplace_back(new DevMem);
+    basis.back()->alloc((size_t)2 * Vp * sizeof(double2));
+  }
+  return basis[i]->as<double2>();
+}
+
+// u = H^-1 f through the polarized interface system (one inner solve)
+int Method::polarized_solve(const double2* f, double2* u, double tol, int max_iter,
+                            int restart, helm_solve_info* info) {
+  const int L = H.G.L;
+  double t0 = now_ms();
+  if (L == 1) {
+    scatter_sources(f);
+    H.solve_layers(*set_all, k);
+    if (H.prec == HELM_FP64)
+      kern::launch_gather_volume<double>(H.layers_h[0], u, H.G.nx, H.G.ny, N, k, H.st);
+    else
+      kern::launch_gather_volume<float>(H.layers_h[0], u, H.G.nx, H.G.ny, N, k, H.st);
+    HELM_HIP(hipStreamSynchronize(H.st));
+    if (info) info->t_reconstruct_ms += now_ms() - t0;
+    return HELM_OK;
+  }
+  DevMem fpol, bpol, xpol;
+  fpol.alloc((size_t)2 * Vp * sizeof(double2));
+  bpol.alloc((size_t)2 * Vp * sizeof(double2));
+  xpol.alloc((size_t)2 * Vp * sizeof(double2));
+  double2* fdv = fpol.as<double2>();
+  polarized_rhs(f, fdv, fdv + Vp);
+  apply_P(fdv, fdv + Vp, bpol.as<double2>(), bpol.as<double2>() + Vp);
+  HELM_HIP(hipStreamSynchronize(H.st));
+  double t1 = now_ms();
+  int iters = 0;
+  int st = gmres(bpol.as<double2>(), xpol.as<double2>(), tol, max_iter, restart, &iters);
+  HELM_HIP(hipStreamSynchronize(H.st));
+  double t2 = now_ms();
+  // traces u_j = u_down_j + u_up_j
+  double2* tr = fpol.as<double2>();
+  kern::launch_add(tr, xpol.as<double2>(), xpol.as<double2>() + Vp, Vp, H.st);
+  reconstruct(f, tr, u);
+  HELM_HIP(hipStreamSynchronize(H.st));
+  double t3 = now_ms();
+  if (info) {
+    info->t_setup_ms += t1 - t0;
+    info->t_gmres_ms += t2 - t1;
+    info->t_reconstruct_ms += t3 - t2;
+    info->gmres_iters += iters;
+  }
+  return st;
+}
+
+// per-column |f - H u| / |f| in FP64; r receives the residual
+void Method::residual(const double2* f, const double2* u, double2* r,
+                      std::vector<double>& rel) {
+  kern::launch_residual(H.grid, f, u, r, k, H.st);
+  std::vector<double> nr(k), nf(k);
+  kern::launch_volume_norm2(r, N, k, norm_partial.as<double>(), norm_out.as<double>(), H.st);
+  HELM_HIP(hipMemcpyAsync(nr.data(), norm_out.p, k * sizeof(double), hipMemcpyDeviceToHost, H.st));
+  HELM_HIP(hipStreamSynchronize(H.st));
+  kern::launch_volume_norm2(f, N, k, norm_partial.as<double>(), norm_out.as<double>(), H.st);
+  HELM_HIP(hipMemcpyAsync(nf.data(), norm_out.p, k * sizeof(double), hipMemcpyDeviceToHost, H.st));
+  HELM_HIP(hipStreamSynchronize(H.st));
+  rel.resize(k);
+  for (int c = 0; c < k; ++c) rel[c] = nf[c] > 0 ? std::sqrt(nr[c] / nf[c]) : std::sqrt(nr[c]);
+}
+
+// Full online solve of k columns (device arrays).
+int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
+  const helm_options& o = H.opt;
+  const int restart = gmres_restart(o.gmres_max_iter);
+  DevMem r;
+  r.alloc((size_t)N * k * sizeof(double2));
+  std::vector<double> rel;
+  int status = HELM_OK;
+  double t0 = now_ms();
+  if (H.prec == HELM_FP64) {
+    status = polarized_solve(f, u, o.gmres_tol, o.gmres_max_iter, restart, info);
+    double tr = now_ms();
+    residual(f, u, r.as<double2>(), rel);
+    if (info) {
+      info->ir_steps = 1;
+      info->t_residual_ms += now_ms() - tr;
+    }
+  } else {
+    // iterative refinement: u <- u + solve_c64(f - H u), FP64 residuals
+    DevMem d;
+    d.alloc((size_t)N * k * sizeof(double2));
+    HELM_HIP(hipMemsetAsync(u, 0, (size_t)N * k * sizeof(double2), H.st));
+    const double2* rhs = f;
+    int steps = 0;
+    status = HELM_ENOCONV;
+    for (int it = 0; it < std::max(1, o.ir_max_steps); ++it) {
+      int s = polarized_solve(rhs, d.as<double2>(), o.inner_tol, o.gmres_max_iter, restart,
+                              info);
+      (void)s;
+      kern::launch_accumulate(u, d.as<double2>(), N * k, H.st);
+      double tr = now_ms();
+      residual(f, u, r.as<double2>(), rel);
+      if (info) info->t_residual_ms += now_ms() - tr;
+      ++steps;
+      double mx = 0;
+      for (double v : rel) mx = std::max(mx, std::isfinite(v) ? v : 1e300);
+      if (mx <= o.ir_tol) { status = HELM_OK; break; }
+      rhs = r.as<double2>();
+    }
+    if (info) info->ir_steps = steps;
+  }
+  if (info) {
+    double mx = 0;
+    for (double v : rel) mx = std::max(mx, v);
+    info->rel_residual_max = std::max(info->rel_residual_max, mx);
+    info->t_total_ms += now_ms() - t0;
+  }
+  return status;
+}
+
+int Method::gmres_restart(int max_iter) const {
+  // bounded by memory: basis vectors of 2 pair vectors x k columns each
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return std::min(max_iter, 16);
+  size_t per = (size_t)2 * Vp * sizeof(double2);
+  size_t fit = per ? (size_t)(0.6 * free_b) / per : 64;
+  int m = (int)std::min<size_t>(fit > 3 ? fit - 3 : 1, 60);
+  return std::max(1, std::min(max_iter, m));
+}
+
+}  // namespace helm

@@ -1,0 +1,53 @@
+// Online stage of the method on one batch of k right-hand-side columns.
+#pragma once
+
+#include <vector>
+
+#include "handle.h"
+
+namespace helm {
+
+struct Method {
+  Handle& H;
+  int k;
+  long long plane = 0, pair_elems = 0, Vp = 0, N = 0;
+  DevMem y, zd, zu, keep, dot_partial, hcol, norm_partial, norm_out, scale;
+  const LayerSet* set_all = nullptr;
+  const LayerSet* set_lower = nullptr;
+  std::vector<const LayerSet*> single;
+  std::vector<double> last_resid;
+  // Krylov basis and temporaries, grown on demand and kept between calls
+  std::vector<std::unique_ptr<DevMem>> basis;
+  DevMem gw, gr;
+  double2* basis_vec(int i);
+
+  Method(Handle& h, int k);
+
+  double2* pair(double2* v, int j) const;
+  const double2* pair(const double2* v, int j) const;
+  void zero_X(int l);
+  template <typename T> void jump_t(int l, const double2* a, const double2* b, int bottom);
+  void jump(int l, const double2* a, const double2* b, int bottom);
+  void readout(int l, int bottom, double sx, const kern::ReadTerms& t, double2* out);
+  static kern::ReadTerms terms(const double2* a = nullptr, double ca = 0, double cb = 0,
+                               const double2* b = nullptr, double cb_a = 0,
+                               double cb_b = 0, const double2* c = nullptr,
+                               double cc_a = 0, double cc_b = 0);
+  void solve_single(int l);
+  void apply_P(const double2* vd, const double2* vu, double2* od, double2* ou);
+  void apply_U(const double2* xu, double2* out);
+  void apply_A(const double2* x, double2* out);
+  void scatter_sources(const double2* f);
+  void polarized_rhs(const double2* f, double2* fd, double2* fu);
+  void reconstruct(const double2* f, const double2* tr, double2* u);
+  void dot(const double2* a, const double2* b, long long V, double2* out);
+  int gmres(const double2* b, double2* x, double tol, int max_iter, int restart,
+            int* iters);
+  int polarized_solve(const double2* f, double2* u, double tol, int max_iter,
+                      int restart, helm_solve_info* info);
+  void residual(const double2* f, const double2* u, double2* r, std::vector<double>& rel);
+  int solve(const double2* f, double2* u, helm_solve_info* info);
+  int gmres_restart(int max_iter) const;
+};
+
+}  // namespace helm

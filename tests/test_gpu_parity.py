@@ -1,0 +1,152 @@
+"""Parity of the HIP path with the CPU oracle (run on an MI355X).
+
+Every comparison uses seeded inputs from ``helm_inputs`` and an expected
+value computed by ``oracle/`` alone (SuperLU on the oracle's own assembly,
+or the oracle's step-by-step polarized traces).  Tolerances:
+complex128 paths relative l2 <= 1e-9 (GMRES tol 1e-10) and <= 1e-11 for a
+single local solve; mixed precision <= 1e-6 against the FP64 reference.
+"""
+
+import numpy as np
+import pytest
+
+from helm_inputs import workload
+from oracle.direct import SparseLU, relative_error
+from oracle.discretization import Problem, local_operator, point_source_rhs
+from oracle.polarized import PolarizedTraces
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.filterwarnings("ignore::DeprecationWarning")]
+
+torch = pytest.importorskip("torch")
+
+
+def _solver(wl, precision, **kw):
+    import paper_1801_08655_amd as pt
+    return pt.Solver(wl.m(), wl.h, wl.omega, wl.pml, wl.n_layers, precision=precision,
+                     pml_local=wl.pml_local, pml_C=wl.pml_C, **kw)
+
+
+def _problem(wl):
+    return Problem(wl.m(), wl.h, wl.omega, wl.pml, wl.pml_C)
+
+
+@pytest.fixture(scope="module")
+def homog():
+    wl = workload("homogeneous-25")
+    pb = _problem(wl)
+    F = point_source_rhs(pb.shape, wl.sources, wl.h)
+    u = SparseLU(pb.operator()).solve(F)[:, 0]
+    return wl, pb, u
+
+
+def _rand(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 2e-4)])
+def test_layer_solve_matches_oracle(homog, precision, tol):
+    """One multi-RHS local solve (H^l)^-1 r against SuperLU on the oracle's H^l."""
+    wl, pb, _ = homog
+    s = _solver(wl, precision)
+    nx, ny, nz = wl.n
+    for l in range(wl.n_layers):
+        _, _, lo, hi = s.layer_info(l)
+        t = hi - lo + 1
+        r = _rand((3, t, ny, nx), 100 + l)
+        w = s.layer_solve(l, torch.from_numpy(r).cuda()).cpu().numpy()
+        Hl = local_operator(pb, wl.n_layers, wl.pml_local, l)
+        ref = SparseLU(Hl).solve(r.reshape(3, -1).T).T
+        err = relative_error(w.reshape(3, -1).T, ref.T)
+        print(f"layer {l} ({precision}) rel err {err}")
+        assert err.max() <= tol
+
+
+def test_operator_matches_oracle(homog):
+    wl, pb, _ = homog
+    s = _solver(wl, "fp64")
+    u = _rand((2,) + pb.shape, 7)
+    hu = s.apply_operator(torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = (pb.operator() @ u.reshape(2, -1).T).T
+    assert relative_error(hu.reshape(2, -1).T, ref.T).max() <= 1e-13
+
+
+def _pairs_gpu_layout(x):
+    """oracle pairs (L-1, 2, ny, nx) per column -> [j][p][y][x][c] flat"""
+    return np.stack(x, axis=-1).ravel()
+
+
+def test_interface_operators_match_oracle(homog):
+    """U (Alg. 10 read as the mirror of Alg. 6), P (Algs. 4-6) and P M."""
+    wl, pb, _ = homog
+    s = _solver(wl, "fp64")
+    pt_cpu = PolarizedTraces(pb, wl.n_layers, wl.pml_local)
+    k = 2
+    shape = pt_cpu.zero_pairs().shape
+    xd = [_rand(shape, 11 + c) for c in range(k)]
+    xu = [_rand(shape, 21 + c) for c in range(k)]
+    gx = torch.from_numpy(np.concatenate([_pairs_gpu_layout(xd), _pairs_gpu_layout(xu)])).cuda()
+    gxu = torch.from_numpy(_pairs_gpu_layout(xu)).cuda()
+    # U
+    gu = s.polarized_op(2, gxu, k).cpu().numpy()
+    ref = _pairs_gpu_layout([pt_cpu.U_op(x) for x in xu])
+    assert relative_error(gu, ref)[0] <= 1e-11
+    # P
+    gp = s.polarized_op(0, gx, k).cpu().numpy()
+    refs = [pt_cpu.precondition(a, b) for a, b in zip(xd, xu)]
+    ref = np.concatenate([_pairs_gpu_layout([r[0] for r in refs]),
+                          _pairs_gpu_layout([r[1] for r in refs])])
+    assert relative_error(gp, ref)[0] <= 1e-11
+    # P M
+    ga = s.polarized_op(1, gx, k).cpu().numpy()
+    refs = [pt_cpu.precondition(*pt_cpu.apply_M(a, b)) for a, b in zip(xd, xu)]
+    ref = np.concatenate([_pairs_gpu_layout([r[0] for r in refs]),
+                          _pairs_gpu_layout([r[1] for r in refs])])
+    assert relative_error(ga, ref)[0] <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["homogeneous-25", "smooth-24", "layered-28"])
+def test_fp64_solve_matches_direct(name):
+    wl = workload(name)
+    pb = _problem(wl)
+    srcs = wl.sources[:2]
+    F = point_source_rhs(pb.shape, srcs, wl.h)
+    ref = SparseLU(pb.operator()).solve(F)
+    s = _solver(wl, "fp64", gmres_tol=1e-10)
+    u, info = s.solve_points(srcs, info=True)
+    u = u.cpu().numpy().reshape(len(srcs), -1).T
+    err = relative_error(u, ref)
+    print(name, "fp64 err", err, info)
+    assert err.max() <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["homogeneous-25", "layered-28"])
+def test_mixed_solve_matches_direct(name):
+    wl = workload(name)
+    pb = _problem(wl)
+    srcs = wl.sources[:2]
+    F = point_source_rhs(pb.shape, srcs, wl.h)
+    ref = SparseLU(pb.operator()).solve(F)
+    s = _solver(wl, "mixed")
+    u, info = s.solve_points(srcs, info=True)
+    u = u.cpu().numpy().reshape(len(srcs), -1).T
+    err = relative_error(u, ref)
+    print(name, "mixed err", err, info)
+    assert err.max() <= 1e-6
+
+
+def test_single_layer_equals_global_solve():
+    """L = 1: the method is one local solve of the global system."""
+    from helm_inputs import smooth_random_model, omega_for_ppw
+    import paper_1801_08655_amd as pt
+    n, p = 16, 4
+    h = 1.0 / (n - 1)
+    m = smooth_random_model((n, n, n), 0.25, 2.0, 0.75, 1.25, 5)
+    om = omega_for_ppw(0.75, h, 10.0)
+    pb = Problem(m, h, om, p, 25.0)
+    F = point_source_rhs(pb.shape, [(5, 7, 9), (8, 8, 8)], h)
+    ref = SparseLU(pb.operator()).solve(F)
+    s = pt.Solver(m, h, om, p, 1, precision="fp64", pml_C=25.0)
+    u = s.solve(torch.from_numpy(F.T.reshape(2, n, n, n).copy()).cuda()).cpu().numpy()
+    assert relative_error(u.reshape(2, -1).T, ref).max() <= 1e-11
