@@ -180,7 +180,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
-                  ir_tol=1e-9, inner_tol=1e-5, **common)
+                  ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4, err_target=1e-6,
+                  ir_max_steps=4, **common)
     torch.cuda.synchronize()
     factor_s = time.perf_counter() - t0
     log(f"[mixed] factorized in {factor_s:.2f}s; warmup {args.warmup}, steps {args.steps}")
@@ -218,6 +219,9 @@ def main():
         "gmres_iters": info["gmres_iters"],
         "ir_steps": info["ir_steps"],
         "rel_residual_max": info["rel_residual_max"],
+        "est_error_max": info["est_error_max"],
+        "ir_residual": info["ir_residual"],
+        "ir_gmres_iters": info["ir_gmres_iters"],
         "layer_solves_per_step": info["layer_solves"],
         "roofline": rl,
         "kernels": kstats,

@@ -72,7 +72,11 @@ typedef struct {
   int    gmres_max_iter;   /* max GMRES iterations (no restart below this)   */
   double ir_tol;           /* mixed: stop refinement at |f-Hu| <= ir_tol |f| */
   int    ir_max_steps;     /* mixed: max refinement steps                    */
-  double inner_tol;        /* mixed: GMRES tolerance of each refinement step */
+  double inner_tol;        /* mixed: GMRES tolerance of the first solve      */
+  double inner_tol_refine; /* mixed: GMRES tolerance of later refinement steps
+                              (<= 0: same as inner_tol)                      */
+  double err_target;       /* mixed: also stop once the estimated error of
+                              every column is below this (<= 0: off)         */
   size_t hbm_budget_bytes; /* 0 = 90% of free device memory                  */
   int    device;           /* HIP device ordinal                             */
   void*  stream;           /* hipStream_t for the *_dev entry points (NULL = default) */
@@ -93,12 +97,20 @@ typedef struct {
   double t_total_ms;
   long long layer_solves;    /* number of single-layer multi-RHS solves      */
   double factor_bytes_read;  /* factor bytes streamed by the substitutions   */
+  double ir_residual[8];     /* max over columns of |f - H u| / |f| after each
+                                refinement step (first 8 steps)              */
+  double est_error_max;      /* mixed: max over columns of the estimated
+                                relative error |u - H^-1 f| / |u|, from the
+                                contraction of successive corrections
+                                (|d_k|/|u| * q/(1-q), q = |d_k|/|d_{k-1}|);
+                                1 when only one step was taken               */
+  int    ir_gmres_iters[8];  /* GMRES iterations of each refinement step     */
 } helm_solve_info;
 
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,
  * gmres_tol 1e-10, gmres_max_iter 40, ir_tol 1e-9, ir_max_steps 6,
- * inner_tol 1e-5, hbm_budget 0 (auto), device 0, stream NULL, max_rhs 64,
- * leaf_size 64, flags 0. */
+ * inner_tol 1e-3, inner_tol_refine 1e-4, err_target 0 (off), hbm_budget 0
+ * (auto), device 0, stream NULL, max_rhs 64, leaf_size 64, flags 0. */
 void helm_default_options(helm_options* opt);
 
 /* Planner (no device memory is touched).  Exact sizes from the symbolic
@@ -162,6 +174,11 @@ typedef struct {
 
 int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count,
                       int reset);
+
+/* Change the online-stage options of a factorized handle (gmres_tol,
+ * gmres_max_iter, ir_tol, ir_max_steps, inner_tol, max_rhs, flags); the
+ * geometry, precision, device and stream fields are ignored. */
+int helm_set_solve_options(helm_handle* h, const helm_options* opt);
 
 /* Release the factors and all device memory owned by the handle. */
 int helm_free(helm_handle* h);

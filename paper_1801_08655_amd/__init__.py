@@ -165,6 +165,15 @@ class Solver:
               "helm_polarized_op_dev")
         return out
 
+    def set_options(self, **kw):
+        """Change online-stage options (tolerances, steps, batch width, flags)."""
+        for key, val in kw.items():
+            if not hasattr(self.opts, key):
+                raise TypeError(f"unknown option {key}")
+            setattr(self.opts, key, val)
+        check(lib().helm_set_solve_options(self._h, ctypes.byref(self.opts)),
+              "helm_set_solve_options")
+
     def kernel_stats(self, reset: bool = False):
         """Event-timed per-kernel-class statistics (needs flags=HELM_FLAG_PROFILE)."""
         arr = (_lib.helm_kernel_stat * 32)()

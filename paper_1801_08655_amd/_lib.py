@@ -22,6 +22,7 @@ EXPORTED = [
     "helm_solve", "helm_solve_dev", "helm_solve_points", "helm_free",
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
+    "helm_set_solve_options",
 ]
 HELM_FLAG_PROFILE = 1
 
@@ -41,6 +42,8 @@ class helm_options(ctypes.Structure):
         ("ir_tol", ctypes.c_double),
         ("ir_max_steps", ctypes.c_int),
         ("inner_tol", ctypes.c_double),
+        ("inner_tol_refine", ctypes.c_double),
+        ("err_target", ctypes.c_double),
         ("hbm_budget_bytes", ctypes.c_size_t),
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
@@ -63,10 +66,17 @@ class helm_solve_info(ctypes.Structure):
         ("t_total_ms", ctypes.c_double),
         ("layer_solves", ctypes.c_longlong),
         ("factor_bytes_read", ctypes.c_double),
+        ("ir_residual", ctypes.c_double * 8),
+        ("est_error_max", ctypes.c_double),
+        ("ir_gmres_iters", ctypes.c_int * 8),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        n = max(1, min(8, self.ir_steps))
+        d["ir_residual"] = list(self.ir_residual[:n])
+        d["ir_gmres_iters"] = list(self.ir_gmres_iters[:n])
+        return d
 
 
 class helm_kernel_stat(ctypes.Structure):
@@ -127,6 +137,8 @@ def lib():
     L.helm_kernel_stats.argtypes = [H, ctypes.POINTER(helm_kernel_stat), I,
                                     ctypes.POINTER(I), I]
     L.helm_kernel_stats.restype = I
+    L.helm_set_solve_options.argtypes = [H, ctypes.POINTER(helm_options)]
+    L.helm_set_solve_options.restype = I
     _lib = L
     return L
 

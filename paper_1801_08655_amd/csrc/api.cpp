@@ -51,6 +51,7 @@ helm_options resolve(const helm_options* o) {
   if (r.ir_tol <= 0) r.ir_tol = d.ir_tol;
   if (r.ir_max_steps <= 0) r.ir_max_steps = d.ir_max_steps;
   if (r.inner_tol <= 0) r.inner_tol = d.inner_tol;
+  if (r.inner_tol_refine <= 0) r.inner_tol_refine = r.inner_tol;
   if (r.max_rhs <= 0) r.max_rhs = d.max_rhs;
   if (r.leaf_size <= 0) r.leaf_size = d.leaf_size;
   return r;
@@ -125,7 +126,9 @@ void helm_default_options(helm_options* o) {
   o->gmres_max_iter = 40;
   o->ir_tol = 1e-9;
   o->ir_max_steps = 6;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 1e-3;
+  o->inner_tol_refine = 1e-4;
+  o->err_target = 0.0;
   o->hbm_budget_bytes = 0;
   o->device = 0;
   o->stream = nullptr;
@@ -265,7 +268,8 @@ int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count
     Handle& H = h->impl;
     H.collect_profile();
     static const char* names[K_NCLASS] = {
-        "solve_fwd_gather", "solve_fwd_gemm", "solve_bwd_gather", "solve_bwd_gemm",
+        "solve_fwd_gather", "solve_fwd_gemm", "solve_fwd_reduce", "solve_bwd_gemm",
+        "solve_bwd_reduce",
         "factor_sweep_gemm", "factor_panel", "factor_swap_rows", "factor_update_cols",
         "factor_extend_add", "factor_orig_entries", "factor_store"};
     int n = 0;
@@ -284,6 +288,25 @@ int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count
     if (count) *count = n;
     if (reset)
       for (auto& k : H.kstats) k = KStat{};
+    return HELM_OK;
+  });
+}
+
+int helm_set_solve_options(helm_handle* h, const helm_options* opt) {
+  return guard([&] {
+    HELM_REQUIRE(h && opt, HELM_EINVAL, "null argument");
+    helm_options o = resolve(opt);
+    Handle& H = h->impl;
+    H.opt.gmres_tol = o.gmres_tol;
+    H.opt.gmres_max_iter = o.gmres_max_iter;
+    H.opt.ir_tol = o.ir_tol;
+    H.opt.ir_max_steps = o.ir_max_steps;
+    H.opt.inner_tol = o.inner_tol;
+    H.opt.inner_tol_refine = o.inner_tol_refine;
+    H.opt.err_target = o.err_target;
+    H.opt.max_rhs = o.max_rhs;
+    H.opt.flags = o.flags;
+    H.profile = (o.flags & HELM_FLAG_PROFILE) != 0;
     return HELM_OK;
   });
 }

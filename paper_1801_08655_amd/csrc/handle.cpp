@@ -465,31 +465,69 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
   int maxd = 0;
   for (int l : layers) maxd = std::max(maxd, G.layers[l].max_depth);
   S->max_depth = maxd;
+  // Split a front's K dimension when the depth has too few output tiles to
+  // fill the device: aim at ~2048 workgroups, chunks of >= 256.
+  const int target = 2048;
+  auto split = [&](long long tiles, int K, int& nch, int& kc) {
+    nch = 1;
+    if (K > 0 && tiles < target / 2) {
+      long long want = (target + tiles - 1) / tiles;
+      nch = (int)std::max<long long>(1, std::min<long long>(want, K / 256));
+    }
+    if (K <= 0) { nch = 1; kc = 16; return; }
+    kc = (K + nch - 1) / nch;
+    kc = (kc + 15) / 16 * 16;
+    nch = (K + kc - 1) / kc;
+  };
   for (int d = 0; d <= maxd; ++d) {
     auto D = std::make_unique<DepthList>();
     std::vector<int> ids;
     for (int l : layers)
       if (d <= G.layers[l].max_depth)
         for (int q : G.layers[l].by_depth[d]) ids.push_back(front_base[l] + q);
-    std::vector<int> pSB(ids.size() + 1, 0), pB(ids.size() + 1, 0), pS(ids.size() + 1, 0);
-    for (size_t a = 0; a < ids.size(); ++a) {
+    const size_t n = ids.size();
+    long long tf = 0, tb = 0;
+    for (int f : ids) {
+      tf += tiles64(fronts_h[f].s + fronts_h[f].b);
+      tb += fronts_h[f].b > 0 ? tiles64(fronts_h[f].s) : 0;
+    }
+    std::vector<SolveTask> tasks(n);
+    std::vector<int> pSB(n + 1, 0), pF(n + 1, 0), pBw(n + 1, 0), rF(n + 1, 0), rB(n + 1, 0);
+    long long scr_f = 0, scr_b = 0;
+    for (size_t a = 0; a < n; ++a) {
       const FrontDev& F = fronts_h[ids[a]];
+      SolveTask& t = tasks[a];
+      split(tf, F.s, t.nch_f, t.kc_f);
+      split(tb, F.b, t.nch_b, t.kc_b);
+      t.scr_f = scr_f;
+      t.scr_b = scr_b;
+      if (t.nch_f > 1) scr_f += (long long)t.nch_f * (F.s + F.b);
+      if (t.nch_b > 1) scr_b += (long long)t.nch_b * F.s;
       D->sum_s += F.s;
       D->sum_b += F.b;
       D->sum_sbs += (double)(F.s + F.b) * F.s;
       D->sum_bs += (double)F.b * F.s;
       pSB[a + 1] = pSB[a] + tiles64(F.s + F.b);
-      pB[a + 1] = pB[a] + tiles64(F.b);
-      pS[a + 1] = pS[a] + tiles64(F.s);
+      pF[a + 1] = pF[a] + tiles64(F.s + F.b) * t.nch_f;
+      pBw[a + 1] = pBw[a] + (F.b > 0 ? tiles64(F.s) * t.nch_b : 0);
+      rF[a + 1] = rF[a] + (t.nch_f > 1 ? tiles64(F.s + F.b) : 0);
+      rB[a + 1] = rB[a] + (t.nch_b > 1 ? tiles64(F.s) : 0);
     }
-    D->n = (int)ids.size();
+    D->n = (int)n;
     upload(D->ids, ids, st);
+    upload(D->tasks, tasks, st);
     upload(D->pSB, pSB, st);
-    upload(D->pB, pB, st);
-    upload(D->pS, pS, st);
+    upload(D->pF, pF, st);
+    upload(D->pBw, pBw, st);
+    upload(D->rF, rF, st);
+    upload(D->rB, rB, st);
     D->tSB = pSB.back();
-    D->tB = pB.back();
-    D->tS = pS.back();
+    D->tF = pF.back();
+    D->tBw = pBw.back();
+    D->tRF = rF.back();
+    D->tRB = rB.back();
+    D->scratch_rows = std::max(scr_f, scr_b);
+    S->scratch_rows = std::max(S->scratch_rows, D->scratch_rows);
     S->depth.push_back(std::move(D));
   }
   HELM_HIP(hipStreamSynchronize(st));
@@ -505,6 +543,11 @@ double Handle::solve_elems(const LayerSet& set) const {
 }
 
 void Handle::solve_layers(const LayerSet& set, int k) {
+  size_t need = (size_t)std::max<long long>(set.scratch_rows, 1) * std::max(k, kcap) * elem;
+  if (scratch.bytes < need) {
+    HELM_HIP(hipStreamSynchronize(st));
+    scratch.alloc(need);
+  }
   if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
   layer_solves += (long long)set.layers.size();
   solve_bytes += solve_elems(set) * (double)elem;
@@ -515,27 +558,39 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
   const FrontDev* fr = fronts.as<FrontDev>();
   const LayerDev* ld = layers_d.as<LayerDev>();
   const double e = (double)elem, kk = (double)k;
+  void* scr = scratch.p;
   for (int d = set.max_depth; d >= 0; --d) {
     const DepthList& D = *set.depth[d];
     if (D.n == 0) continue;
+    const int* ids = D.ids.as<int>();
+    const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin();
-    kern::launch_fwd_gather<T>(fr, D.ids.as<int>(), D.n, D.pSB.as<int>(), D.tSB, ld, k, st);
+    kern::launch_fwd_gather<T>(fr, ids, D.n, D.pSB.as<int>(), D.tSB, ld, k, st);
     prof_end(K_FWD_GATHER, a, 0, 2.0 * (D.sum_s + D.sum_b) * kk * e);
     a = prof_begin();
-    kern::launch_fwd_gemm<T>(fr, D.ids.as<int>(), D.n, D.pSB.as<int>(), D.tSB, ld, k, st);
+    kern::launch_fwd_gemm<T>(fr, ids, tk, D.n, D.pF.as<int>(), D.tF, ld, k, scr, st);
     prof_end(K_FWD_GEMM, a, 8.0 * D.sum_sbs * kk,
              D.sum_sbs * e + (2.0 * D.sum_s + 2.0 * D.sum_b) * kk * e);
+    if (D.tRF > 0) {
+      a = prof_begin();
+      kern::launch_fwd_reduce<T>(fr, ids, tk, D.n, D.rF.as<int>(), D.tRF, ld, k, scr, st);
+      prof_end(K_FWD_REDUCE, a, 0, 0);
+    }
   }
   for (int d = 0; d <= set.max_depth; ++d) {
     const DepthList& D = *set.depth[d];
     if (D.n == 0) continue;
+    const int* ids = D.ids.as<int>();
+    const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin();
-    kern::launch_bwd_gather<T>(fr, D.ids.as<int>(), D.n, D.pB.as<int>(), D.tB, ld, k, st);
-    prof_end(K_BWD_GATHER, a, 0, 2.0 * D.sum_b * kk * e);
-    a = prof_begin();
-    kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.n, D.pS.as<int>(), D.tS, ld, k, st);
+    kern::launch_bwd_gemm<T>(fr, ids, tk, D.n, D.pBw.as<int>(), D.tBw, ld, k, scr, st);
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
+    if (D.tRB > 0) {
+      a = prof_begin();
+      kern::launch_bwd_reduce<T>(fr, ids, tk, D.n, D.rB.as<int>(), D.tRB, ld, k, scr, st);
+      prof_end(K_BWD_REDUCE, a, 0, 0);
+    }
   }
 }
 

@@ -27,14 +27,18 @@ struct DevMem {
 struct DepthList {
   int n = 0;
   DevMem ids;                 // global front ids
-  DevMem pSB, pB, pS;         // prefix sums of 64-row tiles of s+b, b, s
-  int tSB = 0, tB = 0, tS = 0;
+  DevMem tasks;               // SolveTask per front (K splits, scratch offsets)
+  DevMem pSB;                 // prefix of 64-row tiles of s+b (forward gather)
+  DevMem pF, pBw;             // prefix of GEMM tiles incl. K chunks (fwd, bwd)
+  DevMem rF, rB;              // prefix of 64-row reduce tiles of split fronts
+  int tSB = 0, tF = 0, tBw = 0, tRF = 0, tRB = 0;
   double sum_s = 0, sum_b = 0, sum_sbs = 0, sum_bs = 0;  // work counts
+  long long scratch_rows = 0;
 };
 
 // Kernel classes timed with HIP events when HELM_FLAG_PROFILE is set.
 enum KClass {
-  K_FWD_GATHER, K_FWD_GEMM, K_BWD_GATHER, K_BWD_GEMM, K_SWEEP_GEMM, K_PANEL,
+  K_FWD_GATHER, K_FWD_GEMM, K_FWD_REDUCE, K_BWD_GEMM, K_BWD_REDUCE, K_SWEEP_GEMM, K_PANEL,
   K_SWAP_JO, K_UPDATE_OJ, K_EXTEND_ADD, K_ORIG, K_STORE, K_NCLASS
 };
 struct KStat {
@@ -49,6 +53,7 @@ struct PendingEvent {
 struct LayerSet {
   std::vector<int> layers;
   int max_depth = 0;
+  long long scratch_rows = 0;   // max over depths
   std::vector<std::unique_ptr<DepthList>> depth;
 };
 
@@ -88,6 +93,7 @@ struct Handle {
   int kcap = 0;
   std::vector<std::unique_ptr<DevMem>> X, Wt, Ub0, Ub1;
   std::map<std::vector<int>, std::unique_ptr<LayerSet>> sets;
+  DevMem scratch;                // split-K partial products
 
   // kernel timing (HELM_FLAG_PROFILE)
   bool profile = false;

@@ -60,6 +60,16 @@ struct FrontDev {
   int pad;
 };
 
+// Split of one front's substitution GEMMs along K (the pivot / boundary
+// dimension) into chunks computed by separate workgroups; partial products
+// go to a scratch area and are summed in a fixed order.
+struct SolveTask {
+  int nch_f, kc_f;   // forward: chunks, chunk length
+  int nch_b, kc_b;   // backward
+  long long scr_f;   // scratch row offset of the forward partials (nch_f x (s+b) rows)
+  long long scr_b;   // scratch row offset of the backward partials (nch_b x s rows)
+};
+
 // Per-layer base pointers for kernels that touch several layers at once.
 struct LayerDev {
   void* fac;          // factor store base (complex elements of the precision)

@@ -52,14 +52,21 @@ template <typename T>
 void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
                        int total, const LayerDev* layers, int k, hipStream_t st);
 template <typename T>
-void launch_fwd_gemm(const FrontDev* fr, const int* ids, int n, const int* prefix,
-                     int total_mtiles, const LayerDev* layers, int k, hipStream_t st);
+void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     void* scratch, hipStream_t st);
 template <typename T>
-void launch_bwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
-                       int total, const LayerDev* layers, int k, hipStream_t st);
+void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                       const int* prefix, int total, const LayerDev* layers, int k,
+                       const void* scratch, hipStream_t st);
 template <typename T>
-void launch_bwd_gemm(const FrontDev* fr, const int* ids, int n, const int* prefix,
-                     int total_mtiles, const LayerDev* layers, int k, hipStream_t st);
+void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     void* scratch, hipStream_t st);
+template <typename T>
+void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                       const int* prefix, int total, const LayerDev* layers, int k,
+                       const void* scratch, hipStream_t st);
 
 // --- volumes, traces, Krylov (kernels_volume.hip) ---------------------------
 template <typename T>

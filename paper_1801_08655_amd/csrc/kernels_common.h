@@ -114,44 +114,64 @@ template <typename T> struct GemmSmem {
   C_t<T> Q[GK][GT + 1];
 };
 
-// Operand view: element (r, k) at base[r * sr + k * sk], valid for r < nr, k < nk.
+// Operand view: element (r, k) at base[r * sr + kk * sk], valid for r < nr,
+// k < nk, with kk = k, or kk = kmap[k] when a row map is given (indirect
+// rows, e.g. the boundary variables of a front).
 template <typename T> struct View {
   const C_t<T>* base;
   long long sr, sk;
   int nr, nk;
+  const int* kmap = nullptr;
 };
 
-// Cooperative load of a 64 x GK block of `v` (rows r0.., cols k0..) into P
-// (FAST_R: consecutive threads walk r; else they walk k).
-template <typename T, bool FAST_R>
-__device__ __forceinline__ void load_P(GemmSmem<T>& sm, const View<T>& v, int r0, int k0) {
+template <typename T>
+__device__ __forceinline__ C_t<T> view_at(const View<T>& v, int r, int k) {
+  C_t<T> val = czero<C_t<T>>();
+  if (r < v.nr && k < v.nk) {
+    const long long kk = v.kmap ? (long long)v.kmap[k] : (long long)k;
+    val = v.base[(long long)r * v.sr + kk * v.sk];
+  }
+  return val;
+}
+
+constexpr int GLOADS = (GT * GK) / 256;   // elements per thread per operand tile
+
+// Per-thread staging registers for one K step of both operands.
+template <typename T> struct Stage {
+  C_t<T> p[GLOADS], q[GLOADS];
+};
+
+// Global loads of the 64 x GK block of P (rows r0.., k0..) and the GK x 64
+// block of Q (columns c0.., k0..).  FAST_R / FAST_C: consecutive threads walk
+// the rows of P / the columns of Q (the contiguous dimension in memory).
+template <typename T, bool FAST_R, bool FAST_C>
+__device__ __forceinline__ void stage_load(Stage<T>& g, const View<T>& pv, const View<T>& qv,
+                                           int r0, int c0, int k0, int kend) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < (GT * GK) / 256; ++it) {
-    int e = t + it * 256;
+  for (int it = 0; it < GLOADS; ++it) {
+    const int e = t + it * 256;
     int r, k;
     if (FAST_R) { r = e % GT; k = e / GT; } else { k = e % GK; r = e / GK; }
-    int gr = r0 + r, gk = k0 + k;
-    C_t<T> val = czero<C_t<T>>();
-    if (gr < v.nr && gk < v.nk) val = v.base[(long long)gr * v.sr + (long long)gk * v.sk];
-    sm.P[r][k] = val;
+    g.p[it] = (k0 + k < kend) ? view_at(pv, r0 + r, k0 + k) : czero<C_t<T>>();
+    int c, kq;
+    if (FAST_C) { c = e % GT; kq = e / GT; } else { kq = e % GK; c = e / GK; }
+    g.q[it] = (k0 + kq < kend) ? view_at(qv, c0 + c, k0 + kq) : czero<C_t<T>>();
   }
 }
 
-// Cooperative load of a GK x 64 block into Q; the view is indexed (c, k)
-// (c plays the role of r in View), FAST_C: threads walk c.
-template <typename T, bool FAST_C>
-__device__ __forceinline__ void load_Q(GemmSmem<T>& sm, const View<T>& v, int c0, int k0) {
+template <typename T, bool FAST_R, bool FAST_C>
+__device__ __forceinline__ void stage_store(GemmSmem<T>& sm, const Stage<T>& g) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < (GT * GK) / 256; ++it) {
-    int e = t + it * 256;
-    int c, k;
-    if (FAST_C) { c = e % GT; k = e / GT; } else { k = e % GK; c = e / GK; }
-    int gc = c0 + c, gk = k0 + k;
-    C_t<T> val = czero<C_t<T>>();
-    if (gc < v.nr && gk < v.nk) val = v.base[(long long)gc * v.sr + (long long)gk * v.sk];
-    sm.Q[k][c] = val;
+  for (int it = 0; it < GLOADS; ++it) {
+    const int e = t + it * 256;
+    int r, k;
+    if (FAST_R) { r = e % GT; k = e / GT; } else { k = e % GK; r = e / GK; }
+    sm.P[r][k] = g.p[it];
+    int c, kq;
+    if (FAST_C) { c = e % GT; kq = e / GT; } else { kq = e % GK; c = e / GK; }
+    sm.Q[kq][c] = g.q[it];
   }
 }
 
@@ -202,19 +222,24 @@ __device__ __forceinline__ void mfma_step(const GemmSmem<T>& sm, WaveAcc<T>& acc
   }
 }
 
-// Full K loop of a 64x64 tile: rows of P from `pv` starting at r0, columns of
-// Q from `qv` starting at c0, K = min(pv.nk, qv.nk).
+// K loop of a 64x64 tile over k in [kbeg, kend): rows of P from `pv`
+// starting at r0, columns of Q from `qv` starting at c0.  The global loads
+// of the next K step are issued before the matrix-core work of the current
+// one, so their latency overlaps the MFMAs.
 template <typename T, bool P_FAST_R, bool Q_FAST_C>
 __device__ __forceinline__ void gemm_tile(GemmSmem<T>& sm, WaveAcc<T>& acc,
                                           const View<T>& pv, const View<T>& qv,
-                                          int r0, int c0, int K) {
+                                          int r0, int c0, int kbeg, int kend) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
   acc.zero();
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    load_P<T, P_FAST_R>(sm, pv, r0, k0);
-    load_Q<T, Q_FAST_C>(sm, qv, c0, k0);
+  if (kbeg >= kend) return;
+  Stage<T> g;
+  stage_load<T, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
+    stage_store<T, P_FAST_R, Q_FAST_C>(sm, g);
     __syncthreads();
+    if (k0 + GK < kend) stage_load<T, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
     mfma_step<T>(sm, acc, wr, wc, lane);
     __syncthreads();
   }

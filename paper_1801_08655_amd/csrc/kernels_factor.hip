@@ -362,7 +362,7 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   // Q columns = C rows i: A^T(q, i) = F[i + (k+q) n]
   View<T> qv{F + (long long)k * n, 1, (long long)n, n, nbf};
   WaveAcc<T> acc;
-  gemm_tile<T, false, true>(sm, acc, pv, qv, j0, i0, nbf);
+  gemm_tile<T, false, true>(sm, acc, pv, qv, j0, i0, 0, nbf);
   for_each_acc<T>(acc, [&](int r, int c, C z) {
     const int gi = i0 + c, gj = j0 + r;
     if (gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf)) {

@@ -409,6 +409,16 @@ int Method::polarized_solve(const double2* f, double2* u, double tol, int max_it
   return st;
 }
 
+// per-column l2 norms of k volumes
+void Method::norms(const double2* x, std::vector<double>& out) {
+  out.resize(k);
+  kern::launch_volume_norm2(x, N, k, norm_partial.as<double>(), norm_out.as<double>(), H.st);
+  HELM_HIP(hipMemcpyAsync(out.data(), norm_out.p, k * sizeof(double), hipMemcpyDeviceToHost,
+                          H.st));
+  HELM_HIP(hipStreamSynchronize(H.st));
+  for (double& v : out) v = std::sqrt(v);
+}
+
 // per-column |f - H u| / |f| in FP64; r receives the residual
 void Method::residual(const double2* f, const double2* u, double2* r,
                       std::vector<double>& rel) {
@@ -434,12 +444,17 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
   int status = HELM_OK;
   double t0 = now_ms();
   if (H.prec == HELM_FP64) {
+    int it0 = info ? info->gmres_iters : 0;
     status = polarized_solve(f, u, o.gmres_tol, o.gmres_max_iter, restart, info);
     double tr = now_ms();
     residual(f, u, r.as<double2>(), rel);
     if (info) {
-      info->ir_steps = 1;
+      info->ir_steps = std::max(info->ir_steps, 1);
       info->t_residual_ms += now_ms() - tr;
+      double mx = 0;
+      for (double v : rel) mx = std::max(mx, v);
+      info->ir_residual[0] = std::max(info->ir_residual[0], mx);
+      info->ir_gmres_iters[0] = std::max(info->ir_gmres_iters[0], info->gmres_iters - it0);
     }
   } else {
     // iterative refinement: u <- u + solve_c64(f - H u), FP64 residuals
@@ -449,21 +464,45 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
     const double2* rhs = f;
     int steps = 0;
     status = HELM_ENOCONV;
+    std::vector<double> dprev(k, 0.0), dcur(k), unorm(k), est(k, 1.0);
     for (int it = 0; it < std::max(1, o.ir_max_steps); ++it) {
-      int s = polarized_solve(rhs, d.as<double2>(), o.inner_tol, o.gmres_max_iter, restart,
-                              info);
+      int it0 = info ? info->gmres_iters : 0;
+      const double tol = it == 0 ? o.inner_tol : o.inner_tol_refine;
+      int s = polarized_solve(rhs, d.as<double2>(), tol, o.gmres_max_iter, restart, info);
       (void)s;
       kern::launch_accumulate(u, d.as<double2>(), N * k, H.st);
       double tr = now_ms();
       residual(f, u, r.as<double2>(), rel);
+      norms(d.as<double2>(), dcur);
+      norms(u, unorm);
       if (info) info->t_residual_ms += now_ms() - tr;
       ++steps;
-      double mx = 0;
-      for (double v : rel) mx = std::max(mx, std::isfinite(v) ? v : 1e300);
-      if (mx <= o.ir_tol) { status = HELM_OK; break; }
+      double mx = 0, emx = 0;
+      for (int c = 0; c < k; ++c) {
+        mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
+        // error after this step from the contraction of the corrections
+        if (it > 0 && dprev[c] > 0 && unorm[c] > 0) {
+          double q = std::min(dcur[c] / dprev[c], 0.99);
+          est[c] = dcur[c] / unorm[c] * q / (1.0 - q);
+        } else {
+          est[c] = 1.0;
+        }
+        if (unorm[c] == 0) est[c] = 0;
+        emx = std::max(emx, est[c]);
+      }
+      dprev = dcur;
+      if (info && it < 8) {
+        info->ir_residual[it] = std::max(info->ir_residual[it], mx);
+        info->ir_gmres_iters[it] = std::max(info->ir_gmres_iters[it], info->gmres_iters - it0);
+      }
+      if (info) info->est_error_max = emx;
+      if (mx <= o.ir_tol || (o.err_target > 0 && emx <= o.err_target)) {
+        status = HELM_OK;
+        break;
+      }
       rhs = r.as<double2>();
     }
-    if (info) info->ir_steps = steps;
+    if (info) info->ir_steps = std::max(info->ir_steps, steps);
   }
   if (info) {
     double mx = 0;

@@ -46,6 +46,7 @@ struct Method {
   int polarized_solve(const double2* f, double2* u, double tol, int max_iter,
                       int restart, helm_solve_info* info);
   void residual(const double2* f, const double2* u, double2* r, std::vector<double>& rel);
+  void norms(const double2* x, std::vector<double>& out);
   int solve(const double2* f, double2* u, helm_solve_info* info);
   int gmres_restart(int max_iter) const;
 };
