@@ -445,7 +445,7 @@ void Handle::ensure_workspace(int k) {
   for (int l = 0; l < L; ++l) {
     const LayerPlan& P = G.layers[l];
     X.emplace_back(new DevMem); X.back()->alloc((size_t)P.n_loc * k * elem);
-    Wt.emplace_back(new DevMem); Wt.back()->alloc(std::max<size_t>(P.wt_rows, 1) * k * elem);
+    Wt.emplace_back(new DevMem); Wt.back()->alloc((size_t)P.n_loc * k * elem);
     Ub0.emplace_back(new DevMem); Ub0.back()->alloc(std::max<size_t>(P.ub_rows[0], 1) * k * elem);
     Ub1.emplace_back(new DevMem); Ub1.back()->alloc(std::max<size_t>(P.ub_rows[1], 1) * k * elem);
     layers_h[l].X = X[l]->p;
@@ -486,41 +486,74 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
       if (d <= G.layers[l].max_depth)
         for (int q : G.layers[l].by_depth[d]) ids.push_back(front_base[l] + q);
     const size_t n = ids.size();
-    long long tf = 0, tb = 0;
-    for (int f : ids) {
-      tf += tiles64(fronts_h[f].s + fronts_h[f].b);
-      tb += fronts_h[f].b > 0 ? tiles64(fronts_h[f].s) : 0;
-    }
+    // backward: every front; K (boundary) split when the depth has few tiles
+    long long tb = 0;
+    for (int f : ids) tb += tiles64(fronts_h[f].s);
     std::vector<SolveTask> tasks(n);
-    std::vector<int> pSB(n + 1, 0), pF(n + 1, 0), pBw(n + 1, 0), rF(n + 1, 0), rB(n + 1, 0);
-    long long scr_f = 0, scr_b = 0;
+    std::vector<int> pBw(n + 1, 0), rB(n + 1, 0);
+    long long scr_b = 0;
     for (size_t a = 0; a < n; ++a) {
       const FrontDev& F = fronts_h[ids[a]];
       SolveTask& t = tasks[a];
-      split(tf, F.s, t.nch_f, t.kc_f);
+      t.nch_f = 1;
+      t.kc_f = 16;
+      t.scr_f = 0;
       split(tb, F.b, t.nch_b, t.kc_b);
-      t.scr_f = scr_f;
       t.scr_b = scr_b;
-      if (t.nch_f > 1) scr_f += (long long)t.nch_f * (F.s + F.b);
       if (t.nch_b > 1) scr_b += (long long)t.nch_b * F.s;
       D->sum_s += F.s;
       D->sum_b += F.b;
       D->sum_sbs += (double)(F.s + F.b) * F.s;
       D->sum_bs += (double)F.b * F.s;
-      pSB[a + 1] = pSB[a] + tiles64(F.s + F.b);
-      pF[a + 1] = pF[a] + tiles64(F.s + F.b) * t.nch_f;
-      pBw[a + 1] = pBw[a] + (F.b > 0 ? tiles64(F.s) * t.nch_b : 0);
-      rF[a + 1] = rF[a] + (t.nch_f > 1 ? tiles64(F.s + F.b) : 0);
+      pBw[a + 1] = pBw[a] + tiles64(F.s) * t.nch_b;
       rB[a + 1] = rB[a] + (t.nch_b > 1 ? tiles64(F.s) : 0);
     }
+    // forward: every front takes the GEMM; only fronts with children need
+    // the extend-add gather (leaves read their pivots straight from X)
+    std::vector<int> idsS, idsL;   // S: fronts with children (gather), L: all
+    for (int f : ids) {
+      const FrontDev& F = fronts_h[f];
+      const double sbs = (double)(F.s + F.b) * F.s;
+      idsL.push_back(f);
+      D->fl_s += F.s; D->fl_b += F.b; D->fl_sbs += sbs;
+      if (F.child[0] >= 0 || F.child[1] >= 0) {
+        idsS.push_back(f);
+        D->fs_s += F.s; D->fs_b += F.b;
+      }
+    }
+    const size_t nl = idsL.size(), ng = idsS.size();
+    long long tf = 0;
+    for (int f : idsL) tf += tiles64(fronts_h[f].s + fronts_h[f].b);
+    std::vector<SolveTask> tasksL(nl);
+    std::vector<int> pSB(ng + 1, 0), pF(nl + 1, 0), rF(nl + 1, 0);
+    for (size_t a = 0; a < ng; ++a)
+      pSB[a + 1] = pSB[a] + tiles64(fronts_h[idsS[a]].s + fronts_h[idsS[a]].b);
+    long long scr_f = 0;
+    for (size_t a = 0; a < nl; ++a) {
+      const FrontDev& F = fronts_h[idsL[a]];
+      SolveTask& t = tasksL[a];
+      split(tf, F.s, t.nch_f, t.kc_f);
+      t.nch_b = 1;
+      t.kc_b = 16;
+      t.scr_b = 0;
+      t.scr_f = scr_f;
+      if (t.nch_f > 1) scr_f += (long long)t.nch_f * (F.s + F.b);
+      pF[a + 1] = pF[a] + tiles64(F.s + F.b) * t.nch_f;
+      rF[a + 1] = rF[a] + (t.nch_f > 1 ? tiles64(F.s + F.b) : 0);
+    }
     D->n = (int)n;
+    D->nS = (int)idsS.size();
+    D->nL = (int)nl;
     upload(D->ids, ids, st);
     upload(D->tasks, tasks, st);
+    upload(D->pBw, pBw, st);
+    upload(D->rB, rB, st);
+    upload(D->idsS, idsS, st);
+    upload(D->idsL, idsL, st);
+    upload(D->tasksL, tasksL, st);
     upload(D->pSB, pSB, st);
     upload(D->pF, pF, st);
-    upload(D->pBw, pBw, st);
     upload(D->rF, rF, st);
-    upload(D->rB, rB, st);
     D->tSB = pSB.back();
     D->tF = pF.back();
     D->tBw = pBw.back();
@@ -562,19 +595,27 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
   for (int d = set.max_depth; d >= 0; --d) {
     const DepthList& D = *set.depth[d];
     if (D.n == 0) continue;
-    const int* ids = D.ids.as<int>();
-    const SolveTask* tk = D.tasks.as<SolveTask>();
-    hipEvent_t a = prof_begin();
-    kern::launch_fwd_gather<T>(fr, ids, D.n, D.pSB.as<int>(), D.tSB, ld, k, st);
-    prof_end(K_FWD_GATHER, a, 0, 2.0 * (D.sum_s + D.sum_b) * kk * e);
-    a = prof_begin();
-    kern::launch_fwd_gemm<T>(fr, ids, tk, D.n, D.pF.as<int>(), D.tF, ld, k, scr, st);
-    prof_end(K_FWD_GEMM, a, 8.0 * D.sum_sbs * kk,
-             D.sum_sbs * e + (2.0 * D.sum_s + 2.0 * D.sum_b) * kk * e);
-    if (D.tRF > 0) {
+    hipEvent_t a = nullptr;
+    if (D.nS > 0) {
       a = prof_begin();
-      kern::launch_fwd_reduce<T>(fr, ids, tk, D.n, D.rF.as<int>(), D.tRF, ld, k, scr, st);
-      prof_end(K_FWD_REDUCE, a, 0, 0);
+      kern::launch_fwd_gather<T>(fr, D.idsS.as<int>(), D.nS, D.pSB.as<int>(), D.tSB, ld, k,
+                                 st);
+      prof_end(K_FWD_GATHER, a, 0, 3.0 * (D.fs_s + D.fs_b) * kk * e);
+    }
+    if (D.nL > 0) {
+      const int* ids = D.idsL.as<int>();
+      const SolveTask* tk = D.tasksL.as<SolveTask>();
+      a = prof_begin();
+      kern::launch_fwd_gemm<T>(fr, ids, tk, D.nL, D.pF.as<int>(), D.tF, ld, k, scr, st);
+      // factor block read once; pivots read, Z written, boundary updates
+      // written (and read for fronts with children)
+      prof_end(K_FWD_GEMM, a, 8.0 * D.fl_sbs * kk,
+               D.fl_sbs * e + (2.0 * D.fl_s + D.fl_b + D.fs_b) * kk * e);
+      if (D.tRF > 0) {
+        a = prof_begin();
+        kern::launch_fwd_reduce<T>(fr, ids, tk, D.nL, D.rF.as<int>(), D.tRF, ld, k, scr, st);
+        prof_end(K_FWD_REDUCE, a, 0, 0);
+      }
     }
   }
   for (int d = 0; d <= set.max_depth; ++d) {
@@ -584,6 +625,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin();
     kern::launch_bwd_gemm<T>(fr, ids, tk, D.n, D.pBw.as<int>(), D.tBw, ld, k, scr, st);
+    // factor block read once; X(B) rows read, Z(S) read, X(S) written
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
     if (D.tRB > 0) {

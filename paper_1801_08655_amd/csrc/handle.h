@@ -26,19 +26,26 @@ struct DevMem {
 // Fronts of one depth over a set of layers, for the substitutions.
 struct DepthList {
   int n = 0;
-  DevMem ids;                 // global front ids
+  DevMem ids;                 // global front ids (backward: all fronts)
   DevMem tasks;               // SolveTask per front (K splits, scratch offsets)
-  DevMem pSB;                 // prefix of 64-row tiles of s+b (forward gather)
-  DevMem pF, pBw;             // prefix of GEMM tiles incl. K chunks (fwd, bwd)
-  DevMem rF, rB;              // prefix of 64-row reduce tiles of split fronts
+  DevMem pBw, rB;             // backward GEMM tiles incl. K chunks; reduce tiles
+  int nS = 0;                 // forward: fronts with children (extend-add gather)
+  DevMem idsS;
+  int nL = 0;                 // forward: every front (GEMM)
+  DevMem idsL, tasksL;
+  DevMem pSB;                 // prefix of 64-row tiles of s+b of the gathered fronts
+  DevMem pF, rF;              // forward GEMM tiles incl. K chunks; reduce tiles
   int tSB = 0, tF = 0, tBw = 0, tRF = 0, tRB = 0;
-  double sum_s = 0, sum_b = 0, sum_sbs = 0, sum_bs = 0;  // work counts
+  double sum_s = 0, sum_b = 0, sum_sbs = 0, sum_bs = 0;  // work counts, all fronts
+  double fs_s = 0, fs_b = 0, fs_sbs = 0;    // fronts with children
+  double fl_s = 0, fl_b = 0, fl_sbs = 0;    // all fronts (forward GEMM)
   long long scratch_rows = 0;
 };
 
 // Kernel classes timed with HIP events when HELM_FLAG_PROFILE is set.
 enum KClass {
-  K_FWD_GATHER, K_FWD_GEMM, K_FWD_REDUCE, K_BWD_GEMM, K_BWD_REDUCE, K_SWEEP_GEMM, K_PANEL,
+  K_FWD_GATHER, K_FWD_GEMM, K_FWD_REDUCE, K_BWD_GEMM, K_BWD_REDUCE,
+  K_SWEEP_GEMM, K_PANEL,
   K_SWAP_JO, K_UPDATE_OJ, K_EXTEND_ADD, K_ORIG, K_STORE, K_NCLASS
 };
 struct KStat {

@@ -192,8 +192,8 @@ template <typename T> struct WaveAcc {
 // rows of P are read as [re, im, re, im] along k and columns of Q as
 // [re, -im, ...] (real part) and [im, re, ...] (imaginary part).
 template <typename T>
-__device__ __forceinline__ void mfma_step(const GemmSmem<T>& sm, WaveAcc<T>& acc,
-                                          int wr, int wc, int lane) {
+__device__ __forceinline__ void mfma_step_q(const GemmSmem<T>& sm, const C_t<T> (*Q)[GT + 1],
+                                            WaveAcc<T>& acc, int wr, int wc, int lane) {
   const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
   for (int p = 0; p < GK / 2; ++p) {
@@ -208,7 +208,7 @@ __device__ __forceinline__ void mfma_step(const GemmSmem<T>& sm, WaveAcc<T>& acc
     T bre[2], bim[2];
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn) {
-      C_t<T> y = sm.Q[kc][wc * 32 + bn * 16 + li];
+      C_t<T> y = Q[kc][wc * 32 + bn * 16 + li];
       bre[bn] = imag_part ? -y.y : y.x;
       bim[bn] = imag_part ? y.x : y.y;
     }
@@ -220,6 +220,12 @@ __device__ __forceinline__ void mfma_step(const GemmSmem<T>& sm, WaveAcc<T>& acc
         acc.im[bm][bn] = Mfma<T>::op(a[bm], bim[bn], acc.im[bm][bn]);
       }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void mfma_step(const GemmSmem<T>& sm, WaveAcc<T>& acc,
+                                          int wr, int wc, int lane) {
+  mfma_step_q<T>(sm, sm.Q, acc, wr, wc, lane);
 }
 
 // K loop of a 64x64 tile over k in [kbeg, kend): rows of P from `pv`

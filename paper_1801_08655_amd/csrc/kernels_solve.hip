@@ -2,11 +2,13 @@
 // local solve (H^l)^-1 of Algorithms 2-10).
 //
 // With the stored blocks [F11^-1; -F21 F11^-1] of every front:
-//   forward (leaves -> root):  w = [X(S) + children; children] (extend-add of
-//     the children's updates), X(S) <- F11^-1 w_S, update_B <- w_B - F21 F11^-1 w_S
-//   backward (root -> leaves): X(S) <- X(S) + (-F21 F11^-1)^T X(B)
-// Both passes are dense complex GEMMs with the RHS columns as N; the solve
-// vector X is stored in nested-dissection order with the columns fastest.
+//   forward (leaves -> root): X(S) += children's updates (extend-add, in
+//     place; leaves have none), Z(S) <- F11^-1 X(S),
+//     update_B <- children's updates - F21 F11^-1 X(S)
+//   backward (root -> leaves): X(S) <- Z(S) + (-F21 F11^-1)^T X(B)
+// Both passes are dense complex GEMMs with the RHS columns as N.  X (the
+// solve vector) and Z are stored in nested-dissection order with the columns
+// fastest; update_B lives in a per-depth-parity buffer.
 #include "kernels.h"
 #include "kernels_common.h"
 
@@ -20,8 +22,9 @@ __device__ __forceinline__ C_t<T>* ub_ptr(const LayerDev& L, int parity) {
   return reinterpret_cast<C_t<T>*>(L.Ub[parity]);
 }
 
-// forward, step 1: gather the pivots' right-hand side plus the children's
-// updates into Wt (pivot rows) and Ub (boundary rows).
+// forward, step 1 (fronts with children): extend-add of the children's
+// updates, into X(S) in place for the pivot rows and into Ub for the
+// boundary rows.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
@@ -33,8 +36,7 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
   const int r0 = (blockIdx.x - prefix[a]) * GT;
-  const C* X = reinterpret_cast<const C*>(L.X);
-  C* Wt = reinterpret_cast<C*>(L.Wt);
+  C* X = reinterpret_cast<C*>(L.X);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   const C* Uc = ub_ptr<T>(L, f.ub_parity ^ 1);
   long long cub[2] = {0, 0};
@@ -45,17 +47,24 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       inv[slot] = L.inv + f.inv[slot];
     }
   const int rows = (n - r0) < GT ? (n - r0) : GT;
-  for (int e = threadIdx.x; e < rows * k; e += 256) {
-    const int rr = r0 + e / k, c = e % k;
-    C v = rr < f.s ? X[(long long)(f.off + rr) * k + c] : czero<C>();
+  const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
+  for (int rr = r0 + ty; rr < r0 + rows; rr += 256 / GT) {
+    int q[2] = {-1, -1};
 #pragma unroll
     for (int slot = 0; slot < 2; ++slot)
-      if (inv[slot]) {
-        int q = inv[slot][rr];
-        if (q >= 0) v = cadd(v, Uc[(cub[slot] + q) * k + c]);
+      if (inv[slot]) q[slot] = inv[slot][rr];
+    for (int c = tx; c < k; c += GT) {
+      C v = czero<C>();
+#pragma unroll
+      for (int slot = 0; slot < 2; ++slot)
+        if (q[slot] >= 0) v = cadd(v, Uc[(cub[slot] + q[slot]) * k + c]);
+      if (rr < f.s) {
+        C& x = X[(long long)(f.off + rr) * k + c];
+        x = cadd(x, v);
+      } else {
+        Uo[(f.ub + rr - f.s) * k + c] = v;
       }
-    if (rr < f.s) Wt[(f.wt + rr) * k + c] = v;
-    else Uo[(f.ub + rr - f.s) * k + c] = v;
+    }
   }
 }
 
@@ -81,24 +90,26 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int kb = chunk * tk.kc_f;
   const int ke = min(f.s, kb + tk.kc_f);
   const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
-  // P = FT (col-major, rows m), Q = Wt (rows = pivots, columns = RHS)
+  // P = FT (col-major, rows m), Q = X(S) (rows = pivots, columns = RHS)
+  const C* X = reinterpret_cast<const C*>(L.X);
   View<T> pv{FT, 1, (long long)n, n, f.s};
-  View<T> qv{reinterpret_cast<const C*>(L.Wt) + f.wt * k, 1, (long long)k, k, f.s};
+  View<T> qv{X + (long long)f.off * k, 1, (long long)k, k, f.s};
   WaveAcc<T> acc;
   gemm_tile<T, true, true>(sm, acc, pv, qv, m0, n0, kb, ke);
-  C* X = reinterpret_cast<C*>(L.X);
+  C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   C* S = reinterpret_cast<C*>(scratch);
+  const bool has_children = f.child[0] >= 0 || f.child[1] >= 0;
   for_each_acc<T>(acc, [&](int r, int c, C z) {
     const int gm = m0 + r, gc = n0 + c;
     if (gm >= n || gc >= k) return;
     if (tk.nch_f > 1) {
       S[(tk.scr_f + (long long)chunk * n + gm) * k + gc] = z;
     } else if (gm < f.s) {
-      X[(long long)(f.off + gm) * k + gc] = z;
+      Z[(long long)(f.off + gm) * k + gc] = z;
     } else {
       C& u = Uo[(f.ub + gm - f.s) * k + gc];
-      u = cadd(u, z);
+      u = has_children ? cadd(u, z) : z;
     }
   });
 }
@@ -118,24 +129,26 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int r0 = (blockIdx.x - prefix[a]) * GT;
   const int rows = min(GT, n - r0);
   const C* S = reinterpret_cast<const C*>(scratch);
-  C* X = reinterpret_cast<C*>(L.X);
+  C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
+  const bool has_children = f.child[0] >= 0 || f.child[1] >= 0;
   for (int e = threadIdx.x; e < rows * k; e += 256) {
     const int gm = r0 + e / k, gc = e % k;
     C z = czero<C>();
     for (int ch = 0; ch < tk.nch_f; ++ch)
       z = cadd(z, S[(tk.scr_f + (long long)ch * n + gm) * k + gc]);
     if (gm < f.s) {
-      X[(long long)(f.off + gm) * k + gc] = z;
+      Z[(long long)(f.off + gm) * k + gc] = z;
     } else {
       C& u = Uo[(f.ub + gm - f.s) * k + gc];
-      u = cadd(u, z);
+      u = has_children ? cadd(u, z) : z;
     }
   }
 }
 
-// backward: X(S) += (-F21 F11^-1)^T X(B); X(B) is read in place through the
-// front's boundary index list, the K (boundary) dimension optionally split.
+// backward: X(S) = Z(S) + (-F21 F11^-1)^T X(B); X(B) is read in place
+// through the front's boundary index list, the K (boundary) dimension
+// optionally split.  Fronts without boundary (roots) just copy Z(S).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
@@ -164,15 +177,13 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   WaveAcc<T> acc;
   gemm_tile<T, false, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   C* S = reinterpret_cast<C*>(scratch);
+  const C* Z = reinterpret_cast<const C*>(L.Wt);
   for_each_acc<T>(acc, [&](int r, int c, C z) {
     const int gm = m0 + r, gc = n0 + c;
     if (gm >= f.s || gc >= k) return;
-    if (tk.nch_b > 1) {
-      S[(tk.scr_b + (long long)chunk * f.s + gm) * k + gc] = z;
-    } else {
-      C& x = X[(long long)(f.off + gm) * k + gc];
-      x = cadd(x, z);
-    }
+    const long long idx = (long long)(f.off + gm) * k + gc;
+    if (tk.nch_b > 1) S[(tk.scr_b + (long long)chunk * f.s + gm) * k + gc] = z;
+    else X[idx] = cadd(Z[idx], z);
   });
 }
 
@@ -190,13 +201,14 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int rows = min(GT, f.s - r0);
   const C* S = reinterpret_cast<const C*>(scratch);
   C* X = reinterpret_cast<C*>(L.X);
+  const C* Z = reinterpret_cast<const C*>(L.Wt);
   for (int e = threadIdx.x; e < rows * k; e += 256) {
     const int gm = r0 + e / k, gc = e % k;
-    C z = czero<C>();
+    const long long idx = (long long)(f.off + gm) * k + gc;
+    C z = Z[idx];
     for (int ch = 0; ch < tk.nch_b; ++ch)
       z = cadd(z, S[(tk.scr_b + (long long)ch * f.s + gm) * k + gc]);
-    C& x = X[(long long)(f.off + gm) * k + gc];
-    x = cadd(x, z);
+    X[idx] = z;
   }
 }
 

@@ -150,3 +150,39 @@ def test_single_layer_equals_global_solve():
     s = pt.Solver(m, h, om, p, 1, precision="fp64", pml_C=25.0)
     u = s.solve(torch.from_numpy(F.T.reshape(2, n, n, n).copy()).cuda()).cpu().numpy()
     assert relative_error(u.reshape(2, -1).T, ref).max() <= 1e-11
+
+
+def test_layer_solve_wide_batch(homog):
+    """k = 70 columns: more than one 64-column tile in every substitution."""
+    wl, pb, _ = homog
+    s = _solver(wl, "fp64")
+    nx, ny, nz = wl.n
+    l = 1
+    _, _, lo, hi = s.layer_info(l)
+    t = hi - lo + 1
+    r = _rand((70, t, ny, nx), 3)
+    w = s.layer_solve(l, torch.from_numpy(r).cuda()).cpu().numpy()
+    Hl = local_operator(pb, wl.n_layers, wl.pml_local, l)
+    ref = SparseLU(Hl).solve(r.reshape(70, -1).T).T
+    assert relative_error(w.reshape(70, -1).T, ref.T).max() <= 1e-11
+
+
+def test_batches_wider_than_max_rhs_are_chunked():
+    """5 sources with max_rhs = 3: two internal batches, same results."""
+    wl = workload("smooth-24")
+    pb = _problem(wl)
+    srcs = [(8, 9, 7), (12, 12, 12), (15, 7, 16), (6, 14, 10), (11, 11, 6)]
+    ref = SparseLU(pb.operator()).solve(point_source_rhs(pb.shape, srcs, wl.h))
+    s = _solver(wl, "fp64", max_rhs=3)
+    u = s.solve_points(srcs).cpu().numpy().reshape(len(srcs), -1).T
+    assert relative_error(u, ref).max() <= 1e-9
+
+
+def test_batch_composition_does_not_change_results():
+    """A column solved alone and inside a batch agree to rounding."""
+    wl = workload("layered-28")
+    s = _solver(wl, "fp64")
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12)]
+    alone = s.solve_points(srcs[1:2]).cpu().numpy()
+    mixed = s.solve_points(srcs).cpu().numpy()[1:2]
+    assert relative_error(mixed.reshape(1, -1).T, alone.reshape(1, -1).T)[0] <= 1e-10
