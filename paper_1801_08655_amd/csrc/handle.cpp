@@ -43,6 +43,8 @@ std::vector<double2> to_d2(const std::vector<cd>& v) {
 }
 
 int tiles64(long long n) { return (int)((n + 63) / 64); }
+int tiles128(long long n) { return (int)((n + 127) / 128); }
+int tiles16(long long n) { return (int)((n + 15) / 16); }
 
 }  // namespace
 
@@ -486,9 +488,16 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
       if (d <= G.layers[l].max_depth)
         for (int q : G.layers[l].by_depth[d]) ids.push_back(front_base[l] + q);
     const size_t n = ids.size();
-    // backward: every front; K (boundary) split when the depth has few tiles
+    // backward: every front; a 32-row tile when the pivot blocks are small,
+    // K (boundary) split when the depth has few tiles
+    double mean_s = 0;
+    for (int f : ids) mean_s += fronts_h[f].s;
+    mean_s /= std::max<size_t>(n, 1);
+    const int bm = mean_s <= 40 ? 32 : 64;
+    D->bwd_bm = bm;
+    auto tilesB = [&](int s_) { return (s_ + bm - 1) / bm; };
     long long tb = 0;
-    for (int f : ids) tb += tiles64(fronts_h[f].s);
+    for (int f : ids) tb += tilesB(fronts_h[f].s);
     std::vector<SolveTask> tasks(n);
     std::vector<int> pBw(n + 1, 0), rB(n + 1, 0);
     long long scr_b = 0;
@@ -505,8 +514,8 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
       D->sum_b += F.b;
       D->sum_sbs += (double)(F.s + F.b) * F.s;
       D->sum_bs += (double)F.b * F.s;
-      pBw[a + 1] = pBw[a] + tiles64(F.s) * t.nch_b;
-      rB[a + 1] = rB[a] + (t.nch_b > 1 ? tiles64(F.s) : 0);
+      pBw[a + 1] = pBw[a] + tilesB(F.s) * t.nch_b;
+      rB[a + 1] = rB[a] + (t.nch_b > 1 ? tiles16(F.s) : 0);
     }
     // forward: every front takes the GEMM; only fronts with children need
     // the extend-add gather (leaves read their pivots straight from X)
@@ -526,8 +535,7 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
     for (int f : idsL) tf += tiles64(fronts_h[f].s + fronts_h[f].b);
     std::vector<SolveTask> tasksL(nl);
     std::vector<int> pSB(ng + 1, 0), pF(nl + 1, 0), rF(nl + 1, 0);
-    for (size_t a = 0; a < ng; ++a)
-      pSB[a + 1] = pSB[a] + tiles64(fronts_h[idsS[a]].s + fronts_h[idsS[a]].b);
+    for (size_t a = 0; a < ng; ++a) pSB[a + 1] = pSB[a] + tiles16(fronts_h[idsS[a]].s);
     long long scr_f = 0;
     for (size_t a = 0; a < nl; ++a) {
       const FrontDev& F = fronts_h[idsL[a]];
@@ -539,7 +547,7 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
       t.scr_f = scr_f;
       if (t.nch_f > 1) scr_f += (long long)t.nch_f * (F.s + F.b);
       pF[a + 1] = pF[a] + tiles64(F.s + F.b) * t.nch_f;
-      rF[a + 1] = rF[a] + (t.nch_f > 1 ? tiles64(F.s + F.b) : 0);
+      rF[a + 1] = rF[a] + (t.nch_f > 1 ? tiles16(F.s + F.b) : 0);
     }
     D->n = (int)n;
     D->nS = (int)idsS.size();
@@ -600,7 +608,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
       a = prof_begin();
       kern::launch_fwd_gather<T>(fr, D.idsS.as<int>(), D.nS, D.pSB.as<int>(), D.tSB, ld, k,
                                  st);
-      prof_end(K_FWD_GATHER, a, 0, 3.0 * (D.fs_s + D.fs_b) * kk * e);
+      prof_end(K_FWD_GATHER, a, 0, 3.0 * D.fs_s * kk * e);
     }
     if (D.nL > 0) {
       const int* ids = D.idsL.as<int>();
@@ -608,7 +616,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
       a = prof_begin();
       kern::launch_fwd_gemm<T>(fr, ids, tk, D.nL, D.pF.as<int>(), D.tF, ld, k, scr, st);
       // factor block read once; pivots read, Z written, boundary updates
-      // written (and read for fronts with children)
+      // written and the children's updates of the boundary rows read
       prof_end(K_FWD_GEMM, a, 8.0 * D.fl_sbs * kk,
                D.fl_sbs * e + (2.0 * D.fl_s + D.fl_b + D.fs_b) * kk * e);
       if (D.tRF > 0) {
@@ -624,7 +632,8 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     const int* ids = D.ids.as<int>();
     const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin();
-    kern::launch_bwd_gemm<T>(fr, ids, tk, D.n, D.pBw.as<int>(), D.tBw, ld, k, scr, st);
+    kern::launch_bwd_gemm<T>(fr, ids, tk, D.n, D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm,
+                             st);
     // factor block read once; X(B) rows read, Z(S) read, X(S) written
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);

@@ -36,6 +36,7 @@ struct DepthList {
   DevMem pSB;                 // prefix of 64-row tiles of s+b of the gathered fronts
   DevMem pF, rF;              // forward GEMM tiles incl. K chunks; reduce tiles
   int tSB = 0, tF = 0, tBw = 0, tRF = 0, tRB = 0;
+  int bwd_bm = 64;            // row tile of the backward GEMM at this depth
   double sum_s = 0, sum_b = 0, sum_sbs = 0, sum_bs = 0;  // work counts, all fronts
   double fs_s = 0, fs_b = 0, fs_sbs = 0;    // fronts with children
   double fl_s = 0, fl_b = 0, fl_sbs = 0;    // all fronts (forward GEMM)

@@ -62,7 +62,7 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, hipStream_t st);
+                     void* scratch, int bm, hipStream_t st);
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int* prefix, int total, const LayerDev* layers, int k,

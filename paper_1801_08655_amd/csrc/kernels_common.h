@@ -105,14 +105,8 @@ template <> struct Mfma<double> {
 
 constexpr int GT = 64;   // tile edge (complex elements)
 constexpr int GK = 16;   // K step (complex elements)
-
-// Shared-memory staging for one 64x64 complex GEMM tile.
-//   P[r][k]: operand whose rows become the MFMA rows,
-//   Q[k][c]: operand whose columns become the MFMA columns.
-template <typename T> struct GemmSmem {
-  C_t<T> P[GT][GK + 1];
-  C_t<T> Q[GK][GT + 1];
-};
+constexpr int FWD_BM = 64;   // row tile of the forward substitution GEMM
+constexpr int RT = 16;       // row tile of the gather / split-K reduction kernels
 
 // Operand view: element (r, k) at base[r * sr + kk * sk], valid for r < nr,
 // k < nk, with kk = k, or kk = kmap[k] when a row map is given (indirect
@@ -134,53 +128,82 @@ __device__ __forceinline__ C_t<T> view_at(const View<T>& v, int r, int k) {
   return val;
 }
 
-constexpr int GLOADS = (GT * GK) / 256;   // elements per thread per operand tile
-
-// Per-thread staging registers for one K step of both operands.
-template <typename T> struct Stage {
-  C_t<T> p[GLOADS], q[GLOADS];
+// Shared-memory staging of one K step of a BM x 64 complex GEMM tile in the
+// real form of the complex product:
+//   P[r][2k + {0,1}] = (re, im) of the row operand,
+//   Q1[2k][c] = re, Q1[2k+1][c] = -im   (column operand, real part of C),
+//   Q2[2k][c] = im, Q2[2k+1][c] = re    (imaginary part of C),
+// so that every MFMA reads its operands with one load and no arithmetic.
+constexpr int PSTR = 2 * GK + 4;   // row stride of P (padding against bank conflicts)
+constexpr int QSTR = GT + 4;
+template <typename T, int BM> struct GemmSmem {
+  T P[BM][PSTR];
+  T Q1[2 * GK][QSTR];
+  T Q2[2 * GK][QSTR];
 };
 
-// Global loads of the 64 x GK block of P (rows r0.., k0..) and the GK x 64
+// Per-thread staging registers for one K step of both operands.
+template <typename T, int BM> struct Stage {
+  static constexpr int NP = BM * GK / 256, NQ = GT * GK / 256;
+  C_t<T> p[NP], q[NQ];
+};
+
+// Global loads of the BM x GK block of P (rows r0.., k0..) and the GK x 64
 // block of Q (columns c0.., k0..).  FAST_R / FAST_C: consecutive threads walk
 // the rows of P / the columns of Q (the contiguous dimension in memory).
-template <typename T, bool FAST_R, bool FAST_C>
-__device__ __forceinline__ void stage_load(Stage<T>& g, const View<T>& pv, const View<T>& qv,
-                                           int r0, int c0, int k0, int kend) {
+template <typename T, int BM, bool FAST_R, bool FAST_C>
+__device__ __forceinline__ void stage_load(Stage<T, BM>& g, const View<T>& pv,
+                                           const View<T>& qv, int r0, int c0, int k0,
+                                           int kend) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < GLOADS; ++it) {
+  for (int it = 0; it < Stage<T, BM>::NP; ++it) {
     const int e = t + it * 256;
     int r, k;
-    if (FAST_R) { r = e % GT; k = e / GT; } else { k = e % GK; r = e / GK; }
+    if (FAST_R) { r = e % BM; k = e / BM; } else { k = e % GK; r = e / GK; }
     g.p[it] = (k0 + k < kend) ? view_at(pv, r0 + r, k0 + k) : czero<C_t<T>>();
+  }
+#pragma unroll
+  for (int it = 0; it < Stage<T, BM>::NQ; ++it) {
+    const int e = t + it * 256;
     int c, kq;
     if (FAST_C) { c = e % GT; kq = e / GT; } else { kq = e % GK; c = e / GK; }
     g.q[it] = (k0 + kq < kend) ? view_at(qv, c0 + c, k0 + kq) : czero<C_t<T>>();
   }
 }
 
-template <typename T, bool FAST_R, bool FAST_C>
-__device__ __forceinline__ void stage_store(GemmSmem<T>& sm, const Stage<T>& g) {
+template <typename T, int BM, bool FAST_R, bool FAST_C>
+__device__ __forceinline__ void stage_store(GemmSmem<T, BM>& sm, const Stage<T, BM>& g) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < GLOADS; ++it) {
+  for (int it = 0; it < Stage<T, BM>::NP; ++it) {
     const int e = t + it * 256;
     int r, k;
-    if (FAST_R) { r = e % GT; k = e / GT; } else { k = e % GK; r = e / GK; }
-    sm.P[r][k] = g.p[it];
+    if (FAST_R) { r = e % BM; k = e / BM; } else { k = e % GK; r = e / GK; }
+    sm.P[r][2 * k] = g.p[it].x;
+    sm.P[r][2 * k + 1] = g.p[it].y;
+  }
+#pragma unroll
+  for (int it = 0; it < Stage<T, BM>::NQ; ++it) {
+    const int e = t + it * 256;
     int c, kq;
     if (FAST_C) { c = e % GT; kq = e / GT; } else { kq = e % GK; c = e / GK; }
-    sm.Q[kq][c] = g.q[it];
+    const C_t<T> y = g.q[it];
+    sm.Q1[2 * kq][c] = y.x;
+    sm.Q1[2 * kq + 1][c] = -y.y;
+    sm.Q2[2 * kq][c] = y.y;
+    sm.Q2[2 * kq + 1][c] = y.x;
   }
 }
 
-// Accumulators of one wave: a 32x32 complex sub-tile as 2x2 MFMA blocks.
-template <typename T> struct WaveAcc {
-  typename Mfma<T>::v4 re[2][2], im[2][2];
+// Accumulators of one wave: a (BM/2) x 32 complex sub-tile as
+// (BM/32) x 2 MFMA 16x16 blocks.
+template <typename T, int BM> struct WaveAcc {
+  static constexpr int MB = BM / 32;
+  typename Mfma<T>::v4 re[MB][2], im[MB][2];
   __device__ void zero() {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -188,82 +211,72 @@ template <typename T> struct WaveAcc {
   }
 };
 
-// One GK step of MFMAs for this wave.  Real form of the complex product:
-// rows of P are read as [re, im, re, im] along k and columns of Q as
-// [re, -im, ...] (real part) and [im, re, ...] (imaginary part).
-template <typename T>
-__device__ __forceinline__ void mfma_step_q(const GemmSmem<T>& sm, const C_t<T> (*Q)[GT + 1],
-                                            WaveAcc<T>& acc, int wr, int wc, int lane) {
+// One K step (GK complex = 2 GK real) of MFMAs for this wave; lane l supplies
+// A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
+template <typename T, int BM>
+__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM>& sm, WaveAcc<T, BM>& acc,
+                                          int wr, int wc, int lane) {
+  constexpr int MB = BM / 32;
   const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
   for (int p = 0; p < GK / 2; ++p) {
-    const int kc = 2 * p + (lq >> 1);
-    const bool imag_part = lq & 1;
-    T a[2];
+    const int kk = 4 * p + lq;
+    T a[MB], b1[2], b2[2];
 #pragma unroll
-    for (int bm = 0; bm < 2; ++bm) {
-      C_t<T> x = sm.P[wr * 32 + bm * 16 + li][kc];
-      a[bm] = imag_part ? x.y : x.x;
-    }
-    T bre[2], bim[2];
+    for (int bm = 0; bm < MB; ++bm) a[bm] = sm.P[wr * (BM / 2) + bm * 16 + li][kk];
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn) {
-      C_t<T> y = Q[kc][wc * 32 + bn * 16 + li];
-      bre[bn] = imag_part ? -y.y : y.x;
-      bim[bn] = imag_part ? y.x : y.y;
+      b1[bn] = sm.Q1[kk][wc * 32 + bn * 16 + li];
+      b2[bn] = sm.Q2[kk][wc * 32 + bn * 16 + li];
     }
 #pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
+    for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
       for (int bn = 0; bn < 2; ++bn) {
-        acc.re[bm][bn] = Mfma<T>::op(a[bm], bre[bn], acc.re[bm][bn]);
-        acc.im[bm][bn] = Mfma<T>::op(a[bm], bim[bn], acc.im[bm][bn]);
+        acc.re[bm][bn] = Mfma<T>::op(a[bm], b1[bn], acc.re[bm][bn]);
+        acc.im[bm][bn] = Mfma<T>::op(a[bm], b2[bn], acc.im[bm][bn]);
       }
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void mfma_step(const GemmSmem<T>& sm, WaveAcc<T>& acc,
-                                          int wr, int wc, int lane) {
-  mfma_step_q<T>(sm, sm.Q, acc, wr, wc, lane);
-}
-
-// K loop of a 64x64 tile over k in [kbeg, kend): rows of P from `pv`
+// K loop of a BM x 64 tile over k in [kbeg, kend): rows of P from `pv`
 // starting at r0, columns of Q from `qv` starting at c0.  The global loads
 // of the next K step are issued before the matrix-core work of the current
 // one, so their latency overlaps the MFMAs.
-template <typename T, bool P_FAST_R, bool Q_FAST_C>
-__device__ __forceinline__ void gemm_tile(GemmSmem<T>& sm, WaveAcc<T>& acc,
+template <typename T, int BM, bool P_FAST_R, bool Q_FAST_C>
+__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM>& sm, WaveAcc<T, BM>& acc,
                                           const View<T>& pv, const View<T>& qv,
                                           int r0, int c0, int kbeg, int kend) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
   acc.zero();
   if (kbeg >= kend) return;
-  Stage<T> g;
-  stage_load<T, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
+  Stage<T, BM> g;
+  stage_load<T, BM, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
   for (int k0 = kbeg; k0 < kend; k0 += GK) {
-    stage_store<T, P_FAST_R, Q_FAST_C>(sm, g);
+    stage_store<T, BM, P_FAST_R, Q_FAST_C>(sm, g);
     __syncthreads();
-    if (k0 + GK < kend) stage_load<T, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
-    mfma_step<T>(sm, acc, wr, wc, lane);
+    if (k0 + GK < kend)
+      stage_load<T, BM, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
+    mfma_step<T, BM>(sm, acc, wr, wc, lane);
     __syncthreads();
   }
 }
 
-// Visit this lane's outputs: f(r, c, value) with r, c the tile-local MFMA
-// row / column (0..63).
-template <typename T, class F>
-__device__ __forceinline__ void for_each_acc(const WaveAcc<T>& acc, F&& f) {
+// Visit this lane's outputs: f(r, c, value) with r (0..BM-1), c (0..63) the
+// tile-local MFMA row / column.
+template <typename T, int BM, class F>
+__device__ __forceinline__ void for_each_acc(const WaveAcc<T, BM>& acc, F&& f) {
+  constexpr int MB = BM / 32;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
 #pragma unroll
-  for (int bm = 0; bm < 2; ++bm)
+  for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int r = wr * 32 + bm * 16 + Mfma<T>::row(lane, v);
+        int r = wr * (BM / 2) + bm * 16 + Mfma<T>::row(lane, v);
         int c = wc * 32 + bn * 16 + (lane & 15);
         C_t<T> z;
         z.x = acc.re[bm][bn][v];

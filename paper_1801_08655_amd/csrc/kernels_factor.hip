@@ -347,7 +347,7 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              int n_active, const int* __restrict__ prefix, int k, int nb,
              void* ws0, void* ws1) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T> sm;
+  __shared__ GemmSmem<T, 64> sm;
   const int a = find_segment(prefix, n_active, blockIdx.x);
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
@@ -361,9 +361,9 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> pv{F + k, (long long)n, 1, n, nbf};
   // Q columns = C rows i: A^T(q, i) = F[i + (k+q) n]
   View<T> qv{F + (long long)k * n, 1, (long long)n, n, nbf};
-  WaveAcc<T> acc;
-  gemm_tile<T, false, true>(sm, acc, pv, qv, j0, i0, 0, nbf);
-  for_each_acc<T>(acc, [&](int r, int c, C z) {
+  WaveAcc<T, 64> acc;
+  gemm_tile<T, 64, false, true>(sm, acc, pv, qv, j0, i0, 0, nbf);
+  for_each_acc<T, 64>(acc, [&](int r, int c, C z) {
     const int gi = i0 + c, gj = j0 + r;
     if (gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf)) {
       C& e = F[(long long)gi + (long long)gj * n];

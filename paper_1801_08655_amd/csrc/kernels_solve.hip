@@ -22,9 +22,37 @@ __device__ __forceinline__ C_t<T>* ub_ptr(const LayerDev& L, int parity) {
   return reinterpret_cast<C_t<T>*>(L.Ub[parity]);
 }
 
-// forward, step 1 (fronts with children): extend-add of the children's
-// updates, into X(S) in place for the pivot rows and into Ub for the
-// boundary rows.
+// Sum of the children's updates landing on front row `row` (extend-add in
+// pull form through the front-row -> child-boundary maps).
+template <typename T> struct ChildSum {
+  const C_t<T>* Uc;
+  long long cub[2];
+  const int* inv[2];
+  __device__ ChildSum(const FrontDev* fronts, const FrontDev& f, const LayerDev& L) {
+    Uc = reinterpret_cast<const C_t<T>*>(L.Ub[f.ub_parity ^ 1]);
+    for (int slot = 0; slot < 2; ++slot) {
+      cub[slot] = 0;
+      inv[slot] = nullptr;
+      if (f.child[slot] >= 0) {
+        cub[slot] = fronts[f.child[slot]].ub;
+        inv[slot] = L.inv + f.inv[slot];
+      }
+    }
+  }
+  __device__ __forceinline__ C_t<T> operator()(int row, int col, int k) const {
+    C_t<T> v = czero<C_t<T>>();
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot)
+      if (inv[slot]) {
+        const int q = inv[slot][row];
+        if (q >= 0) v = cadd(v, Uc[(cub[slot] + q) * k + col]);
+      }
+    return v;
+  }
+};
+
+// forward, step 1 (fronts with children): X(S) += children's updates on the
+// pivot rows, in place.  The boundary rows are summed in the GEMM epilogue.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
@@ -34,38 +62,16 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int a = find_segment(prefix, n_ids, blockIdx.x);
   const FrontDev f = fronts[ids[a]];
   const LayerDev& L = layers[f.layer];
-  const int n = f.s + f.b;
-  const int r0 = (blockIdx.x - prefix[a]) * GT;
+  const int r0 = (blockIdx.x - prefix[a]) * RT;
   C* X = reinterpret_cast<C*>(L.X);
-  C* Uo = ub_ptr<T>(L, f.ub_parity);
-  const C* Uc = ub_ptr<T>(L, f.ub_parity ^ 1);
-  long long cub[2] = {0, 0};
-  const int* inv[2] = {nullptr, nullptr};
-  for (int slot = 0; slot < 2; ++slot)
-    if (f.child[slot] >= 0) {
-      cub[slot] = fronts[f.child[slot]].ub;
-      inv[slot] = L.inv + f.inv[slot];
-    }
-  const int rows = (n - r0) < GT ? (n - r0) : GT;
+  const ChildSum<T> cs(fronts, f, L);
+  const int rows = (f.s - r0) < RT ? (f.s - r0) : RT;
   const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
-  for (int rr = r0 + ty; rr < r0 + rows; rr += 256 / GT) {
-    int q[2] = {-1, -1};
-#pragma unroll
-    for (int slot = 0; slot < 2; ++slot)
-      if (inv[slot]) q[slot] = inv[slot][rr];
+  for (int rr = r0 + ty; rr < r0 + rows; rr += 256 / GT)
     for (int c = tx; c < k; c += GT) {
-      C v = czero<C>();
-#pragma unroll
-      for (int slot = 0; slot < 2; ++slot)
-        if (q[slot] >= 0) v = cadd(v, Uc[(cub[slot] + q[slot]) * k + c]);
-      if (rr < f.s) {
-        C& x = X[(long long)(f.off + rr) * k + c];
-        x = cadd(x, v);
-      } else {
-        Uo[(f.ub + rr - f.s) * k + c] = v;
-      }
+      C& x = X[(long long)(f.off + rr) * k + c];
+      x = cadd(x, cs(rr, c, k));
     }
-  }
 }
 
 // forward, step 2: [X(S); Ub] = [F11^-1 w_S; Ub - F21 F11^-1 w_S], the K
@@ -76,7 +82,8 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T> sm;
+  constexpr int BM = FWD_BM;
+  __shared__ GemmSmem<T, BM> sm;
   const int ntn = (k + GT - 1) / GT;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int a = find_segment(prefix, n_ids, mt);
@@ -86,7 +93,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int n = f.s + f.b;
   const int local = mt - prefix[a];
   const int chunk = local % tk.nch_f;
-  const int m0 = (local / tk.nch_f) * GT, n0 = nt * GT;
+  const int m0 = (local / tk.nch_f) * BM, n0 = nt * GT;
   const int kb = chunk * tk.kc_f;
   const int ke = min(f.s, kb + tk.kc_f);
   const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
@@ -94,13 +101,13 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* X = reinterpret_cast<const C*>(L.X);
   View<T> pv{FT, 1, (long long)n, n, f.s};
   View<T> qv{X + (long long)f.off * k, 1, (long long)k, k, f.s};
-  WaveAcc<T> acc;
-  gemm_tile<T, true, true>(sm, acc, pv, qv, m0, n0, kb, ke);
+  WaveAcc<T, BM> acc;
+  gemm_tile<T, BM, true, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   C* S = reinterpret_cast<C*>(scratch);
-  const bool has_children = f.child[0] >= 0 || f.child[1] >= 0;
-  for_each_acc<T>(acc, [&](int r, int c, C z) {
+  const ChildSum<T> cs(fronts, f, L);
+  for_each_acc<T, BM>(acc, [&](int r, int c, C z) {
     const int gm = m0 + r, gc = n0 + c;
     if (gm >= n || gc >= k) return;
     if (tk.nch_f > 1) {
@@ -108,8 +115,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     } else if (gm < f.s) {
       Z[(long long)(f.off + gm) * k + gc] = z;
     } else {
-      C& u = Uo[(f.ub + gm - f.s) * k + gc];
-      u = has_children ? cadd(u, z) : z;
+      Uo[(f.ub + gm - f.s) * k + gc] = cadd(z, cs(gm, gc, k));
     }
   });
 }
@@ -126,36 +132,32 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
-  const int r0 = (blockIdx.x - prefix[a]) * GT;
-  const int rows = min(GT, n - r0);
+  const int r0 = (blockIdx.x - prefix[a]) * RT;
+  const int rows = min(RT, n - r0);
   const C* S = reinterpret_cast<const C*>(scratch);
   C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
-  const bool has_children = f.child[0] >= 0 || f.child[1] >= 0;
+  const ChildSum<T> cs(fronts, f, L);
   for (int e = threadIdx.x; e < rows * k; e += 256) {
     const int gm = r0 + e / k, gc = e % k;
     C z = czero<C>();
     for (int ch = 0; ch < tk.nch_f; ++ch)
       z = cadd(z, S[(tk.scr_f + (long long)ch * n + gm) * k + gc]);
-    if (gm < f.s) {
-      Z[(long long)(f.off + gm) * k + gc] = z;
-    } else {
-      C& u = Uo[(f.ub + gm - f.s) * k + gc];
-      u = has_children ? cadd(u, z) : z;
-    }
+    if (gm < f.s) Z[(long long)(f.off + gm) * k + gc] = z;
+    else Uo[(f.ub + gm - f.s) * k + gc] = cadd(z, cs(gm, gc, k));
   }
 }
 
 // backward: X(S) = Z(S) + (-F21 F11^-1)^T X(B); X(B) is read in place
 // through the front's boundary index list, the K (boundary) dimension
 // optionally split.  Fronts without boundary (roots) just copy Z(S).
-template <typename T>
+template <typename T, int BM>
 __global__ void __launch_bounds__(256)
 k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T> sm;
+  __shared__ GemmSmem<T, BM> sm;
   const int ntn = (k + GT - 1) / GT;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int a = find_segment(prefix, n_ids, mt);
@@ -165,7 +167,7 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int n = f.s + f.b;
   const int local = mt - prefix[a];
   const int chunk = local % tk.nch_b;
-  const int m0 = (local / tk.nch_b) * GT, n0 = nt * GT;
+  const int m0 = (local / tk.nch_b) * BM, n0 = nt * GT;
   const int kb = chunk * tk.kc_b;
   const int ke = min(f.b, kb + tk.kc_b);
   const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
@@ -174,11 +176,11 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> pv{FT + f.s, (long long)n, 1, f.s, f.b};
   // Q(c, q) = X[B[q] k + c]
   View<T> qv{X, 1, (long long)k, k, f.b, L.bidx + f.bidx};
-  WaveAcc<T> acc;
-  gemm_tile<T, false, true>(sm, acc, pv, qv, m0, n0, kb, ke);
+  WaveAcc<T, BM> acc;
+  gemm_tile<T, BM, false, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   C* S = reinterpret_cast<C*>(scratch);
   const C* Z = reinterpret_cast<const C*>(L.Wt);
-  for_each_acc<T>(acc, [&](int r, int c, C z) {
+  for_each_acc<T, BM>(acc, [&](int r, int c, C z) {
     const int gm = m0 + r, gc = n0 + c;
     if (gm >= f.s || gc >= k) return;
     const long long idx = (long long)(f.off + gm) * k + gc;
@@ -197,8 +199,8 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
-  const int r0 = (blockIdx.x - prefix[a]) * GT;
-  const int rows = min(GT, f.s - r0);
+  const int r0 = (blockIdx.x - prefix[a]) * RT;
+  const int rows = min(RT, f.s - r0);
   const C* S = reinterpret_cast<const C*>(scratch);
   C* X = reinterpret_cast<C*>(L.X);
   const C* Z = reinterpret_cast<const C*>(L.Wt);
@@ -241,11 +243,15 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, hipStream_t st) {
+                     void* scratch, int bm, hipStream_t st) {
   if (total_tiles <= 0) return;
   const int ntn = (k + GT - 1) / GT;
-  hipLaunchKernelGGL(k_bwd_gemm<T>, dim3(total_tiles * ntn), dim3(256), 0, st, fr, ids,
-                     tasks, n, prefix, layers, k, scratch);
+  if (bm == 32)
+    hipLaunchKernelGGL((k_bwd_gemm<T, 32>), dim3(total_tiles * ntn), dim3(256), 0, st, fr,
+                       ids, tasks, n, prefix, layers, k, scratch);
+  else
+    hipLaunchKernelGGL((k_bwd_gemm<T, 64>), dim3(total_tiles * ntn), dim3(256), 0, st, fr,
+                       ids, tasks, n, prefix, layers, k, scratch);
 }
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
@@ -267,7 +273,7 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                                      const void*, hipStream_t);                      \
   template void launch_bwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int*, int, const LayerDev*, int,       \
-                                   void*, hipStream_t);                              \
+                                   void*, int, hipStream_t);                         \
   template void launch_bwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);
