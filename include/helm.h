@@ -52,6 +52,8 @@ extern "C" {
 /* ---- option flags ------------------------------------------------------ */
 #define HELM_FLAG_PROFILE 1  /* time every substitution / sweep kernel launch with
                                 HIP events on the handle's stream            */
+#define HELM_FLAG_NO_GRAPHS 2 /* launch the substitution kernels one by one
+                                instead of replaying captured HIP graphs     */
 
 /* ---- precision of the local factors ----------------------------------- */
 #define HELM_FP64   0   /* complex128 fronts and substitutions              */

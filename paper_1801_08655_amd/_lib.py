@@ -25,6 +25,7 @@ EXPORTED = [
     "helm_set_solve_options",
 ]
 HELM_FLAG_PROFILE = 1
+HELM_FLAG_NO_GRAPHS = 2
 
 
 class helm_grid(ctypes.Structure):

@@ -48,8 +48,14 @@ int tiles16(long long n) { return (int)((n + 15) / 16); }
 
 }  // namespace
 
+void Handle::clear_graphs() {
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+}
+
 Handle::~Handle() {
   if (st) (void)hipStreamSynchronize(st);
+  clear_graphs();
   for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto e : ev_free) (void)hipEventDestroy(e);
   sets.clear();
@@ -442,6 +448,7 @@ template void Handle::factorize_t<double>();
 void Handle::ensure_workspace(int k) {
   if (k <= kcap) return;
   HELM_HIP(hipStreamSynchronize(st));
+  clear_graphs();
   const int L = G.L;
   X.clear(); Wt.clear(); Ub0.clear(); Ub1.clear();
   for (int l = 0; l < L; ++l) {
@@ -587,9 +594,30 @@ void Handle::solve_layers(const LayerSet& set, int k) {
   size_t need = (size_t)std::max<long long>(set.scratch_rows, 1) * std::max(k, kcap) * elem;
   if (scratch.bytes < need) {
     HELM_HIP(hipStreamSynchronize(st));
+    clear_graphs();
     scratch.alloc(need);
   }
-  if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
+  // The ~35 dependent launches of one multi-RHS solve are captured once per
+  // (layer set, width) into a HIP graph and replayed; the sequence holds no
+  // memset or host work.  Event timing needs the launches one by one.
+  const bool use_graph = !profile && !(opt.flags & HELM_FLAG_NO_GRAPHS);
+  if (use_graph) {
+    GraphKey key{&set, k};
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+      hipGraph_t g;
+      HELM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
+      HELM_HIP(hipStreamEndCapture(st, &g));
+      hipGraphExec_t ex;
+      HELM_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      HELM_HIP(hipGraphDestroy(g));
+      it = graphs.emplace(key, ex).first;
+    }
+    HELM_HIP(hipGraphLaunch(it->second, st));
+  } else {
+    if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
+  }
   layer_solves += (long long)set.layers.size();
   solve_bytes += solve_elems(set) * (double)elem;
 }

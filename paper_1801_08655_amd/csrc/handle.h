@@ -102,6 +102,16 @@ struct Handle {
   std::vector<std::unique_ptr<DevMem>> X, Wt, Ub0, Ub1;
   std::map<std::vector<int>, std::unique_ptr<LayerSet>> sets;
   DevMem scratch;                // split-K partial products
+  // captured substitution sequences: (set, k) -> executable graph
+  struct GraphKey {
+    const LayerSet* set;
+    int k;
+    bool operator<(const GraphKey& o) const {
+      return set < o.set || (set == o.set && k < o.k);
+    }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  void clear_graphs();
 
   // kernel timing (HELM_FLAG_PROFILE)
   bool profile = false;
