@@ -21,6 +21,9 @@ from .models import (
     surface_grid_sources,
     workload,
     WORKLOADS,
+    serving_models,
+    poisson_requests,
+    ServingRequest,
 )
 
 __all__ = [
@@ -32,4 +35,7 @@ __all__ = [
     "surface_grid_sources",
     "workload",
     "WORKLOADS",
+    "serving_models",
+    "poisson_requests",
+    "ServingRequest",
 ]

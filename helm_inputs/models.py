@@ -214,6 +214,44 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
 }
 
 
+def serving_models(n: int = 160, pml: int = 16, L: int = 16, alpha: int = 4,
+                   seed: int = 1805, ppws=(6.0, 8.0, 10.0)) -> List[Workload]:
+    """Resident models of the serving workload: one layered-dipping medium
+    (seed 1805) at three frequencies (6, 8 and 10 points per wavelength at
+    c_min).  The candidate sources are a 16 x 16 surface grid at depth
+    pml + 1."""
+    out = []
+    for ppw in ppws:
+        w = _wl_layered(n=n, pml=pml, L=L, alpha=alpha, seed=seed, n_side=16,
+                        depth=pml + 1, ppw=ppw, name=f"layered-{n}-ppw{ppw:g}")
+        out.append(w)
+    return out
+
+
+@dataclasses.dataclass
+class ServingRequest:
+    t: float                       # arrival time [s] from the start
+    model: int
+    sources: List[Tuple[int, int, int]]
+
+
+def poisson_requests(count: int, rate: float, n_models: int, candidates,
+                     max_sources: int = 128, seed: int = 1806) -> List[ServingRequest]:
+    """``count`` requests with exponential inter-arrival times of mean
+    1/rate, a uniformly random model, and R ~ U{1..max_sources} sources drawn
+    without replacement from ``candidates``."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += rng.exponential(1.0 / rate)
+        model = int(rng.integers(0, n_models))
+        r = int(rng.integers(1, min(max_sources, len(candidates)) + 1))
+        pick = rng.choice(len(candidates), size=r, replace=False)
+        out.append(ServingRequest(t, model, [tuple(candidates[i]) for i in pick]))
+    return out
+
+
 def workload(name: str) -> Workload:
     return WORKLOADS[name]()
 

@@ -51,6 +51,17 @@ def plan(n, pml: int, n_layers: int, h: float = None, **kw):
     return {"factor_bytes": fb.value, "bytes_per_rhs": br.value, "max_front": mf.value}
 
 
+def node_indices(nodes: Sequence, n) -> np.ndarray:
+    """Linear indices (x fastest) of (i, j, k) nodes; ValueError outside the grid."""
+    nx, ny, nz = n
+    out = []
+    for (i, j, kk) in nodes:
+        if not (0 <= i < nx and 0 <= j < ny and 0 <= kk < nz):
+            raise ValueError(f"node {(i, j, kk)} outside the {nx}x{ny}x{nz} grid")
+        out.append(i + nx * (j + ny * kk))
+    return np.array(out, dtype=np.int64)
+
+
 def _ptr(t) -> int:
     """Device pointer of a contiguous torch tensor (complex128 / float64)."""
     if not t.is_contiguous():
@@ -109,7 +120,7 @@ class Solver:
         """Point sources at (i, j, k) nodes, amplitude/h^3 each (default 1)."""
         import torch
         nx, ny, nz = self.n
-        idx = np.array([i + nx * (j + ny * kk) for (i, j, kk) in nodes], dtype=np.int64)
+        idx = node_indices(nodes, self.n)
         r = len(idx)
         amp = np.ones(r, dtype=np.complex128) if amplitudes is None else \
             np.ascontiguousarray(amplitudes, dtype=np.complex128)

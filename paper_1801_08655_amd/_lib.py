@@ -23,6 +23,10 @@ EXPORTED = [
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
     "helm_set_solve_options",
+    # include/helm_serve.h
+    "helm_server_default_options", "helm_server_create", "helm_server_add_model",
+    "helm_server_submit", "helm_server_wait", "helm_server_poll", "helm_server_get_stats",
+    "helm_server_free",
 ]
 HELM_FLAG_PROFILE = 1
 HELM_FLAG_NO_GRAPHS = 2
@@ -86,6 +90,47 @@ class helm_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+class helm_server_options(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int),
+                ("device", ctypes.c_int)]
+
+
+class helm_request_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("n_rhs", ctypes.c_int),
+        ("model", ctypes.c_int),
+        ("ir_steps_max", ctypes.c_int),
+        ("rel_residual_max", ctypes.c_double),
+        ("est_error_max", ctypes.c_double),
+        ("t_submit_ms", ctypes.c_double),
+        ("t_first_ms", ctypes.c_double),
+        ("t_done_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class helm_server_summary(ctypes.Structure):
+    _fields_ = [
+        ("requests_done", ctypes.c_longlong),
+        ("columns_done", ctypes.c_longlong),
+        ("steps", ctypes.c_longlong),
+        ("p50_ms", ctypes.c_double),
+        ("p99_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double),
+        ("mean_active_slots", ctypes.c_double),
+        ("elapsed_s", ctypes.c_double),
+        ("columns_per_s", ctypes.c_double),
+        ("bytes_reserved", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -140,6 +185,23 @@ def lib():
     L.helm_kernel_stats.restype = I
     L.helm_set_solve_options.argtypes = [H, ctypes.POINTER(helm_options)]
     L.helm_set_solve_options.restype = I
+    SV = ctypes.c_void_p
+    L.helm_server_default_options.argtypes = [ctypes.POINTER(helm_server_options)]
+    L.helm_server_default_options.restype = None
+    L.helm_server_create.argtypes = [ctypes.POINTER(helm_server_options), ctypes.POINTER(SV)]
+    L.helm_server_create.restype = I
+    L.helm_server_add_model.argtypes = [SV, H, ctypes.POINTER(I), ctypes.POINTER(I)]
+    L.helm_server_add_model.restype = I
+    L.helm_server_submit.argtypes = [SV, I, I, P, P, P, ctypes.POINTER(ctypes.c_int64)]
+    L.helm_server_submit.restype = I
+    L.helm_server_wait.argtypes = [SV, ctypes.c_int64, ctypes.POINTER(helm_request_info)]
+    L.helm_server_wait.restype = I
+    L.helm_server_poll.argtypes = [SV, ctypes.c_int64, ctypes.POINTER(I)]
+    L.helm_server_poll.restype = I
+    L.helm_server_get_stats.argtypes = [SV, ctypes.POINTER(helm_server_summary)]
+    L.helm_server_get_stats.restype = I
+    L.helm_server_free.argtypes = [SV]
+    L.helm_server_free.restype = I
     _lib = L
     return L
 

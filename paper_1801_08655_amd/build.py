@@ -36,9 +36,11 @@ def _headers_digest():
         if f.endswith(".h"):
             with open(os.path.join(CSRC, f), "rb") as fh:
                 h.update(fh.read())
-    inc = os.path.join(HERE, "..", "include", "helm.h")
-    with open(inc, "rb") as fh:
-        h.update(fh.read())
+    inc = os.path.join(HERE, "..", "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            with open(os.path.join(inc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

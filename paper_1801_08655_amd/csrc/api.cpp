@@ -7,38 +7,12 @@
 #include <string>
 #include <vector>
 
-#include "handle.h"
-#include "method.h"
-
-struct helm_handle {
-  helm::Handle impl;
-  std::unique_ptr<helm::Method> method;   // cached for the last batch width
-};
+#include "api_common.h"
 
 namespace helm {
 
 namespace {
 thread_local std::string g_last_error;
-
-template <class F>
-int guard(F&& f) {
-  try {
-    (void)hipGetLastError();   // do not report a failure of an earlier call
-    return f();
-  } catch (const Error& e) {
-    set_last_error(e.msg);
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
-    return HELM_ENOMEM;
-  } catch (const std::exception& e) {
-    set_last_error(e.what());
-    return HELM_EINVAL;
-  } catch (...) {
-    set_last_error("unknown failure");
-    return HELM_EINVAL;
-  }
-}
 
 helm_options resolve(const helm_options* o) {
   helm_options d;

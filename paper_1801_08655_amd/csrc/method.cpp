@@ -202,8 +202,8 @@ void Method::dot(const double2* a, const double2* b, long long V, double2* out) 
 // Arnoldi (modified Gram-Schmidt), norms and basis updates in FP64 on the
 // device; the (j+2) x k Hessenberg column is copied to the host where the
 // Givens rotations and the stopping test are applied per column.
-int Method::gmres(const double2* b, double2* x, double tol, int max_iter, int restart,
-                  int* iters_out) {
+int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, int max_iter,
+                  int restart, int* iters_out) {
   const long long V = 2 * Vp / k;             // polarized vector length per column
   const int m = std::max(1, std::min(restart, max_iter));
   if (!gw.p) {
@@ -250,7 +250,7 @@ int Method::gmres(const double2* b, double2* x, double tol, int max_iter, int re
       beta[c] = std::sqrt(std::max(hh[c].x, 0.0));
       double rel = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
       resid[c] = rel;
-      active[c] = (bnorm[c] > 0 && rel > tol) ? 1 : 0;
+      active[c] = (bnorm[c] > 0 && rel > tol[c]) ? 1 : 0;
       scl[c] = active[c] ? 1.0 / beta[c] : 0.0;
     }
     bool any = false;
@@ -308,7 +308,7 @@ int Method::gmres(const double2* b, double2* x, double tol, int max_iter, int re
         double rel = bnorm[c] > 0 ? std::abs(g[c][j + 1]) / bnorm[c] : 0.0;
         resid[c] = rel;
         // stop this column on convergence or (lucky) breakdown
-        if (rel <= tol || hn <= 1e-300 || !(std::isfinite(rel))) {
+        if (rel <= tol[c] || hn <= 1e-300 || !(std::isfinite(rel))) {
           run[c] = 0;
           scl[c] = 0.0;
         } else {
@@ -348,7 +348,7 @@ int Method::gmres(const double2* b, double2* x, double tol, int max_iter, int re
       HELM_HIP(hipStreamSynchronize(H.st));
     }
     bool conv = true;
-    for (int c = 0; c < k; ++c) conv &= !(active[c] && resid[c] > tol);
+    for (int c = 0; c < k; ++c) conv &= !(active[c] && resid[c] > tol[c]);
     if (conv) break;
     if (total >= max_iter) { status = HELM_ENOCONV; break; }
   }
@@ -368,6 +368,11 @@ double2* Method::basis_vec(int i) {
 // u = H^-1 f through the polarized interface system (one inner solve)
 int Method::polarized_solve(const double2* f, double2* u, double tol, int max_iter,
                             int restart, helm_solve_info* info) {
+  return polarized_solve(f, u, std::vector<double>(k, tol), max_iter, restart, info);
+}
+
+int Method::polarized_solve(const double2* f, double2* u, const std::vector<double>& tol,
+                            int max_iter, int restart, helm_solve_info* info) {
   const int L = H.G.L;
   double t0 = now_ms();
   if (L == 1) {
@@ -381,10 +386,11 @@ int Method::polarized_solve(const double2* f, double2* u, double tol, int max_it
     if (info) info->t_reconstruct_ms += now_ms() - t0;
     return HELM_OK;
   }
-  DevMem fpol, bpol, xpol;
-  fpol.alloc((size_t)2 * Vp * sizeof(double2));
-  bpol.alloc((size_t)2 * Vp * sizeof(double2));
-  xpol.alloc((size_t)2 * Vp * sizeof(double2));
+  if (!fpol.p) {
+    fpol.alloc((size_t)2 * Vp * sizeof(double2));
+    bpol.alloc((size_t)2 * Vp * sizeof(double2));
+    xpol.alloc((size_t)2 * Vp * sizeof(double2));
+  }
   double2* fdv = fpol.as<double2>();
   polarized_rhs(f, fdv, fdv + Vp);
   apply_P(fdv, fdv + Vp, bpol.as<double2>(), bpol.as<double2>() + Vp);
@@ -434,12 +440,36 @@ void Method::residual(const double2* f, const double2* u, double2* r,
   for (int c = 0; c < k; ++c) rel[c] = nf[c] > 0 ? std::sqrt(nr[c] / nf[c]) : std::sqrt(nr[c]);
 }
 
+// One refinement step on the k columns: D = (polarized solve of R) with a
+// tolerance per column, U += D, R = F - H U in FP64, and the per-column
+// relative residual |R|/|F| and norms |D|, |U|.  With U = 0 and R = F on
+// entry this is the first solve of the column; later steps correct U.
+int Method::refine_step(const double2* F, double2* U, double2* R, double2* D,
+                        const std::vector<double>& tol, StepNorms& out, helm_solve_info* info) {
+  const int restart = gmres_restart(H.opt.gmres_max_iter);
+  int s = polarized_solve(R, D, tol, H.opt.gmres_max_iter, restart, info);
+  kern::launch_accumulate(U, D, N * k, H.st);
+  double tr = now_ms();
+  residual(F, U, R, out.rel);
+  norms(D, out.dn);
+  norms(U, out.un);
+  if (info) info->t_residual_ms += now_ms() - tr;
+  return s;
+}
+
+void Method::ensure_volumes() {
+  if (!vr.p) {
+    vr.alloc((size_t)N * k * sizeof(double2));
+    vd.alloc((size_t)N * k * sizeof(double2));
+  }
+}
+
 // Full online solve of k columns (device arrays).
 int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
   const helm_options& o = H.opt;
   const int restart = gmres_restart(o.gmres_max_iter);
-  DevMem r;
-  r.alloc((size_t)N * k * sizeof(double2));
+  ensure_volumes();
+  double2* r = vr.as<double2>();
   std::vector<double> rel;
   int status = HELM_OK;
   double t0 = now_ms();
@@ -447,7 +477,7 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
     int it0 = info ? info->gmres_iters : 0;
     status = polarized_solve(f, u, o.gmres_tol, o.gmres_max_iter, restart, info);
     double tr = now_ms();
-    residual(f, u, r.as<double2>(), rel);
+    residual(f, u, r, rel);
     if (info) {
       info->ir_steps = std::max(info->ir_steps, 1);
       info->t_residual_ms += now_ms() - tr;
@@ -458,39 +488,26 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
     }
   } else {
     // iterative refinement: u <- u + solve_c64(f - H u), FP64 residuals
-    DevMem d;
-    d.alloc((size_t)N * k * sizeof(double2));
     HELM_HIP(hipMemsetAsync(u, 0, (size_t)N * k * sizeof(double2), H.st));
-    const double2* rhs = f;
+    HELM_HIP(hipMemcpyAsync(r, f, (size_t)N * k * sizeof(double2), hipMemcpyDeviceToDevice,
+                            H.st));
     int steps = 0;
     status = HELM_ENOCONV;
-    std::vector<double> dprev(k, 0.0), dcur(k), unorm(k), est(k, 1.0);
+    std::vector<double> dprev(k, 0.0);
+    StepNorms nm;
     for (int it = 0; it < std::max(1, o.ir_max_steps); ++it) {
       int it0 = info ? info->gmres_iters : 0;
-      const double tol = it == 0 ? o.inner_tol : o.inner_tol_refine;
-      int s = polarized_solve(rhs, d.as<double2>(), tol, o.gmres_max_iter, restart, info);
-      (void)s;
-      kern::launch_accumulate(u, d.as<double2>(), N * k, H.st);
-      double tr = now_ms();
-      residual(f, u, r.as<double2>(), rel);
-      norms(d.as<double2>(), dcur);
-      norms(u, unorm);
-      if (info) info->t_residual_ms += now_ms() - tr;
+      std::vector<double> tol(k, it == 0 ? o.inner_tol : o.inner_tol_refine);
+      refine_step(f, u, r, vd.as<double2>(), tol, nm, info);
+      rel = nm.rel;
       ++steps;
       double mx = 0, emx = 0;
       for (int c = 0; c < k; ++c) {
         mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
-        // error after this step from the contraction of the corrections
-        if (it > 0 && dprev[c] > 0 && unorm[c] > 0) {
-          double q = std::min(dcur[c] / dprev[c], 0.99);
-          est[c] = dcur[c] / unorm[c] * q / (1.0 - q);
-        } else {
-          est[c] = 1.0;
-        }
-        if (unorm[c] == 0) est[c] = 0;
-        emx = std::max(emx, est[c]);
+        double est = refinement_error(it, dprev[c], nm.dn[c], nm.un[c]);
+        emx = std::max(emx, est);
       }
-      dprev = dcur;
+      dprev = nm.dn;
       if (info && it < 8) {
         info->ir_residual[it] = std::max(info->ir_residual[it], mx);
         info->ir_gmres_iters[it] = std::max(info->ir_gmres_iters[it], info->gmres_iters - it0);
@@ -500,7 +517,6 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
         status = HELM_OK;
         break;
       }
-      rhs = r.as<double2>();
     }
     if (info) info->ir_steps = std::max(info->ir_steps, steps);
   }
@@ -511,6 +527,17 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
     info->t_total_ms += now_ms() - t0;
   }
   return status;
+}
+
+// Error of the refined column after step `step` (0-based), estimated from
+// the contraction of the corrections: with q = |d_k| / |d_{k-1}| the
+// remaining error is about |d_k| q / (1 - q) relative to |u|.  Unknown
+// (1) after the first step.
+double refinement_error(int step, double dprev, double dcur, double unorm) {
+  if (unorm == 0) return 0.0;
+  if (step == 0 || dprev <= 0) return 1.0;
+  double q = std::min(dcur / dprev, 0.99);
+  return dcur / unorm * q / (1.0 - q);
 }
 
 int Method::gmres_restart(int max_iter) const {

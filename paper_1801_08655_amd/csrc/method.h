@@ -12,6 +12,8 @@ struct Method {
   int k;
   long long plane = 0, pair_elems = 0, Vp = 0, N = 0;
   DevMem y, zd, zu, keep, dot_partial, hcol, norm_partial, norm_out, scale;
+  DevMem fpol, bpol, xpol;   // polarized right-hand side, P b and the iterate
+  DevMem vr, vd;             // FP64 volumes: residual and correction
   const LayerSet* set_all = nullptr;
   const LayerSet* set_lower = nullptr;
   std::vector<const LayerSet*> single;
@@ -41,14 +43,24 @@ struct Method {
   void polarized_rhs(const double2* f, double2* fd, double2* fu);
   void reconstruct(const double2* f, const double2* tr, double2* u);
   void dot(const double2* a, const double2* b, long long V, double2* out);
-  int gmres(const double2* b, double2* x, double tol, int max_iter, int restart,
-            int* iters);
+  int gmres(const double2* b, double2* x, const std::vector<double>& tol, int max_iter,
+            int restart, int* iters);
   int polarized_solve(const double2* f, double2* u, double tol, int max_iter,
                       int restart, helm_solve_info* info);
+  int polarized_solve(const double2* f, double2* u, const std::vector<double>& tol,
+                      int max_iter, int restart, helm_solve_info* info);
+  struct StepNorms {
+    std::vector<double> rel, dn, un;
+  };
+  int refine_step(const double2* F, double2* U, double2* R, double2* D,
+                  const std::vector<double>& tol, StepNorms& out, helm_solve_info* info);
+  void ensure_volumes();
   void residual(const double2* f, const double2* u, double2* r, std::vector<double>& rel);
   void norms(const double2* x, std::vector<double>& out);
   int solve(const double2* f, double2* u, helm_solve_info* info);
   int gmres_restart(int max_iter) const;
 };
+
+double refinement_error(int step, double dprev, double dcur, double unorm);
 
 }  // namespace helm

@@ -1,0 +1,466 @@
+// Request server: continuous batching of point-source requests over resident
+// factorizations (contracts in include/helm_serve.h).
+//
+// One lane per model: K column slots in FP64 volumes F (source), U (iterate),
+// R (residual) and D (correction), a Method of width K on the handle's
+// stream, and a host thread.  A lane step is one refinement step over all K
+// slots (Method::refine_step); between steps finished columns are copied
+// out and queued columns take their slots.  Empty slots hold zero volumes,
+// which every stage of the solve maps to zero (GMRES treats a zero
+// right-hand side as converged), so they cost launch width but do not
+// change the other columns.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/helm_serve.h"
+#include "api_common.h"
+
+namespace helm {
+namespace {
+
+double wall_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  int64_t id = 0;
+  int model = 0, n = 0;
+  std::vector<long long> nodes;
+  std::vector<double2> amps;
+  double2* out = nullptr;
+  int next_col = 0;       // next column to enter a slot
+  int done_cols = 0;
+  bool finished = false;
+  helm_request_info info{};
+};
+
+struct Slot {
+  Request* req = nullptr;
+  int col = -1;
+  int steps = 0;
+  double dprev = 0;
+};
+
+struct Lane {
+  int model = 0;
+  helm_handle* h = nullptr;
+  int K = 0;
+  size_t bytes = 0;
+  std::unique_ptr<Method> M;
+  DevMem F, U, R, D, nodes_d, amps_d;
+  std::vector<Slot> slots;
+  std::deque<Request*> queue;   // requests with columns not yet in a slot
+  std::vector<long long> node_h;
+  std::vector<double2> amp_h;
+  std::thread th;
+  int occupied() const {
+    int c = 0;
+    for (const Slot& s : slots) c += s.req != nullptr;
+    return c;
+  }
+};
+
+}  // namespace
+
+struct Server {
+  helm_server_options opt{};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  std::vector<std::unique_ptr<Lane>> lanes;
+  std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
+  int64_t next_id = 1;
+  size_t reserved = 0;
+  double t0 = 0;
+  std::vector<double> lat;
+  long long req_done = 0, cols_done = 0, steps = 0;
+  double slot_steps = 0;
+  double t_first_submit = -1, t_last_done = 0;
+
+  void run_lane(Lane& ln);
+  void finish_column(Request* r, int status, int steps, double rel, double est);
+};
+
+// Account a finished column (lock held).
+void Server::finish_column(Request* r, int status, int nsteps, double rel, double est) {
+  helm_request_info& I = r->info;
+  if (status != HELM_OK && I.status == HELM_OK) I.status = status;
+  I.ir_steps_max = std::max(I.ir_steps_max, nsteps);
+  I.rel_residual_max = std::max(I.rel_residual_max, rel);
+  I.est_error_max = std::max(I.est_error_max, est);
+  ++cols_done;
+  if (++r->done_cols == r->n) {
+    r->finished = true;
+    I.t_done_ms = wall_ms() - t0;
+    I.latency_ms = I.t_done_ms - I.t_submit_ms;
+    lat.push_back(I.latency_ms);
+    ++req_done;
+    t_last_done = std::max(t_last_done, I.t_done_ms);
+    cv_done.notify_all();
+  }
+}
+
+void Server::run_lane(Lane& ln) {
+  Handle& H = ln.h->impl;
+  (void)hipSetDevice(H.device);
+  const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
+  const size_t col_bytes = (size_t)N * sizeof(double2);
+  const bool fp64 = H.prec == HELM_FP64;
+  const double inv_h3 = 1.0 / (H.G.h * H.G.h * H.G.h);
+  Method::StepNorms nm;
+  std::vector<int> fresh;
+  struct Done { int slot, status, steps; double rel, est; };
+  std::vector<Done> done;
+  while (true) {
+    fresh.clear();
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || ln.occupied() > 0 || !ln.queue.empty(); });
+      if (stop) return;
+      // admission: queued columns take the free slots, oldest request first
+      for (int s = 0; s < ln.K && !ln.queue.empty(); ++s) {
+        if (ln.slots[s].req) continue;
+        Request* r = ln.queue.front();
+        const int c = r->next_col++;
+        ln.slots[s] = Slot{r, c, 0, 0.0};
+        if (r->info.t_first_ms < 0) r->info.t_first_ms = wall_ms() - t0;
+        ln.node_h[s] = r->nodes[c];
+        ln.amp_h[s] = r->amps[c];
+        fresh.push_back(s);
+        if (r->next_col == r->n) ln.queue.pop_front();
+      }
+    }
+    done.clear();
+    int step_status = HELM_OK;
+    std::string step_error;
+    try {
+      double2* F = ln.F.as<double2>();
+      double2* U = ln.U.as<double2>();
+      double2* R = ln.R.as<double2>();
+      if (!fresh.empty()) {
+        HELM_HIP(hipMemcpyAsync(ln.nodes_d.p, ln.node_h.data(), ln.K * sizeof(long long),
+                                hipMemcpyHostToDevice, H.st));
+        HELM_HIP(hipMemcpyAsync(ln.amps_d.p, ln.amp_h.data(), ln.K * sizeof(double2),
+                                hipMemcpyHostToDevice, H.st));
+      }
+      for (int s : fresh) {
+        // new column: f = point source, u = 0, r = f
+        HELM_HIP(hipMemsetAsync(F + s * N, 0, col_bytes, H.st));
+        HELM_HIP(hipMemsetAsync(U + s * N, 0, col_bytes, H.st));
+        kern::launch_point_sources(F + s * N, ln.nodes_d.as<long long>() + s,
+                                   ln.amps_d.as<double2>() + s, inv_h3, N, 1, H.st);
+        HELM_HIP(hipMemcpyAsync(R + s * N, F + s * N, col_bytes, hipMemcpyDeviceToDevice,
+                                H.st));
+      }
+      std::vector<double> tol(ln.K, 0.0);
+      for (int s = 0; s < ln.K; ++s)
+        tol[s] = fp64 ? H.opt.gmres_tol
+                      : (ln.slots[s].steps == 0 ? H.opt.inner_tol : H.opt.inner_tol_refine);
+      ln.M->refine_step(F, U, R, ln.D.as<double2>(), tol, nm, nullptr);
+      for (int s = 0; s < ln.K; ++s) {
+        Slot& sl = ln.slots[s];
+        if (!sl.req) continue;
+        const int st = sl.steps++;
+        const double rel = nm.rel[s];
+        const double est = fp64 ? 0.0 : refinement_error(st, sl.dprev, nm.dn[s], nm.un[s]);
+        sl.dprev = nm.dn[s];
+        bool fin;
+        int status = HELM_OK;
+        if (fp64) {
+          // one step: GMRES to gmres_tol (a single layer is a direct solve)
+          fin = true;
+          if (H.G.L > 1 && !(ln.M->last_resid.size() > (size_t)s &&
+                             ln.M->last_resid[s] <= H.opt.gmres_tol))
+            status = HELM_ENOCONV;
+        } else {
+          const bool ok = rel <= H.opt.ir_tol || (H.opt.err_target > 0 && est <= H.opt.err_target);
+          fin = ok || sl.steps >= std::max(1, H.opt.ir_max_steps);
+          if (!ok) status = HELM_ENOCONV;
+        }
+        if (!std::isfinite(rel)) { fin = true; status = HELM_ENOCONV; }
+        if (!fin) continue;
+        HELM_HIP(hipMemcpyAsync(sl.req->out + (long long)sl.col * N, U + s * N, col_bytes,
+                                hipMemcpyDefault, H.st));
+        HELM_HIP(hipMemsetAsync(F + s * N, 0, col_bytes, H.st));
+        HELM_HIP(hipMemsetAsync(U + s * N, 0, col_bytes, H.st));
+        HELM_HIP(hipMemsetAsync(R + s * N, 0, col_bytes, H.st));
+        done.push_back(Done{s, status, sl.steps, rel, est});
+      }
+      HELM_HIP(hipStreamSynchronize(H.st));
+    } catch (const Error& e) {
+      step_status = e.code;
+      step_error = e.msg;
+    } catch (const std::exception& e) {
+      step_status = HELM_EINVAL;
+      step_error = e.what();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    const int occ = ln.occupied();
+    ++steps;
+    slot_steps += occ;
+    if (step_status != HELM_OK) {
+      // a failed step ends every column of the lane; the volumes are reset
+      // before the lane takes new columns
+      set_last_error(step_error);
+      for (int s = 0; s < ln.K; ++s) {
+        Slot& sl = ln.slots[s];
+        if (!sl.req) continue;
+        finish_column(sl.req, step_status, sl.steps, INFINITY, INFINITY);
+        sl = Slot{};
+      }
+      (void)hipGetLastError();
+      (void)hipMemsetAsync(ln.F.p, 0, ln.F.bytes, H.st);
+      (void)hipMemsetAsync(ln.U.p, 0, ln.U.bytes, H.st);
+      (void)hipMemsetAsync(ln.R.p, 0, ln.R.bytes, H.st);
+      (void)hipStreamSynchronize(H.st);
+      continue;
+    }
+    for (const Done& d : done) {
+      Slot& sl = ln.slots[d.slot];
+      finish_column(sl.req, d.status, d.steps, d.rel, d.est);
+      sl = Slot{};
+    }
+  }
+}
+
+}  // namespace helm
+
+struct helm_server {
+  helm::Server impl;
+};
+
+using namespace helm;
+
+extern "C" {
+
+void helm_server_default_options(helm_server_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->hbm_budget_bytes = 0;
+  o->slots = 32;
+  o->device = 0;
+}
+
+int helm_server_create(const helm_server_options* opt, helm_server** out) {
+  return guard([&] {
+    HELM_REQUIRE(out, HELM_EINVAL, "null argument");
+    *out = nullptr;
+    std::unique_ptr<helm_server> s(new helm_server);
+    helm_server_default_options(&s->impl.opt);
+    if (opt) s->impl.opt = *opt;
+    if (s->impl.opt.slots <= 0) s->impl.opt.slots = 32;
+    HELM_HIP(hipSetDevice(s->impl.opt.device));
+    s->impl.t0 = wall_ms();
+    *out = s.release();
+    return HELM_OK;
+  });
+}
+
+int helm_server_add_model(helm_server* sv, helm_handle* h, int* model_id, int* slots_out) {
+  return guard([&] {
+    HELM_REQUIRE(sv && h && model_id, HELM_EINVAL, "null argument");
+    Server& S = sv->impl;
+    Handle& H = h->impl;
+    HELM_REQUIRE(H.device == S.opt.device, HELM_EINVAL, "handle lives on another device");
+    HELM_HIP(hipSetDevice(H.device));
+    std::lock_guard<std::mutex> lk(S.mu);
+    for (auto& l : S.lanes) HELM_REQUIRE(l->h != h, HELM_EINVAL, "handle already served");
+    const size_t per = plan_bytes_per_rhs(H.G, H.elem);
+    size_t free_b = 0, total_b = 0;
+    HELM_HIP(hipMemGetInfo(&free_b, &total_b));
+    // memory admission: the largest slot count whose workspace fits
+    int K = S.opt.slots;
+    auto fits = [&](int k) {
+      const size_t ws = per * (size_t)k;
+      if (S.opt.hbm_budget_bytes)
+        return S.reserved + H.bytes_factors + ws <= S.opt.hbm_budget_bytes;
+      return ws <= (size_t)(0.9 * (double)free_b);
+    };
+    while (K > 1 && !fits(K)) K /= 2;
+    HELM_REQUIRE(fits(K), HELM_ENOMEM, "model does not fit the server's memory budget");
+    std::unique_ptr<Lane> ln(new Lane);
+    ln->model = (int)S.lanes.size();
+    ln->h = h;
+    ln->K = K;
+    ln->bytes = H.bytes_factors + per * (size_t)K;
+    const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
+    const size_t vol = (size_t)N * K * sizeof(double2);
+    ln->F.alloc(vol);
+    ln->U.alloc(vol);
+    ln->R.alloc(vol);
+    ln->D.alloc(vol);
+    ln->nodes_d.alloc(K * sizeof(long long));
+    ln->amps_d.alloc(K * sizeof(double2));
+    for (DevMem* d : {&ln->F, &ln->U, &ln->R}) HELM_HIP(hipMemsetAsync(d->p, 0, vol, H.st));
+    HELM_HIP(hipStreamSynchronize(H.st));
+    h->method.reset();   // the lane's Method owns the solve workspace from here
+    ln->M.reset(new Method(H, K));
+    ln->slots.assign(K, Slot{});
+    ln->node_h.assign(K, 0);
+    ln->amp_h.assign(K, make_double2(0, 0));
+    Lane* lp = ln.get();
+    S.reserved += ln->bytes;
+    S.lanes.push_back(std::move(ln));
+    lp->th = std::thread([&S, lp] { S.run_lane(*lp); });
+    *model_id = lp->model;
+    if (slots_out) *slots_out = K;
+    return HELM_OK;
+  });
+}
+
+int helm_server_submit(helm_server* sv, int model_id, int n_rhs, const int64_t* node_index,
+                       const double* amplitude, double* u, int64_t* request_id) {
+  return guard([&] {
+    HELM_REQUIRE(sv && request_id && n_rhs >= 0, HELM_EINVAL, "bad argument");
+    HELM_REQUIRE(n_rhs == 0 || (node_index && amplitude && u), HELM_EINVAL, "null argument");
+    Server& S = sv->impl;
+    std::unique_ptr<Request> r(new Request);
+    Lane* ln = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      HELM_REQUIRE(!S.stop, HELM_EINVAL, "server is stopping");
+      HELM_REQUIRE(model_id >= 0 && model_id < (int)S.lanes.size(), HELM_EINVAL,
+                   "unknown model");
+      ln = S.lanes[model_id].get();
+    }
+    const Geometry& G = ln->h->impl.G;
+    const long long N = (long long)G.nx * G.ny * G.nz;
+    r->n = n_rhs;
+    r->model = model_id;
+    r->out = reinterpret_cast<double2*>(u);
+    r->nodes.resize(n_rhs);
+    r->amps.resize(n_rhs);
+    for (int c = 0; c < n_rhs; ++c) {
+      HELM_REQUIRE(node_index[c] >= 0 && node_index[c] < N, HELM_EINVAL,
+                   "point source outside the grid");
+      HELM_REQUIRE(std::isfinite(amplitude[2 * c]) && std::isfinite(amplitude[2 * c + 1]),
+                   HELM_EINVAL, "non-finite amplitude");
+      r->nodes[c] = node_index[c];
+      r->amps[c] = make_double2(amplitude[2 * c], amplitude[2 * c + 1]);
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    r->id = S.next_id++;
+    r->info.status = HELM_OK;
+    r->info.n_rhs = n_rhs;
+    r->info.model = model_id;
+    r->info.t_submit_ms = wall_ms() - S.t0;
+    r->info.t_first_ms = -1;
+    if (S.t_first_submit < 0) S.t_first_submit = r->info.t_submit_ms;
+    *request_id = r->id;
+    Request* rp = r.get();
+    S.reqs.emplace(r->id, std::move(r));
+    if (n_rhs == 0) {
+      rp->finished = true;
+      rp->info.t_first_ms = rp->info.t_done_ms = rp->info.t_submit_ms;
+      S.cv_done.notify_all();
+    } else {
+      ln->queue.push_back(rp);
+      S.cv_work.notify_all();
+    }
+    return HELM_OK;
+  });
+}
+
+int helm_server_wait(helm_server* sv, int64_t request_id, helm_request_info* info) {
+  return guard([&] {
+    HELM_REQUIRE(sv, HELM_EINVAL, "null server");
+    Server& S = sv->impl;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(request_id);
+    HELM_REQUIRE(it != S.reqs.end(), HELM_EINVAL, "unknown request (or already waited for)");
+    Request* r = it->second.get();
+    S.cv_done.wait(lk, [&] { return r->finished; });
+    if (info) *info = r->info;
+    int st = r->info.status;
+    S.reqs.erase(it);
+    if (st != HELM_OK) set_last_error(st == HELM_ENOCONV ? "tolerance not reached" : "request failed");
+    return st;
+  });
+}
+
+int helm_server_poll(helm_server* sv, int64_t request_id, int* done) {
+  return guard([&] {
+    HELM_REQUIRE(sv && done, HELM_EINVAL, "null argument");
+    Server& S = sv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(request_id);
+    HELM_REQUIRE(it != S.reqs.end(), HELM_EINVAL, "unknown request (or already waited for)");
+    *done = it->second->finished ? 1 : 0;
+    return HELM_OK;
+  });
+}
+
+int helm_server_get_stats(helm_server* sv, helm_server_summary* out) {
+  return guard([&] {
+    HELM_REQUIRE(sv && out, HELM_EINVAL, "null argument");
+    Server& S = sv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    std::memset(out, 0, sizeof(*out));
+    out->requests_done = S.req_done;
+    out->columns_done = S.cols_done;
+    out->steps = S.steps;
+    out->bytes_reserved = S.reserved;
+    out->mean_active_slots = S.steps ? S.slot_steps / S.steps : 0.0;
+    if (!S.lat.empty()) {
+      std::vector<double> v = S.lat;
+      std::sort(v.begin(), v.end());
+      auto pct = [&](double q) {
+        size_t i = (size_t)std::ceil(q / 100.0 * v.size());
+        return v[std::min(v.size() - 1, i > 0 ? i - 1 : 0)];
+      };
+      out->p50_ms = pct(50);
+      out->p99_ms = pct(99);
+      double sum = 0;
+      for (double x : v) sum += x;
+      out->mean_ms = sum / v.size();
+    }
+    if (S.t_first_submit >= 0 && S.t_last_done > S.t_first_submit) {
+      out->elapsed_s = (S.t_last_done - S.t_first_submit) * 1e-3;
+      out->columns_per_s = S.cols_done / out->elapsed_s;
+    }
+    return HELM_OK;
+  });
+}
+
+int helm_server_free(helm_server* sv) {
+  return guard([&] {
+    if (!sv) return HELM_OK;
+    Server& S = sv->impl;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      S.stop = true;
+    }
+    S.cv_work.notify_all();
+    for (auto& l : S.lanes)
+      if (l->th.joinable()) l->th.join();
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      for (auto& kv : S.reqs) {
+        Request* r = kv.second.get();
+        if (!r->finished) {
+          r->finished = true;
+          r->info.status = HELM_EINVAL;
+        }
+      }
+      S.cv_done.notify_all();
+    }
+    for (auto& l : S.lanes) {
+      (void)hipSetDevice(l->h->impl.device);
+      (void)hipStreamSynchronize(l->h->impl.st);
+      l->M.reset();
+    }
+    delete sv;
+    return HELM_OK;
+  });
+}
+
+}  // extern "C"

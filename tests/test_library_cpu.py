@@ -16,15 +16,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    with open(os.path.join(ROOT, "include", "helm.h")) as fh:
-        text = fh.read()
-    return sorted(set(re.findall(r"\b(helm_[a-z_]+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            with open(os.path.join(inc, f)) as fh:
+                names |= set(re.findall(r"\b(helm_[a-z_]+)\s*\(", fh.read()))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     L = pt.lib()
     declared = _declared_symbols()
-    assert len(declared) >= 14
+    assert len(declared) >= 24
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(declared) == sorted(_lib.EXPORTED)
@@ -129,3 +133,19 @@ def test_headline_plan_fits_one_gpu():
         r = pt.plan((200, 200, 200), 15, 20, precision=prec, pml_local=4)
         total = r["factor_bytes"] + 32 * r["bytes_per_rhs"]
         assert total < 288e9, (prec, r)
+
+
+def test_server_entry_points_reject_null_arguments():
+    """Argument checks of the request server that return before any device call."""
+    L = pt.lib()
+    assert L.helm_server_create(None, None) == pt.HELM_EINVAL
+    assert L.helm_server_add_model(None, None, None, None) == pt.HELM_EINVAL
+    rid = ctypes.c_int64()
+    assert L.helm_server_submit(None, 0, 1, None, None, None, ctypes.byref(rid)) == pt.HELM_EINVAL
+    assert L.helm_server_wait(None, 1, None) == pt.HELM_EINVAL
+    assert L.helm_server_poll(None, 1, None) == pt.HELM_EINVAL
+    assert L.helm_server_get_stats(None, None) == pt.HELM_EINVAL
+    assert L.helm_server_free(None) == pt.HELM_OK
+    o = _lib.helm_server_options()
+    L.helm_server_default_options(ctypes.byref(o))
+    assert o.slots == 32 and o.hbm_budget_bytes == 0
