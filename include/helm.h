@@ -54,6 +54,11 @@ extern "C" {
                                 HIP events on the handle's stream            */
 #define HELM_FLAG_NO_GRAPHS 2 /* launch the substitution kernels one by one
                                 instead of replaying captured HIP graphs     */
+#define HELM_FLAG_AUTOTUNE 4  /* on the first solve of a layer set at a batch
+                                width, time every column-tile width of the
+                                substitution GEMMs per depth of the front
+                                trees and keep the fastest (default: widths
+                                from the batch width alone)                  */
 
 /* ---- precision of the local factors ----------------------------------- */
 #define HELM_FP64   0   /* complex128 fronts and substitutions              */
@@ -176,6 +181,22 @@ typedef struct {
 
 int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count,
                       int reset);
+
+/* Column-tile choices of the substitution GEMMs: one record per (layer set,
+ * batch width k, depth of the front trees), for the sets used so far.  A
+ * layer set is described by its number of layers.  fwd_bn / bwd_bn are the
+ * tile widths in use (16, 32 or 64 columns); when the choice was measured
+ * (HELM_FLAG_AUTOTUNE), t_fwd_us / t_bwd_us hold the timed launch of each
+ * width in the order 16, 32, 64 (0 where a width was not tried).  Writes up
+ * to `max` records and the total to *count. */
+typedef struct {
+  int    set_layers, k, depth, fronts;
+  double mean_s, mean_b;   /* mean pivot / boundary size of the depth's fronts */
+  int    fwd_bn, bwd_bn, bwd_bm, tuned;
+  double t_fwd_us[3], t_bwd_us[3];
+} helm_tile_choice;
+
+int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count);
 
 /* Change the online-stage options of a factorized handle (gmres_tol,
  * gmres_max_iter, ir_tol, ir_max_steps, inner_tol, max_rhs, flags); the

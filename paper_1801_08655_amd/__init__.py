@@ -196,6 +196,15 @@ class Solver:
                                        "flops": arr[i].flops, "bytes": arr[i].bytes}
                 for i in range(cnt.value)}
 
+    def tile_choices(self):
+        """Column-tile widths of the substitution GEMMs per (layer set, k, depth)."""
+        cnt = ctypes.c_int()
+        check(lib().helm_tile_choices(self._h, None, 0, ctypes.byref(cnt)), "helm_tile_choices")
+        arr = (_lib.helm_tile_choice * max(cnt.value, 1))()
+        check(lib().helm_tile_choices(self._h, arr, cnt.value, ctypes.byref(cnt)),
+              "helm_tile_choices")
+        return [arr[i].as_dict() for i in range(cnt.value)]
+
     def close(self):
         if self._h:
             lib().helm_free(self._h)

@@ -22,7 +22,7 @@ EXPORTED = [
     "helm_solve", "helm_solve_dev", "helm_solve_points", "helm_free",
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
-    "helm_set_solve_options",
+    "helm_set_solve_options", "helm_tile_choices",
     # include/helm_serve.h
     "helm_server_default_options", "helm_server_create", "helm_server_add_model",
     "helm_server_submit", "helm_server_wait", "helm_server_poll", "helm_server_get_stats",
@@ -30,6 +30,7 @@ EXPORTED = [
 ]
 HELM_FLAG_PROFILE = 1
 HELM_FLAG_NO_GRAPHS = 2
+HELM_FLAG_AUTOTUNE = 4
 
 
 class helm_grid(ctypes.Structure):
@@ -88,6 +89,20 @@ class helm_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_longlong),
                 ("total_ms", ctypes.c_double), ("flops", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
+
+
+class helm_tile_choice(ctypes.Structure):
+    _fields_ = [("set_layers", ctypes.c_int), ("k", ctypes.c_int), ("depth", ctypes.c_int),
+                ("fronts", ctypes.c_int), ("mean_s", ctypes.c_double),
+                ("mean_b", ctypes.c_double), ("fwd_bn", ctypes.c_int),
+                ("bwd_bn", ctypes.c_int), ("bwd_bm", ctypes.c_int), ("tuned", ctypes.c_int),
+                ("t_fwd_us", ctypes.c_double * 3), ("t_bwd_us", ctypes.c_double * 3)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["t_fwd_us"] = list(self.t_fwd_us)
+        d["t_bwd_us"] = list(self.t_bwd_us)
+        return d
 
 
 class helm_server_options(ctypes.Structure):
@@ -185,6 +200,8 @@ def lib():
     L.helm_kernel_stats.restype = I
     L.helm_set_solve_options.argtypes = [H, ctypes.POINTER(helm_options)]
     L.helm_set_solve_options.restype = I
+    L.helm_tile_choices.argtypes = [H, ctypes.POINTER(helm_tile_choice), I, ctypes.POINTER(I)]
+    L.helm_tile_choices.restype = I
     SV = ctypes.c_void_p
     L.helm_server_default_options.argtypes = [ctypes.POINTER(helm_server_options)]
     L.helm_server_default_options.restype = None

@@ -266,6 +266,42 @@ int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count
   });
 }
 
+int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count) {
+  return guard([&] {
+    HELM_REQUIRE(h, HELM_EINVAL, "null handle");
+    Handle& H = h->impl;
+    int n = 0;
+    for (const auto& kv : H.tiles) {
+      const LayerSet& S = *kv.first.set;
+      for (int d = 0; d <= S.max_depth && d < (int)kv.second.size(); ++d) {
+        const DepthList& D = *S.depth[d];
+        const Handle::TileChoice& c = kv.second[d];
+        if (out && n < max) {
+          helm_tile_choice& o = out[n];
+          std::memset(&o, 0, sizeof(o));
+          o.set_layers = (int)S.layers.size();
+          o.k = kv.first.k;
+          o.depth = d;
+          o.fronts = D.n;
+          o.mean_s = D.n ? D.sum_s / D.n : 0.0;
+          o.mean_b = D.n ? D.sum_b / D.n : 0.0;
+          o.fwd_bn = c.fwd_bn;
+          o.bwd_bn = (D.bwd_bm == 32 && c.bwd_bn == 16) ? 32 : c.bwd_bn;
+          o.bwd_bm = D.bwd_bm;
+          o.tuned = c.tuned ? 1 : 0;
+          for (int w = 0; w < 3; ++w) {
+            o.t_fwd_us[w] = c.t_fwd[w];
+            o.t_bwd_us[w] = c.t_bwd[w];
+          }
+        }
+        ++n;
+      }
+    }
+    if (count) *count = n;
+    return HELM_OK;
+  });
+}
+
 int helm_set_solve_options(helm_handle* h, const helm_options* opt) {
   return guard([&] {
     HELM_REQUIRE(h && opt, HELM_EINVAL, "null argument");

@@ -600,6 +600,7 @@ void Handle::solve_layers(const LayerSet& set, int k) {
   // The ~35 dependent launches of one multi-RHS solve are captured once per
   // (layer set, width) into a HIP graph and replayed; the sequence holds no
   // memset or host work.  Event timing needs the launches one by one.
+  (void)tile_plan(set, k);   // measured choices, if asked for, are taken here
   const bool use_graph = !profile && !(opt.flags & HELM_FLAG_NO_GRAPHS);
   if (use_graph) {
     GraphKey key{&set, k};
@@ -622,12 +623,111 @@ void Handle::solve_layers(const LayerSet& set, int k) {
   solve_bytes += solve_elems(set) * (double)elem;
 }
 
+// Tile width from the batch width alone: the narrowest of 16 / 32 / 64
+// columns that covers k (wider batches take several 64-column tiles).
+static int width_bn(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+const std::vector<Handle::TileChoice>& Handle::tile_plan(const LayerSet& set, int k) {
+  GraphKey key{&set, k};
+  auto it = tiles.find(key);
+  if (it != tiles.end()) return it->second;
+  std::vector<TileChoice> plan(set.max_depth + 1);
+  for (auto& c : plan) c.fwd_bn = c.bwd_bn = width_bn(k);
+  if (opt.flags & HELM_FLAG_AUTOTUNE) {
+    if (prec == HELM_FP64) autotune_t<double>(set, k, plan);
+    else autotune_t<float>(set, k, plan);
+  }
+  return tiles.emplace(key, std::move(plan)).first->second;
+}
+
+// Measured tile choice: every depth's forward and backward GEMM launched
+// alone with each admissible width (a width is tried when it is the default
+// or narrower than it), best of three launches each, on the solve workspace.
+// The right-hand sides already in X are saved and restored around it; the
+// other buffers the launches write are rewritten by every solve before they
+// are read.
+template <typename T>
+void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& plan) {
+  const FrontDev* fr = fronts.as<FrontDev>();
+  const LayerDev* ld = layers_d.as<LayerDev>();
+  void* scr = scratch.p;
+  size_t save_bytes = 0;
+  for (int l : set.layers) save_bytes += (size_t)G.layers[l].n_loc * k * elem;
+  DevMem save;
+  save.alloc(save_bytes);
+  {
+    size_t off = 0;
+    for (int l : set.layers) {
+      const size_t b = (size_t)G.layers[l].n_loc * k * elem;
+      HELM_HIP(hipMemcpyAsync((char*)save.p + off, X[l]->p, b, hipMemcpyDeviceToDevice, st));
+      off += b;
+    }
+  }
+  hipEvent_t e0, e1;
+  HELM_HIP(hipEventCreate(&e0));
+  HELM_HIP(hipEventCreate(&e1));
+  const int widths[3] = {16, 32, 64};
+  auto time_us = [&](auto&& launch) {
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      HELM_HIP(hipEventRecord(e0, st));
+      launch();
+      HELM_HIP(hipEventRecord(e1, st));
+      HELM_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      HELM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, 1e3 * (double)ms);
+    }
+    return best;
+  };
+  const int dflt = width_bn(k);
+  for (int d = 0; d <= set.max_depth; ++d) {
+    const DepthList& D = *set.depth[d];
+    TileChoice& c = plan[d];
+    c.tuned = true;
+    if (D.n == 0) continue;
+    double bf = 1e30, bb = 1e30;
+    for (int w = 0; w < 3; ++w) {
+      const int bn = widths[w];
+      if (bn > dflt) continue;
+      if (D.nL > 0) {
+        double t = time_us([&] {
+          kern::launch_fwd_gemm<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
+                                   D.pF.as<int>(), D.tF, ld, k, scr, bn, st);
+        });
+        c.t_fwd[w] = t;
+        if (t < bf) { bf = t; c.fwd_bn = bn; }
+      }
+      if (D.bwd_bm == 32 && bn == 16) continue;   // not a distinct tile
+      double t = time_us([&] {
+        kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
+                                 D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm, bn, st);
+      });
+      c.t_bwd[w] = t;
+      if (t < bb) { bb = t; c.bwd_bn = bn; }
+    }
+  }
+  HELM_HIP(hipGetLastError());
+  {
+    size_t off = 0;
+    for (int l : set.layers) {
+      const size_t b = (size_t)G.layers[l].n_loc * k * elem;
+      HELM_HIP(hipMemcpyAsync(X[l]->p, (char*)save.p + off, b, hipMemcpyDeviceToDevice, st));
+      off += b;
+    }
+  }
+  HELM_HIP(hipStreamSynchronize(st));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 template <typename T>
 void Handle::solve_layers_t(const LayerSet& set, int k) {
   const FrontDev* fr = fronts.as<FrontDev>();
   const LayerDev* ld = layers_d.as<LayerDev>();
   const double e = (double)elem, kk = (double)k;
   void* scr = scratch.p;
+  const std::vector<TileChoice>& tp = tile_plan(set, k);
   for (int d = set.max_depth; d >= 0; --d) {
     const DepthList& D = *set.depth[d];
     if (D.n == 0) continue;
@@ -642,7 +742,8 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
       const int* ids = D.idsL.as<int>();
       const SolveTask* tk = D.tasksL.as<SolveTask>();
       a = prof_begin();
-      kern::launch_fwd_gemm<T>(fr, ids, tk, D.nL, D.pF.as<int>(), D.tF, ld, k, scr, st);
+      kern::launch_fwd_gemm<T>(fr, ids, tk, D.nL, D.pF.as<int>(), D.tF, ld, k, scr,
+                               tp[d].fwd_bn, st);
       // factor block read once; pivots read, Z written, boundary updates
       // written and the children's updates of the boundary rows read
       prof_end(K_FWD_GEMM, a, 8.0 * D.fl_sbs * kk,
@@ -661,7 +762,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin();
     kern::launch_bwd_gemm<T>(fr, ids, tk, D.n, D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm,
-                             st);
+                             tp[d].bwd_bn, st);
     // factor block read once; X(B) rows read, Z(S) read, X(S) written
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);

@@ -112,6 +112,16 @@ struct Handle {
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
   void clear_graphs();
+  // column-tile widths of the substitution GEMMs per depth, per (set, k)
+  struct TileChoice {
+    int fwd_bn = 64, bwd_bn = 64;
+    bool tuned = false;
+    double t_fwd[3] = {0, 0, 0}, t_bwd[3] = {0, 0, 0};   // us per width 16/32/64
+  };
+  std::map<GraphKey, std::vector<TileChoice>> tiles;
+  const std::vector<TileChoice>& tile_plan(const LayerSet& set, int k);
+  template <typename T> void autotune_t(const LayerSet& set, int k,
+                                        std::vector<TileChoice>& plan);
 
   // kernel timing (HELM_FLAG_PROFILE)
   bool profile = false;

@@ -54,7 +54,7 @@ void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* pre
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, hipStream_t st);
+                     void* scratch, int bn, hipStream_t st);
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int* prefix, int total, const LayerDev* layers, int k,
@@ -62,7 +62,7 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, hipStream_t st);
+                     void* scratch, int bm, int bn, hipStream_t st);
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int* prefix, int total, const LayerDev* layers, int k,

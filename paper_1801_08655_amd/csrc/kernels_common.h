@@ -128,55 +128,69 @@ __device__ __forceinline__ C_t<T> view_at(const View<T>& v, int r, int k) {
   return val;
 }
 
-// Shared-memory staging of one K step of a BM x 64 complex GEMM tile in the
+// Shared-memory staging of one K step of a BM x BN complex GEMM tile in the
 // real form of the complex product:
 //   P[r][2k + {0,1}] = (re, im) of the row operand,
 //   Q1[2k][c] = re, Q1[2k+1][c] = -im   (column operand, real part of C),
 //   Q2[2k][c] = im, Q2[2k+1][c] = re    (imaginary part of C),
 // so that every MFMA reads its operands with one load and no arithmetic.
+// BN (columns of the tile: right-hand sides in the substitutions) is 64, 32
+// or 16; narrow tiles keep the matrix cores busy on useful columns when a
+// batch has fewer than 64 columns.
 constexpr int PSTR = 2 * GK + 4;   // row stride of P (padding against bank conflicts)
-constexpr int QSTR = GT + 4;
-template <typename T, int BM> struct GemmSmem {
+template <typename T, int BM, int BN = GT> struct GemmSmem {
   T P[BM][PSTR];
-  T Q1[2 * GK][QSTR];
-  T Q2[2 * GK][QSTR];
+  T Q1[2 * GK][BN + 4];
+  T Q2[2 * GK][BN + 4];
+};
+
+// The 4 waves of a block tile it as WR x WC sub-tiles of RW x CW, each made
+// of MB x NB MFMA 16x16 blocks.
+template <int BM, int BN> struct WaveGrid {
+  static constexpr int WC = BN >= 32 ? 2 : 1;
+  static constexpr int WR = 4 / WC;
+  static constexpr int RW = BM / WR, CW = BN / WC;
+  static constexpr int MB = RW / 16, NB = CW / 16;
+  static_assert(RW >= 16 && CW >= 16 && RW % 16 == 0 && CW % 16 == 0,
+                "wave sub-tile must be whole MFMA blocks");
 };
 
 // Per-thread staging registers for one K step of both operands.
-template <typename T, int BM> struct Stage {
-  static constexpr int NP = BM * GK / 256, NQ = GT * GK / 256;
+template <typename T, int BM, int BN = GT> struct Stage {
+  static constexpr int NP = BM * GK / 256, NQ = BN * GK / 256;
   C_t<T> p[NP], q[NQ];
 };
 
-// Global loads of the BM x GK block of P (rows r0.., k0..) and the GK x 64
+// Global loads of the BM x GK block of P (rows r0.., k0..) and the GK x BN
 // block of Q (columns c0.., k0..).  FAST_R / FAST_C: consecutive threads walk
 // the rows of P / the columns of Q (the contiguous dimension in memory).
-template <typename T, int BM, bool FAST_R, bool FAST_C>
-__device__ __forceinline__ void stage_load(Stage<T, BM>& g, const View<T>& pv,
+template <typename T, int BM, int BN, bool FAST_R, bool FAST_C>
+__device__ __forceinline__ void stage_load(Stage<T, BM, BN>& g, const View<T>& pv,
                                            const View<T>& qv, int r0, int c0, int k0,
                                            int kend) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < Stage<T, BM>::NP; ++it) {
+  for (int it = 0; it < Stage<T, BM, BN>::NP; ++it) {
     const int e = t + it * 256;
     int r, k;
     if (FAST_R) { r = e % BM; k = e / BM; } else { k = e % GK; r = e / GK; }
     g.p[it] = (k0 + k < kend) ? view_at(pv, r0 + r, k0 + k) : czero<C_t<T>>();
   }
 #pragma unroll
-  for (int it = 0; it < Stage<T, BM>::NQ; ++it) {
+  for (int it = 0; it < Stage<T, BM, BN>::NQ; ++it) {
     const int e = t + it * 256;
     int c, kq;
-    if (FAST_C) { c = e % GT; kq = e / GT; } else { kq = e % GK; c = e / GK; }
+    if (FAST_C) { c = e % BN; kq = e / BN; } else { kq = e % GK; c = e / GK; }
     g.q[it] = (k0 + kq < kend) ? view_at(qv, c0 + c, k0 + kq) : czero<C_t<T>>();
   }
 }
 
-template <typename T, int BM, bool FAST_R, bool FAST_C>
-__device__ __forceinline__ void stage_store(GemmSmem<T, BM>& sm, const Stage<T, BM>& g) {
+template <typename T, int BM, int BN, bool FAST_R, bool FAST_C>
+__device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN>& sm,
+                                            const Stage<T, BM, BN>& g) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int it = 0; it < Stage<T, BM>::NP; ++it) {
+  for (int it = 0; it < Stage<T, BM, BN>::NP; ++it) {
     const int e = t + it * 256;
     int r, k;
     if (FAST_R) { r = e % BM; k = e / BM; } else { k = e % GK; r = e / GK; }
@@ -184,10 +198,10 @@ __device__ __forceinline__ void stage_store(GemmSmem<T, BM>& sm, const Stage<T, 
     sm.P[r][2 * k + 1] = g.p[it].y;
   }
 #pragma unroll
-  for (int it = 0; it < Stage<T, BM>::NQ; ++it) {
+  for (int it = 0; it < Stage<T, BM, BN>::NQ; ++it) {
     const int e = t + it * 256;
     int c, kq;
-    if (FAST_C) { c = e % GT; kq = e / GT; } else { kq = e % GK; c = e / GK; }
+    if (FAST_C) { c = e % BN; kq = e / BN; } else { kq = e % GK; c = e / GK; }
     const C_t<T> y = g.q[it];
     sm.Q1[2 * kq][c] = y.x;
     sm.Q1[2 * kq + 1][c] = -y.y;
@@ -196,16 +210,16 @@ __device__ __forceinline__ void stage_store(GemmSmem<T, BM>& sm, const Stage<T, 
   }
 }
 
-// Accumulators of one wave: a (BM/2) x 32 complex sub-tile as
-// (BM/32) x 2 MFMA 16x16 blocks.
-template <typename T, int BM> struct WaveAcc {
-  static constexpr int MB = BM / 32;
-  typename Mfma<T>::v4 re[MB][2], im[MB][2];
+// Accumulators of one wave: its RW x CW complex sub-tile as MB x NB MFMA
+// 16x16 blocks (real and imaginary parts).
+template <typename T, int BM, int BN = GT> struct WaveAcc {
+  using G = WaveGrid<BM, BN>;
+  typename Mfma<T>::v4 re[G::MB][G::NB], im[G::MB][G::NB];
   __device__ void zero() {
 #pragma unroll
-    for (int a = 0; a < MB; ++a)
+    for (int a = 0; a < G::MB; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < G::NB; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) { re[a][b][v] = 0; im[a][b][v] = 0; }
   }
@@ -213,71 +227,72 @@ template <typename T, int BM> struct WaveAcc {
 
 // One K step (GK complex = 2 GK real) of MFMAs for this wave; lane l supplies
 // A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
-template <typename T, int BM>
-__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM>& sm, WaveAcc<T, BM>& acc,
-                                          int wr, int wc, int lane) {
-  constexpr int MB = BM / 32;
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN>& sm,
+                                          WaveAcc<T, BM, BN>& acc, int wr, int wc, int lane) {
+  using G = WaveGrid<BM, BN>;
   const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
   for (int p = 0; p < GK / 2; ++p) {
     const int kk = 4 * p + lq;
-    T a[MB], b1[2], b2[2];
+    T a[G::MB], b1[G::NB], b2[G::NB];
 #pragma unroll
-    for (int bm = 0; bm < MB; ++bm) a[bm] = sm.P[wr * (BM / 2) + bm * 16 + li][kk];
+    for (int bm = 0; bm < G::MB; ++bm) a[bm] = sm.P[wr * G::RW + bm * 16 + li][kk];
 #pragma unroll
-    for (int bn = 0; bn < 2; ++bn) {
-      b1[bn] = sm.Q1[kk][wc * 32 + bn * 16 + li];
-      b2[bn] = sm.Q2[kk][wc * 32 + bn * 16 + li];
+    for (int bn = 0; bn < G::NB; ++bn) {
+      b1[bn] = sm.Q1[kk][wc * G::CW + bn * 16 + li];
+      b2[bn] = sm.Q2[kk][wc * G::CW + bn * 16 + li];
     }
 #pragma unroll
-    for (int bm = 0; bm < MB; ++bm)
+    for (int bm = 0; bm < G::MB; ++bm)
 #pragma unroll
-      for (int bn = 0; bn < 2; ++bn) {
+      for (int bn = 0; bn < G::NB; ++bn) {
         acc.re[bm][bn] = Mfma<T>::op(a[bm], b1[bn], acc.re[bm][bn]);
         acc.im[bm][bn] = Mfma<T>::op(a[bm], b2[bn], acc.im[bm][bn]);
       }
   }
 }
 
-// K loop of a BM x 64 tile over k in [kbeg, kend): rows of P from `pv`
+// K loop of a BM x BN tile over k in [kbeg, kend): rows of P from `pv`
 // starting at r0, columns of Q from `qv` starting at c0.  The global loads
 // of the next K step are issued before the matrix-core work of the current
 // one, so their latency overlaps the MFMAs.
-template <typename T, int BM, bool P_FAST_R, bool Q_FAST_C>
-__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM>& sm, WaveAcc<T, BM>& acc,
+template <typename T, int BM, bool P_FAST_R, bool Q_FAST_C, int BN>
+__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN>& sm, WaveAcc<T, BM, BN>& acc,
                                           const View<T>& pv, const View<T>& qv,
                                           int r0, int c0, int kbeg, int kend) {
+  using G = WaveGrid<BM, BN>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / G::WC, wc = wave % G::WC;
   acc.zero();
   if (kbeg >= kend) return;
-  Stage<T, BM> g;
-  stage_load<T, BM, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
+  Stage<T, BM, BN> g;
+  stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
   for (int k0 = kbeg; k0 < kend; k0 += GK) {
-    stage_store<T, BM, P_FAST_R, Q_FAST_C>(sm, g);
+    stage_store<T, BM, BN, P_FAST_R, Q_FAST_C>(sm, g);
     __syncthreads();
     if (k0 + GK < kend)
-      stage_load<T, BM, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
-    mfma_step<T, BM>(sm, acc, wr, wc, lane);
+      stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
+    mfma_step<T, BM, BN>(sm, acc, wr, wc, lane);
     __syncthreads();
   }
 }
 
-// Visit this lane's outputs: f(r, c, value) with r (0..BM-1), c (0..63) the
+// Visit this lane's outputs: f(r, c, value) with r (0..BM-1), c (0..BN-1) the
 // tile-local MFMA row / column.
-template <typename T, int BM, class F>
-__device__ __forceinline__ void for_each_acc(const WaveAcc<T, BM>& acc, F&& f) {
-  constexpr int MB = BM / 32;
+template <typename T, int BM, int BN, class F>
+__device__ __forceinline__ void for_each_acc(const WaveAcc<T, BM, BN>& acc, F&& f) {
+  using G = WaveGrid<BM, BN>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / G::WC, wc = wave % G::WC;
 #pragma unroll
-  for (int bm = 0; bm < MB; ++bm)
+  for (int bm = 0; bm < G::MB; ++bm)
 #pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
+    for (int bn = 0; bn < G::NB; ++bn)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int r = wr * (BM / 2) + bm * 16 + Mfma<T>::row(lane, v);
-        int c = wc * 32 + bn * 16 + (lane & 15);
+        int r = wr * G::RW + bm * 16 + Mfma<T>::row(lane, v);
+        int c = wc * G::CW + bn * 16 + (lane & 15);
         C_t<T> z;
         z.x = acc.re[bm][bn][v];
         z.y = acc.im[bm][bn][v];

@@ -363,7 +363,7 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> qv{F + (long long)k * n, 1, (long long)n, n, nbf};
   WaveAcc<T, 64> acc;
   gemm_tile<T, 64, false, true>(sm, acc, pv, qv, j0, i0, 0, nbf);
-  for_each_acc<T, 64>(acc, [&](int r, int c, C z) {
+  for_each_acc<T, 64, 64>(acc, [&](int r, int c, C z) {
     const int gi = i0 + c, gj = j0 + r;
     if (gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf)) {
       C& e = F[(long long)gi + (long long)gj * n];

@@ -76,15 +76,15 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 
 // forward, step 2: [X(S); Ub] = [F11^-1 w_S; Ub - F21 F11^-1 w_S], the K
 // (pivot) dimension optionally split into chunks (partials to scratch).
-template <typename T>
+template <typename T, int BN>
 __global__ void __launch_bounds__(256)
 k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
   constexpr int BM = FWD_BM;
-  __shared__ GemmSmem<T, BM> sm;
-  const int ntn = (k + GT - 1) / GT;
+  __shared__ GemmSmem<T, BM, BN> sm;
+  const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int a = find_segment(prefix, n_ids, mt);
   const FrontDev f = fronts[ids[a]];
@@ -93,7 +93,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int n = f.s + f.b;
   const int local = mt - prefix[a];
   const int chunk = local % tk.nch_f;
-  const int m0 = (local / tk.nch_f) * BM, n0 = nt * GT;
+  const int m0 = (local / tk.nch_f) * BM, n0 = nt * BN;
   const int kb = chunk * tk.kc_f;
   const int ke = min(f.s, kb + tk.kc_f);
   const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
@@ -101,7 +101,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* X = reinterpret_cast<const C*>(L.X);
   View<T> pv{FT, 1, (long long)n, n, f.s};
   View<T> qv{X + (long long)f.off * k, 1, (long long)k, k, f.s};
-  WaveAcc<T, BM> acc;
+  WaveAcc<T, BM, BN> acc;
   gemm_tile<T, BM, true, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
@@ -151,14 +151,14 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // backward: X(S) = Z(S) + (-F21 F11^-1)^T X(B); X(B) is read in place
 // through the front's boundary index list, the K (boundary) dimension
 // optionally split.  Fronts without boundary (roots) just copy Z(S).
-template <typename T, int BM>
+template <typename T, int BM, int BN>
 __global__ void __launch_bounds__(256)
 k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T, BM> sm;
-  const int ntn = (k + GT - 1) / GT;
+  __shared__ GemmSmem<T, BM, BN> sm;
+  const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int a = find_segment(prefix, n_ids, mt);
   const FrontDev f = fronts[ids[a]];
@@ -167,7 +167,7 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int n = f.s + f.b;
   const int local = mt - prefix[a];
   const int chunk = local % tk.nch_b;
-  const int m0 = (local / tk.nch_b) * BM, n0 = nt * GT;
+  const int m0 = (local / tk.nch_b) * BM, n0 = nt * BN;
   const int kb = chunk * tk.kc_b;
   const int ke = min(f.b, kb + tk.kc_b);
   const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
@@ -176,7 +176,7 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> pv{FT + f.s, (long long)n, 1, f.s, f.b};
   // Q(c, q) = X[B[q] k + c]
   View<T> qv{X, 1, (long long)k, k, f.b, L.bidx + f.bidx};
-  WaveAcc<T, BM> acc;
+  WaveAcc<T, BM, BN> acc;
   gemm_tile<T, BM, false, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   C* S = reinterpret_cast<C*>(scratch);
   const C* Z = reinterpret_cast<const C*>(L.Wt);
@@ -226,11 +226,19 @@ void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* pre
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, hipStream_t st) {
+                     void* scratch, int bn, hipStream_t st) {
   if (total_tiles <= 0) return;
-  const int ntn = (k + GT - 1) / GT;
-  hipLaunchKernelGGL(k_fwd_gemm<T>, dim3(total_tiles * ntn), dim3(256), 0, st, fr, ids,
-                     tasks, n, prefix, layers, k, scratch);
+  const int ntn = (k + bn - 1) / bn;
+  const dim3 grid(total_tiles * ntn);
+  if (bn == 16)
+    hipLaunchKernelGGL((k_fwd_gemm<T, 16>), grid, dim3(256), 0, st, fr, ids, tasks, n,
+                       prefix, layers, k, scratch);
+  else if (bn == 32)
+    hipLaunchKernelGGL((k_fwd_gemm<T, 32>), grid, dim3(256), 0, st, fr, ids, tasks, n,
+                       prefix, layers, k, scratch);
+  else
+    hipLaunchKernelGGL((k_fwd_gemm<T, 64>), grid, dim3(256), 0, st, fr, ids, tasks, n,
+                       prefix, layers, k, scratch);
 }
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
@@ -243,15 +251,21 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, hipStream_t st) {
+                     void* scratch, int bm, int bn, hipStream_t st) {
   if (total_tiles <= 0) return;
-  const int ntn = (k + GT - 1) / GT;
-  if (bm == 32)
-    hipLaunchKernelGGL((k_bwd_gemm<T, 32>), dim3(total_tiles * ntn), dim3(256), 0, st, fr,
-                       ids, tasks, n, prefix, layers, k, scratch);
-  else
-    hipLaunchKernelGGL((k_bwd_gemm<T, 64>), dim3(total_tiles * ntn), dim3(256), 0, st, fr,
-                       ids, tasks, n, prefix, layers, k, scratch);
+  // a 32 x 16 tile has fewer MFMA blocks than waves: use 32 columns there
+  if (bm == 32 && bn == 16) bn = 32;
+  const int ntn = (k + bn - 1) / bn;
+  const dim3 grid(total_tiles * ntn);
+#define HELM_BWD(BM_, BN_)                                                              \
+  hipLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_>), grid, dim3(256), 0, st, fr, ids, tasks, \
+                     n, prefix, layers, k, scratch)
+  if (bm == 32) {
+    if (bn == 32) HELM_BWD(32, 32); else HELM_BWD(32, 64);
+  } else {
+    if (bn == 16) HELM_BWD(64, 16); else if (bn == 32) HELM_BWD(64, 32); else HELM_BWD(64, 64);
+  }
+#undef HELM_BWD
 }
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
@@ -267,13 +281,13 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                                      int, const LayerDev*, int, hipStream_t);        \
   template void launch_fwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int*, int, const LayerDev*, int,       \
-                                   void*, hipStream_t);                              \
+                                   void*, int, hipStream_t);                         \
   template void launch_fwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);                      \
   template void launch_bwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int*, int, const LayerDev*, int,       \
-                                   void*, int, hipStream_t);                         \
+                                   void*, int, int, hipStream_t);                    \
   template void launch_bwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);

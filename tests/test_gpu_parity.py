@@ -186,3 +186,23 @@ def test_batch_composition_does_not_change_results():
     alone = s.solve_points(srcs[1:2]).cpu().numpy()
     mixed = s.solve_points(srcs).cpu().numpy()[1:2]
     assert relative_error(mixed.reshape(1, -1).T, alone.reshape(1, -1).T)[0] <= 1e-10
+
+
+def test_autotuned_tiles_give_the_same_solution():
+    """Column-tile widths chosen by timing (16 or 32 columns for a batch of
+    21) change the launch shapes, not the arithmetic of any column."""
+    import paper_1801_08655_amd as pt
+    wl = workload("layered-28")
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12), (11, 17, 15), (5, 20, 9), (16, 6, 18),
+            (12, 12, 21)] * 3
+    a = _solver(wl, "fp64")
+    ua = a.solve_points(srcs).cpu().numpy().reshape(len(srcs), -1).T
+    b = _solver(wl, "fp64", flags=pt._lib.HELM_FLAG_AUTOTUNE)
+    ub = b.solve_points(srcs).cpu().numpy().reshape(len(srcs), -1).T
+    assert relative_error(ub, ua).max() <= 1e-12
+    ch = b.tile_choices()
+    print(ch[:4])
+    assert ch and all(c["tuned"] for c in ch)
+    assert {c["fwd_bn"] for c in ch} <= {16, 32} and {c["bwd_bn"] for c in ch} <= {16, 32}
+    assert any(c["t_fwd_us"][0] > 0 and c["t_fwd_us"][1] > 0 for c in ch)
+    assert all(c["tuned"] == 0 for c in a.tile_choices())
