@@ -23,6 +23,7 @@ from .models import (
     WORKLOADS,
     serving_models,
     poisson_requests,
+    batched_problems,
     ServingRequest,
 )
 
@@ -36,6 +37,7 @@ __all__ = [
     "workload",
     "WORKLOADS",
     "serving_models",
+    "batched_problems",
     "poisson_requests",
     "ServingRequest",
 ]

@@ -252,6 +252,35 @@ def poisson_requests(count: int, rate: float, n_models: int, candidates,
     return out
 
 
+def batched_problems(count: int = 32, seed: int = 1804, n_lo: int = 64, n_hi: int = 160,
+                     pml: int = 8, alpha: int = 4, max_sources: int = 256) -> List[Workload]:
+    """Independent problems of the batched workload: n ~ U{n_lo..n_hi} per
+    cube, c = clip(1 + 0.2 N, 0.8, 1.2) with N smoothed normalised noise
+    (sigma 6 points, its own seed per problem), 10 points per wavelength at
+    c_min = 0.8, L = round(n / 10) layers, and R ~ U{1..max_sources} point
+    sources drawn without replacement from a 16 x 16 surface grid at depth
+    pml + 1.  All draws come from ``numpy.random.default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        mseed = int(rng.integers(0, 2**31 - 1))
+        dims, h = _cube(n)
+        L = max(1, int(round(n / 10)))
+        grid = surface_grid_sources(16, pml, n - 2 * pml, pml + 1)
+        r = int(rng.integers(1, min(max_sources, len(grid)) + 1))
+        pick = rng.choice(len(grid), size=r, replace=False)
+        srcs = [grid[j] for j in sorted(pick)]
+        out.append(Workload(
+            name=f"batch-{i}-n{n}", n=dims, h=h, pml=pml, n_layers=L, pml_local=alpha,
+            ppw=10.0, c_min=0.8, c_max=1.2,
+            model=(lambda d=dims, s_=mseed: smooth_random_model(d, 0.2, 6.0, 0.8, 1.2, s_)),
+            sources=srcs,
+            description=f"{n}^3 incl. {pml}-pt PML, smooth random c in [0.8, 1.2], "
+                        f"10 ppw, L={L}, R={r}"))
+    return out
+
+
 def workload(name: str) -> Workload:
     return WORKLOADS[name]()
 

@@ -91,6 +91,12 @@ int helm_server_create(const helm_server_options* opt, helm_server** out);
  * (`*slots_out`, nullable).  HELM_ENOMEM when not even one slot fits. */
 int helm_server_add_model(helm_server* s, helm_handle* h, int* model_id, int* slots_out);
 
+/* Stop serving a model: blocks until its queued and active columns have
+ * completed, then ends its lane and releases the lane's memory (the handle
+ * itself is not freed and may be freed by the caller afterwards).  Further
+ * submissions to the model fail with HELM_EINVAL. */
+int helm_server_remove_model(helm_server* s, int model_id);
+
 /* Queue a request of n_rhs point sources: node_index[c] is the linear index
  * (x fastest) of source c, amplitude[2c], amplitude[2c+1] its complex
  * amplitude (f = amplitude / h^3 at the node).  The solutions are written to

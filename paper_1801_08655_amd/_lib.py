@@ -26,7 +26,9 @@ EXPORTED = [
     # include/helm_serve.h
     "helm_server_default_options", "helm_server_create", "helm_server_add_model",
     "helm_server_submit", "helm_server_wait", "helm_server_poll", "helm_server_get_stats",
-    "helm_server_free",
+    "helm_server_free", "helm_server_remove_model",
+    # include/helm_batch.h
+    "helm_batch_default_options", "helm_solve_batch",
 ]
 HELM_FLAG_PROFILE = 1
 HELM_FLAG_NO_GRAPHS = 2
@@ -146,6 +148,38 @@ class helm_server_summary(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class helm_problem(ctypes.Structure):
+    _fields_ = [("grid", helm_grid), ("m", ctypes.c_void_p), ("omega", ctypes.c_double),
+                ("pml_width", ctypes.c_int), ("n_layers", ctypes.c_int),
+                ("n_rhs", ctypes.c_int), ("node_index", ctypes.c_void_p),
+                ("amplitude", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
+class helm_batch_options(ctypes.Structure):
+    _fields_ = [("opt", helm_options), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("slots", ctypes.c_int), ("max_resident", ctypes.c_int)]
+
+
+class helm_problem_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("slots", ctypes.c_int),
+                ("planned_bytes", ctypes.c_size_t), ("t_admit_ms", ctypes.c_double),
+                ("t_factored_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("factor_ms", ctypes.c_double), ("ir_steps_max", ctypes.c_int),
+                ("rel_residual_max", ctypes.c_double), ("est_error_max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class helm_batch_summary(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("factor_s", ctypes.c_double),
+                ("columns", ctypes.c_longlong), ("rhs_per_s", ctypes.c_double),
+                ("max_resident", ctypes.c_int), ("peak_planned_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -219,6 +253,15 @@ def lib():
     L.helm_server_get_stats.restype = I
     L.helm_server_free.argtypes = [SV]
     L.helm_server_free.restype = I
+    L.helm_server_remove_model.argtypes = [SV, I]
+    L.helm_server_remove_model.restype = I
+    L.helm_batch_default_options.argtypes = [ctypes.POINTER(helm_batch_options)]
+    L.helm_batch_default_options.restype = None
+    L.helm_solve_batch.argtypes = [I, ctypes.POINTER(helm_problem),
+                                   ctypes.POINTER(helm_batch_options),
+                                   ctypes.POINTER(helm_problem_info),
+                                   ctypes.POINTER(helm_batch_summary)]
+    L.helm_solve_batch.restype = I
     _lib = L
     return L
 

@@ -12,83 +12,16 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <mutex>
-#include <thread>
-#include <unordered_map>
-#include <vector>
 
-#include "../../include/helm_serve.h"
-#include "api_common.h"
+#include "serve_internal.h"
 
 namespace helm {
-namespace {
 
 double wall_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-
-struct Request {
-  int64_t id = 0;
-  int model = 0, n = 0;
-  std::vector<long long> nodes;
-  std::vector<double2> amps;
-  double2* out = nullptr;
-  int next_col = 0;       // next column to enter a slot
-  int done_cols = 0;
-  bool finished = false;
-  helm_request_info info{};
-};
-
-struct Slot {
-  Request* req = nullptr;
-  int col = -1;
-  int steps = 0;
-  double dprev = 0;
-};
-
-struct Lane {
-  int model = 0;
-  helm_handle* h = nullptr;
-  int K = 0;
-  size_t bytes = 0;
-  std::unique_ptr<Method> M;
-  DevMem F, U, R, D, nodes_d, amps_d;
-  std::vector<Slot> slots;
-  std::deque<Request*> queue;   // requests with columns not yet in a slot
-  std::vector<long long> node_h;
-  std::vector<double2> amp_h;
-  std::thread th;
-  int occupied() const {
-    int c = 0;
-    for (const Slot& s : slots) c += s.req != nullptr;
-    return c;
-  }
-};
-
-}  // namespace
-
-struct Server {
-  helm_server_options opt{};
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  bool stop = false;
-  std::vector<std::unique_ptr<Lane>> lanes;
-  std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
-  int64_t next_id = 1;
-  size_t reserved = 0;
-  double t0 = 0;
-  std::vector<double> lat;
-  long long req_done = 0, cols_done = 0, steps = 0;
-  double slot_steps = 0;
-  double t_first_submit = -1, t_last_done = 0;
-
-  void run_lane(Lane& ln);
-  void finish_column(Request* r, int status, int steps, double rel, double est);
-};
 
 // Account a finished column (lock held).
 void Server::finish_column(Request* r, int status, int nsteps, double rel, double est) {
@@ -124,8 +57,11 @@ void Server::run_lane(Lane& ln) {
     fresh.clear();
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || ln.occupied() > 0 || !ln.queue.empty(); });
+      cv_work.wait(lk, [&] {
+        return stop || ln.retire || ln.occupied() > 0 || !ln.queue.empty();
+      });
       if (stop) return;
+      if (ln.retire && ln.occupied() == 0 && ln.queue.empty()) return;
       // admission: queued columns take the free slots, oldest request first
       for (int s = 0; s < ln.K && !ln.queue.empty(); ++s) {
         if (ln.slots[s].req) continue;
@@ -232,6 +168,147 @@ void Server::run_lane(Lane& ln) {
   }
 }
 
+
+int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
+  Handle& H = h->impl;
+  HELM_REQUIRE(H.device == opt.device, HELM_EINVAL, "handle lives on another device");
+  HELM_HIP(hipSetDevice(H.device));
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& l : lanes) HELM_REQUIRE(l->gone || l->h != h, HELM_EINVAL, "handle already served");
+  const size_t per = plan_bytes_per_rhs(H.G, H.elem);
+  size_t free_b = 0, total_b = 0;
+  HELM_HIP(hipMemGetInfo(&free_b, &total_b));
+  // memory admission: the largest slot count whose workspace fits
+  int K = std::max(1, max_slots);
+  auto fits = [&](int k) {
+    const size_t ws = per * (size_t)k;
+    if (opt.hbm_budget_bytes) return reserved + H.bytes_factors + ws <= opt.hbm_budget_bytes;
+    return ws <= (size_t)(0.9 * (double)free_b);
+  };
+  while (K > 1 && !fits(K)) K /= 2;
+  HELM_REQUIRE(fits(K), HELM_ENOMEM, "model does not fit the server's memory budget");
+  std::unique_ptr<Lane> ln(new Lane);
+  ln->model = (int)lanes.size();
+  ln->h = h;
+  ln->K = K;
+  ln->bytes = H.bytes_factors + per * (size_t)K;
+  const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
+  const size_t vol = (size_t)N * K * sizeof(double2);
+  ln->F.alloc(vol);
+  ln->U.alloc(vol);
+  ln->R.alloc(vol);
+  ln->D.alloc(vol);
+  ln->nodes_d.alloc(K * sizeof(long long));
+  ln->amps_d.alloc(K * sizeof(double2));
+  for (DevMem* d : {&ln->F, &ln->U, &ln->R}) HELM_HIP(hipMemsetAsync(d->p, 0, vol, H.st));
+  HELM_HIP(hipStreamSynchronize(H.st));
+  h->method.reset();   // the lane's Method owns the solve workspace from here
+  ln->M.reset(new Method(H, K));
+  ln->slots.assign(K, Slot{});
+  ln->node_h.assign(K, 0);
+  ln->amp_h.assign(K, make_double2(0, 0));
+  Lane* lp = ln.get();
+  reserved += ln->bytes;
+  lanes.push_back(std::move(ln));
+  lp->th = std::thread([this, lp] { run_lane(*lp); });
+  if (slots_out) *slots_out = K;
+  return lp->model;
+}
+
+Request* Server::submit(int model, int n, const int64_t* nodes, const double* amps,
+                        double* u) {
+  Lane* ln = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    HELM_REQUIRE(!stop, HELM_EINVAL, "server is stopping");
+    HELM_REQUIRE(model >= 0 && model < (int)lanes.size() && !lanes[model]->retire,
+                 HELM_EINVAL, "unknown model");
+    ln = lanes[model].get();
+  }
+  const Geometry& G = ln->h->impl.G;
+  const long long N = (long long)G.nx * G.ny * G.nz;
+  std::unique_ptr<Request> r(new Request);
+  r->n = n;
+  r->model = model;
+  r->out = reinterpret_cast<double2*>(u);
+  r->nodes.resize(n);
+  r->amps.resize(n);
+  for (int c = 0; c < n; ++c) {
+    HELM_REQUIRE(nodes[c] >= 0 && nodes[c] < N, HELM_EINVAL, "point source outside the grid");
+    HELM_REQUIRE(std::isfinite(amps[2 * c]) && std::isfinite(amps[2 * c + 1]), HELM_EINVAL,
+                 "non-finite amplitude");
+    r->nodes[c] = nodes[c];
+    r->amps[c] = make_double2(amps[2 * c], amps[2 * c + 1]);
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  r->id = next_id++;
+  r->info.status = HELM_OK;
+  r->info.n_rhs = n;
+  r->info.model = model;
+  r->info.t_submit_ms = wall_ms() - t0;
+  r->info.t_first_ms = -1;
+  if (t_first_submit < 0) t_first_submit = r->info.t_submit_ms;
+  Request* rp = r.get();
+  reqs.emplace(r->id, std::move(r));
+  if (n == 0) {
+    rp->finished = true;
+    rp->info.t_first_ms = rp->info.t_done_ms = rp->info.t_submit_ms;
+    cv_done.notify_all();
+  } else {
+    ln->queue.push_back(rp);
+    cv_work.notify_all();
+  }
+  return rp;
+}
+
+void Server::remove_model(int model) {
+  Lane* ln = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    HELM_REQUIRE(model >= 0 && model < (int)lanes.size() && !lanes[model]->retire,
+                 HELM_EINVAL, "unknown model");
+    ln = lanes[model].get();
+    ln->retire = true;
+  }
+  cv_work.notify_all();
+  if (ln->th.joinable()) ln->th.join();
+  Handle& H = ln->h->impl;
+  (void)hipSetDevice(H.device);
+  HELM_HIP(hipStreamSynchronize(H.st));
+  ln->M.reset();
+  for (DevMem* d : {&ln->F, &ln->U, &ln->R, &ln->D, &ln->nodes_d, &ln->amps_d}) d->release();
+  std::lock_guard<std::mutex> lk(mu);
+  reserved -= ln->bytes;
+  ln->gone = true;
+}
+
+void Server::shutdown() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;
+  }
+  cv_work.notify_all();
+  for (auto& l : lanes)
+    if (l->th.joinable()) l->th.join();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& kv : reqs) {
+      Request* r = kv.second.get();
+      if (!r->finished) {
+        r->finished = true;
+        r->info.status = HELM_EINVAL;
+      }
+    }
+    cv_done.notify_all();
+  }
+  for (auto& l : lanes) {
+    if (l->gone) continue;
+    (void)hipSetDevice(l->h->impl.device);
+    (void)hipStreamSynchronize(l->h->impl.st);
+    l->M.reset();
+  }
+}
+
 }  // namespace helm
 
 struct helm_server {
@@ -268,51 +345,15 @@ int helm_server_create(const helm_server_options* opt, helm_server** out) {
 int helm_server_add_model(helm_server* sv, helm_handle* h, int* model_id, int* slots_out) {
   return guard([&] {
     HELM_REQUIRE(sv && h && model_id, HELM_EINVAL, "null argument");
-    Server& S = sv->impl;
-    Handle& H = h->impl;
-    HELM_REQUIRE(H.device == S.opt.device, HELM_EINVAL, "handle lives on another device");
-    HELM_HIP(hipSetDevice(H.device));
-    std::lock_guard<std::mutex> lk(S.mu);
-    for (auto& l : S.lanes) HELM_REQUIRE(l->h != h, HELM_EINVAL, "handle already served");
-    const size_t per = plan_bytes_per_rhs(H.G, H.elem);
-    size_t free_b = 0, total_b = 0;
-    HELM_HIP(hipMemGetInfo(&free_b, &total_b));
-    // memory admission: the largest slot count whose workspace fits
-    int K = S.opt.slots;
-    auto fits = [&](int k) {
-      const size_t ws = per * (size_t)k;
-      if (S.opt.hbm_budget_bytes)
-        return S.reserved + H.bytes_factors + ws <= S.opt.hbm_budget_bytes;
-      return ws <= (size_t)(0.9 * (double)free_b);
-    };
-    while (K > 1 && !fits(K)) K /= 2;
-    HELM_REQUIRE(fits(K), HELM_ENOMEM, "model does not fit the server's memory budget");
-    std::unique_ptr<Lane> ln(new Lane);
-    ln->model = (int)S.lanes.size();
-    ln->h = h;
-    ln->K = K;
-    ln->bytes = H.bytes_factors + per * (size_t)K;
-    const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
-    const size_t vol = (size_t)N * K * sizeof(double2);
-    ln->F.alloc(vol);
-    ln->U.alloc(vol);
-    ln->R.alloc(vol);
-    ln->D.alloc(vol);
-    ln->nodes_d.alloc(K * sizeof(long long));
-    ln->amps_d.alloc(K * sizeof(double2));
-    for (DevMem* d : {&ln->F, &ln->U, &ln->R}) HELM_HIP(hipMemsetAsync(d->p, 0, vol, H.st));
-    HELM_HIP(hipStreamSynchronize(H.st));
-    h->method.reset();   // the lane's Method owns the solve workspace from here
-    ln->M.reset(new Method(H, K));
-    ln->slots.assign(K, Slot{});
-    ln->node_h.assign(K, 0);
-    ln->amp_h.assign(K, make_double2(0, 0));
-    Lane* lp = ln.get();
-    S.reserved += ln->bytes;
-    S.lanes.push_back(std::move(ln));
-    lp->th = std::thread([&S, lp] { S.run_lane(*lp); });
-    *model_id = lp->model;
-    if (slots_out) *slots_out = K;
+    *model_id = sv->impl.add_model(h, sv->impl.opt.slots, slots_out);
+    return HELM_OK;
+  });
+}
+
+int helm_server_remove_model(helm_server* sv, int model_id) {
+  return guard([&] {
+    HELM_REQUIRE(sv, HELM_EINVAL, "null server");
+    sv->impl.remove_model(model_id);
     return HELM_OK;
   });
 }
@@ -322,50 +363,7 @@ int helm_server_submit(helm_server* sv, int model_id, int n_rhs, const int64_t* 
   return guard([&] {
     HELM_REQUIRE(sv && request_id && n_rhs >= 0, HELM_EINVAL, "bad argument");
     HELM_REQUIRE(n_rhs == 0 || (node_index && amplitude && u), HELM_EINVAL, "null argument");
-    Server& S = sv->impl;
-    std::unique_ptr<Request> r(new Request);
-    Lane* ln = nullptr;
-    {
-      std::lock_guard<std::mutex> lk(S.mu);
-      HELM_REQUIRE(!S.stop, HELM_EINVAL, "server is stopping");
-      HELM_REQUIRE(model_id >= 0 && model_id < (int)S.lanes.size(), HELM_EINVAL,
-                   "unknown model");
-      ln = S.lanes[model_id].get();
-    }
-    const Geometry& G = ln->h->impl.G;
-    const long long N = (long long)G.nx * G.ny * G.nz;
-    r->n = n_rhs;
-    r->model = model_id;
-    r->out = reinterpret_cast<double2*>(u);
-    r->nodes.resize(n_rhs);
-    r->amps.resize(n_rhs);
-    for (int c = 0; c < n_rhs; ++c) {
-      HELM_REQUIRE(node_index[c] >= 0 && node_index[c] < N, HELM_EINVAL,
-                   "point source outside the grid");
-      HELM_REQUIRE(std::isfinite(amplitude[2 * c]) && std::isfinite(amplitude[2 * c + 1]),
-                   HELM_EINVAL, "non-finite amplitude");
-      r->nodes[c] = node_index[c];
-      r->amps[c] = make_double2(amplitude[2 * c], amplitude[2 * c + 1]);
-    }
-    std::lock_guard<std::mutex> lk(S.mu);
-    r->id = S.next_id++;
-    r->info.status = HELM_OK;
-    r->info.n_rhs = n_rhs;
-    r->info.model = model_id;
-    r->info.t_submit_ms = wall_ms() - S.t0;
-    r->info.t_first_ms = -1;
-    if (S.t_first_submit < 0) S.t_first_submit = r->info.t_submit_ms;
-    *request_id = r->id;
-    Request* rp = r.get();
-    S.reqs.emplace(r->id, std::move(r));
-    if (n_rhs == 0) {
-      rp->finished = true;
-      rp->info.t_first_ms = rp->info.t_done_ms = rp->info.t_submit_ms;
-      S.cv_done.notify_all();
-    } else {
-      ln->queue.push_back(rp);
-      S.cv_work.notify_all();
-    }
+    *request_id = sv->impl.submit(model_id, n_rhs, node_index, amplitude, u)->id;
     return HELM_OK;
   });
 }
@@ -434,30 +432,7 @@ int helm_server_get_stats(helm_server* sv, helm_server_summary* out) {
 int helm_server_free(helm_server* sv) {
   return guard([&] {
     if (!sv) return HELM_OK;
-    Server& S = sv->impl;
-    {
-      std::lock_guard<std::mutex> lk(S.mu);
-      S.stop = true;
-    }
-    S.cv_work.notify_all();
-    for (auto& l : S.lanes)
-      if (l->th.joinable()) l->th.join();
-    {
-      std::lock_guard<std::mutex> lk(S.mu);
-      for (auto& kv : S.reqs) {
-        Request* r = kv.second.get();
-        if (!r->finished) {
-          r->finished = true;
-          r->info.status = HELM_EINVAL;
-        }
-      }
-      S.cv_done.notify_all();
-    }
-    for (auto& l : S.lanes) {
-      (void)hipSetDevice(l->h->impl.device);
-      (void)hipStreamSynchronize(l->h->impl.st);
-      l->M.reset();
-    }
+    sv->impl.shutdown();
     delete sv;
     return HELM_OK;
   });

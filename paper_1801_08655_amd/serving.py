@@ -95,6 +95,10 @@ class Server:
               "helm_server_submit")
         return Request(self, rid.value, u, r)
 
+    def remove_model(self, model: int):
+        """Wait for the model's queued columns, then release its lane."""
+        check(lib().helm_server_remove_model(self._s, model), "helm_server_remove_model")
+
     def stats(self) -> dict:
         s = _lib.helm_server_summary()
         check(lib().helm_server_get_stats(self._s, ctypes.byref(s)), "helm_server_get_stats")

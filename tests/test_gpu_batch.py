@@ -1,0 +1,83 @@
+"""Batched solves of independent problems on the GPU, each checked against
+the oracle's global direct solve of that problem (relative l2 <= 1e-6 for
+complex64 factors with FP64 refinement), with admission limited by a
+resident count and by a memory budget."""
+
+import numpy as np
+import pytest
+
+from helm_inputs import omega_for_ppw, smooth_random_model
+from oracle.direct import SparseLU, relative_error
+from oracle.discretization import Problem as OracleProblem, point_source_rhs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.filterwarnings("ignore::DeprecationWarning")]
+
+torch = pytest.importorskip("torch")
+
+PML_C = 25.0
+
+
+def _problems():
+    from paper_1801_08655_amd.batch import Problem
+    out = []
+    specs = [(20, 2, 1, 11), (24, 3, 5, 12), (26, 4, 3, 13), (28, 3, 9, 14)]
+    for n, L, R, seed in specs:
+        h = 1.0 / (n - 1)
+        m = smooth_random_model((n, n, n), 0.2, 3.0, 0.8, 1.2, seed)
+        om = omega_for_ppw(0.8, h, 10.0)
+        rng = np.random.default_rng(seed)
+        src = [tuple(int(v) for v in rng.integers(5, n - 5, 3)) for _ in range(R)]
+        amp = rng.standard_normal(R) + 1j * rng.standard_normal(R)
+        out.append(Problem(m, h, om, 4, L, src, amp))
+    return out
+
+
+def _reference(p):
+    pb = OracleProblem(p.m, p.h, p.omega, p.pml, PML_C)
+    F = point_source_rhs(pb.shape, p.sources, p.h) * np.asarray(p.amplitudes)[None, :]
+    return SparseLU(pb.operator()).solve(F)
+
+
+@pytest.fixture(scope="module")
+def probs():
+    ps = _problems()
+    return ps, [_reference(p) for p in ps]
+
+
+def test_batch_matches_oracle_with_two_resident(probs):
+    from paper_1801_08655_amd.batch import solve_batch
+    ps, refs = probs
+    res, summ = solve_batch(ps, slots=4, max_resident=2, precision="mixed", pml_local=3,
+                            pml_C=PML_C, err_target=1e-6)
+    print(summ)
+    for (u, inf), ref, p in zip(res, refs, ps):
+        err = relative_error(u.cpu().numpy().reshape(len(p.sources), -1).T, ref)
+        print(inf, err.max())
+        assert inf["status"] == 0 and err.max() <= 1e-6
+    assert summ["columns"] == sum(len(p.sources) for p in ps)
+    assert summ["max_resident"] == 2
+    # the third problem was admitted only after one of the first two finished
+    assert res[2][1]["t_admit_ms"] >= min(res[0][1]["t_done_ms"], res[1][1]["t_done_ms"])
+
+
+def test_batch_memory_budget_refuses_only_what_cannot_fit(probs):
+    import paper_1801_08655_amd as pt
+    from paper_1801_08655_amd.batch import solve_batch
+    ps, refs = probs
+    needs = []
+    for p in ps:
+        n = p.m.shape[0]
+        pl = pt.plan((n, n, n), p.pml, p.n_layers, pml_local=3, precision="fp64")
+        needs.append(pl["factor_bytes"] + pl["bytes_per_rhs"] * min(len(p.sources), 8))
+    budget = int(sorted(needs)[-2] * 1.05)       # the largest problem cannot fit
+    big = int(np.argmax(needs))
+    res, summ = solve_batch(ps, slots=8, hbm_budget_bytes=budget, precision="fp64",
+                            pml_local=3, pml_C=PML_C, gmres_tol=1e-10)
+    for i, ((u, inf), ref, p) in enumerate(zip(res, refs, ps)):
+        if i == big:
+            assert inf["status"] == pt.HELM_ENOMEM and u is None
+            continue
+        err = relative_error(u.cpu().numpy().reshape(len(p.sources), -1).T, ref)
+        assert inf["status"] == 0 and err.max() <= 1e-9
+    assert summ["peak_planned_bytes"] <= budget

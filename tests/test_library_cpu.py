@@ -149,3 +149,20 @@ def test_server_entry_points_reject_null_arguments():
     o = _lib.helm_server_options()
     L.helm_server_default_options(ctypes.byref(o))
     assert o.slots == 32 and o.hbm_budget_bytes == 0
+
+
+def test_batch_entry_point_rejects_bad_problems():
+    """Argument checks of helm_solve_batch that return before any device call."""
+    L = pt.lib()
+    assert L.helm_solve_batch(1, None, None, None, None) == pt.HELM_EINVAL
+    arr = (_lib.helm_problem * 1)()
+    arr[0] = _lib.helm_problem(_lib.helm_grid(8, 8, 8, 1 / 7.0), None, 1.0, 2, 1, 0,
+                               None, None, None)
+    assert L.helm_solve_batch(1, arr, None, None, None) == pt.HELM_EINVAL   # null model
+    m = (ctypes.c_double * 512)()
+    arr[0] = _lib.helm_problem(_lib.helm_grid(8, 8, 8, 1 / 7.0), ctypes.addressof(m), 1.0,
+                               2, 1, 3, None, None, None)
+    assert L.helm_solve_batch(1, arr, None, None, None) == pt.HELM_EINVAL   # null sources
+    bo = _lib.helm_batch_options()
+    L.helm_batch_default_options(ctypes.byref(bo))
+    assert bo.slots == 64 and bo.opt.precision == pt.HELM_MIXED
