@@ -41,10 +41,15 @@ def parse():
     ap.add_argument("--workload", default="layered-200")
     ap.add_argument("--rhs", type=int, default=64)
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-warmup", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", default=True,
                     help="time kernel classes with HIP events (roofline)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="tile widths from the batch width instead of measured per depth")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead: 3 resident 160^3 models, Poisson requests")
     ap.add_argument("--serve-requests", type=int, default=12)
@@ -86,26 +91,40 @@ def percentile(v, q):
     return v[i]
 
 
-def roofline(stats, precision):
+def measured_traffic(kernel_class, workload):
+    """HBM bytes per launch of a kernel class from the calibrated rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs kept in profiles/, if they were taken on the
+    current kernel sources (else None)."""
+    from paper_1801_08655_amd.rocprof_summary import kernel_sources_hash, read_traffic
+    t = read_traffic(os.path.join(ROOT, "profiles", f"traffic_{kernel_class}_{workload}.txt"))
+    if not t or t.get("sources_sha256") != kernel_sources_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def roofline(stats, precision, workload):
     """Dominant (longest) kernel class: achieved flops per launch-second vs
     the matrix-core peak of its arithmetic type."""
     best = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
     name, st = best
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     flops_per_launch = st["flops"] / max(st["launches"], 1)
+    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
+    traffic = measured_traffic(name, workload)
     if flops_per_launch > 0:
         achieved = flops_per_launch / (avg_ms * 1e-3)
         peak = PEAK["fp32_mfma"] if precision == "mixed" else PEAK["fp64_mfma"]
         return {"kernel": name, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "launches": st["launches"],
+                "traffic": traffic, "launches": st["launches"],
                 "avg_launch_ms": avg_ms,
                 "flops_per_launch": flops_per_launch,
-                "bytes_per_launch": st["bytes"] / max(st["launches"], 1)}
-    achieved = st["bytes"] / max(st["launches"], 1) / (avg_ms * 1e-3)
+                "bytes_per_launch": bytes_per_launch,
+                "traffic_over_algorithmic": (traffic / bytes_per_launch) if traffic else None}
+    achieved = bytes_per_launch / (avg_ms * 1e-3)
     return {"kernel": name, "bound": "hbm", "achieved": achieved / 1e9,
             "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "frac": achieved / PEAK["hbm"],
-            "traffic": None, "launches": st["launches"], "avg_launch_ms": avg_ms}
+            "traffic": traffic, "launches": st["launches"], "avg_launch_ms": avg_ms}
 
 
 def cpu_baseline():
@@ -284,7 +303,15 @@ def main():
     m = wl.m()
     srcs = wl.point_sources(args.rhs)
     R = len(srcs)
+    if args.copy_calibration_mib:
+        x = torch.ones(args.copy_calibration_mib << 17, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     flags = pt._lib.HELM_FLAG_PROFILE if args.profile else 0
+    if not args.no_autotune:
+        flags |= pt._lib.HELM_FLAG_AUTOTUNE
     common = dict(pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64, flags=flags)
     extra = {}
 
@@ -299,7 +326,8 @@ def main():
         torch.cuda.synchronize()
         f64_factor = time.perf_counter() - t0
         log(f"[fp64] factorized in {f64_factor:.2f}s; solving R={R}")
-        u_ref, info64, tot64, lat64 = timed_solves(s64, srcs, args.fp64_steps, 0, torch)
+        u_ref, info64, tot64, lat64 = timed_solves(s64, srcs, args.fp64_steps,
+                                                   args.fp64_warmup, torch)
         fp64 = {"value": R * args.fp64_steps / tot64, "factor_s": f64_factor,
                 "ms_per_step": 1e3 * tot64 / args.fp64_steps,
                 "gmres_iters": info64["gmres_iters"],
@@ -327,7 +355,8 @@ def main():
     if u_ref is not None:
         d = (u - u_ref).reshape(R, -1).norm(dim=1) / u_ref.reshape(R, -1).norm(dim=1)
         err = float(d.max())
-    rl = roofline({k: v for k, v in kstats.items() if k.startswith("solve_")}, "mixed")
+    rl = roofline({k: v for k, v in kstats.items() if k.startswith("solve_")}, "mixed",
+                  wl.name)
     out = {
         "metric": METRIC,
         "value": value,

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 
 namespace helm {
@@ -85,7 +86,9 @@ hipEvent_t Handle::prof_begin() {
     e = ev_free.back();
     ev_free.pop_back();
   } else {
-    HELM_HIP(hipEventCreate(&e));
+    // timing only: no system-scope fence (cache writeback / invalidate)
+    // between the kernels being timed
+    HELM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   HELM_HIP(hipEventRecord(e, st));
   return e;
@@ -686,6 +689,13 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
     TileChoice& c = plan[d];
     c.tuned = true;
     if (D.n == 0) continue;
+    auto q = [](double v) { return (long long)std::lround(4.0 * std::log2(1.0 + v)); };
+    const std::vector<long long> bucket{k, D.n, q(D.sum_s / D.n), q(D.sum_b / D.n), D.bwd_bm};
+    auto hit = tuned.find(bucket);
+    if (hit != tuned.end()) {
+      c = hit->second;
+      continue;
+    }
     double bf = 1e30, bb = 1e30;
     for (int w = 0; w < 3; ++w) {
       const int bn = widths[w];
@@ -706,6 +716,7 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
       c.t_bwd[w] = t;
       if (t < bb) { bb = t; c.bwd_bn = bn; }
     }
+    tuned[bucket] = c;
   }
   HELM_HIP(hipGetLastError());
   {

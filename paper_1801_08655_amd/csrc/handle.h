@@ -119,6 +119,9 @@ struct Handle {
     double t_fwd[3] = {0, 0, 0}, t_bwd[3] = {0, 0, 0};   // us per width 16/32/64
   };
   std::map<GraphKey, std::vector<TileChoice>> tiles;
+  // measured choices shared by every depth list of the same front-size
+  // bucket: (k, fronts, log2 mean s and mean b in quarter steps, bwd row tile)
+  std::map<std::vector<long long>, TileChoice> tuned;
   const std::vector<TileChoice>& tile_plan(const LayerSet& set, int k);
   template <typename T> void autotune_t(const LayerSet& set, int k,
                                         std::vector<TileChoice>& plan);

@@ -1,0 +1,168 @@
+"""Summaries of rocprofv3 output for the solver's kernels.
+
+    python -m paper_1801_08655_amd.rocprof_summary stats <dir> [--match REGEX]
+    python -m paper_1801_08655_amd.rocprof_summary traffic <fetch_dir> <write_dir>
+        --kernel REGEX --copy REGEX --copy-bytes N --class NAME --out FILE
+
+``stats`` prints the per-kernel table of a ``--kernel-trace --stats`` run.
+``traffic`` combines a ``--pmc FETCH_SIZE`` run and a ``--pmc WRITE_SIZE``
+run: the counters of a plain device copy of known size calibrate the
+counters (bytes per counted KiB), and the kernels matching ``--kernel`` get
+their HBM bytes per dispatch from the calibrated counters.  The result is
+written as ``key: value`` lines, with a hash of the substitution kernel
+sources so that a later run can tell whether the figures still describe
+the code.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/kernels_solve.hip", "csrc/kernels_common.h", "csrc/kernels.h"]
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return hits
+
+
+def read_stats(d):
+    rows = []
+    for path in _find(d, "*kernel_stats.csv"):
+        with open(path) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def read_counters(d, counter):
+    """[(kernel name, value)] of every dispatch for one counter, in dispatch
+    order (values of one dispatch summed over its records)."""
+    acc = {}
+    for path in _find(d, "*counter_collection.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    key = int(r.get("Dispatch_Id", 0) or 0)
+                    name, v = acc.get(key, (r["Kernel_Name"], 0.0))
+                    acc[key] = (name, v + float(r["Counter_Value"]))
+    return [acc[k] for k in sorted(acc)]
+
+
+def read_trace(d):
+    """[(kernel name, duration ns)] of every dispatch, in dispatch order."""
+    rows = []
+    for path in _find(d, "*kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r.get("Dispatch_Id", 0) or 0), r["Kernel_Name"],
+                             int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    return [(n, t) for _, n, t in rows]
+
+
+def cmd_stats(a):
+    if a.last:
+        # the last N dispatches of the matching kernels: the timed steps of a
+        # run whose earlier dispatches were warm-up and one-time set-up
+        rx = re.compile(a.match)
+        sel = [t for n, t in read_trace(a.dir) if rx.search(n)][-a.last:]
+        print(f"last {len(sel)} dispatches matching `{a.match}`: "
+              f"average {sum(sel) / len(sel) / 1e3:.2f} us, total {sum(sel) / 1e6:.3f} ms")
+        return
+    rows = read_stats(a.dir)
+    rx = re.compile(a.match) if a.match else None
+    print("| kernel | calls | total ms | avg us | % |")
+    print("|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        if rx and not rx.search(r["Name"]):
+            continue
+        print(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+              f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+
+
+def cmd_traffic(a):
+    kx, cx = re.compile(a.kernel), re.compile(a.copy)
+    res = {"kernel_class": a.cls, "kernel_regex": a.kernel,
+           "sources_sha256": kernel_sources_hash(), "copy_bytes": a.copy_bytes}
+    for counter, d in (("FETCH_SIZE", a.fetch_dir), ("WRITE_SIZE", a.write_dir)):
+        vals = read_counters(d, counter)
+        ker = [v for n, v in vals if kx.search(n)]
+        if a.last:
+            ker = ker[-a.last:]
+        cop = [v for n, v in vals if cx.search(n) and not kx.search(n)]
+        if not ker or not cop:
+            raise SystemExit(f"{counter}: {len(ker)} kernel and {len(cop)} copy dispatches")
+        copy_kib = max(cop)                      # the calibration copy is the largest
+        scale = a.copy_bytes / copy_kib          # bytes per counted KiB
+        key = counter.lower()
+        res[f"{key}_dispatches"] = len(ker)
+        res[f"{key}_kib_per_dispatch"] = sum(ker) / len(ker)
+        res[f"{key}_copy_kib"] = copy_kib
+        res[f"{key}_bytes_per_kib"] = scale
+        res[f"{key}_bytes_per_dispatch"] = sum(ker) / len(ker) * scale
+    res["hbm_bytes_per_launch"] = res["fetch_size_bytes_per_dispatch"] + \
+        res["write_size_bytes_per_dispatch"]
+    with open(a.out, "w") as fh:
+        for k, v in res.items():
+            fh.write(f"{k}: {v}\n")
+        if a.note:
+            fh.write(f"note: {a.note}\n")
+    print(open(a.out).read())
+
+
+def read_traffic(path):
+    """Parsed ``key: value`` file written by ``traffic`` (None if missing)."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if ": " in line:
+                k, v = line.rstrip("\n").split(": ", 1)
+                try:
+                    out[k] = float(v)
+                except ValueError:
+                    out[k] = v
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--match", default=None)
+    s.add_argument("--last", type=int, default=0)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--class", dest="cls", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--note", default="")
+    t.add_argument("--last", type=int, default=0)
+    a = ap.parse_args(argv)
+    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
