@@ -351,6 +351,16 @@ def main():
     u, info, total, lat = timed_solves(s, srcs, args.steps, args.warmup, torch)
     kstats = s.kernel_stats()
     value = R * args.steps / total
+    # the same step with the 64 solution volumes handed back to host memory
+    # (pinned): the PCIe-inclusive rate, reported beside the HBM-resident one
+    u_host = torch.empty(u.shape, dtype=u.dtype, pin_memory=True)
+    torch.cuda.synchronize()
+    t_copy = time.perf_counter()
+    u_host.copy_(u)
+    t_copy = time.perf_counter() - t_copy
+    del u_host
+    pcie = {"d2h_s": t_copy, "bytes": u.numel() * u.element_size(),
+            "rhs_per_s": R / (total / args.steps + t_copy)}
     err = None
     if u_ref is not None:
         d = (u - u_ref).reshape(R, -1).norm(dim=1) / u_ref.reshape(R, -1).norm(dim=1)
@@ -386,6 +396,7 @@ def main():
         "ir_residual": info["ir_residual"],
         "ir_gmres_iters": info["ir_gmres_iters"],
         "layer_solves_per_step": info["layer_solves"],
+        "pcie_inclusive": pcie,
         "roofline": rl,
         "kernels": kstats,
         "factor_kernels": fstats,
