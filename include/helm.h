@@ -185,15 +185,17 @@ int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count
 /* Column-tile choices of the substitution GEMMs: one record per (layer set,
  * batch width k, depth of the front trees), for the sets used so far.  A
  * layer set is described by its number of layers.  fwd_bn / bwd_bn are the
- * tile widths in use (16, 32 or 64 columns); when the choice was measured
+ * tile widths in use: 16, 32 or 64 columns on the matrix cores, or 1 for the
+ * vector path (default up to 2 columns, a candidate up to 4); when the
+ * choice was measured
  * (HELM_FLAG_AUTOTUNE), t_fwd_us / t_bwd_us hold the timed launch of each
- * width in the order 16, 32, 64 (0 where a width was not tried).  Writes up
- * to `max` records and the total to *count. */
+ * width in the order 1, 16, 32, 64 (0 where a width was not tried).  Writes
+ * up to `max` records and the total to *count. */
 typedef struct {
   int    set_layers, k, depth, fronts;
   double mean_s, mean_b;   /* mean pivot / boundary size of the depth's fronts */
   int    fwd_bn, bwd_bn, bwd_bm, tuned;
-  double t_fwd_us[3], t_bwd_us[3];
+  double t_fwd_us[4], t_bwd_us[4];
 } helm_tile_choice;
 
 int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count);

@@ -289,7 +289,7 @@ int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count
           o.bwd_bn = (D.bwd_bm == 32 && c.bwd_bn == 16) ? 32 : c.bwd_bn;
           o.bwd_bm = D.bwd_bm;
           o.tuned = c.tuned ? 1 : 0;
-          for (int w = 0; w < 3; ++w) {
+          for (int w = 0; w < 4; ++w) {
             o.t_fwd_us[w] = c.t_fwd[w];
             o.t_bwd_us[w] = c.t_bwd[w];
           }

@@ -626,9 +626,35 @@ void Handle::solve_layers(const LayerSet& set, int k) {
   solve_bytes += solve_elems(set) * (double)elem;
 }
 
-// Tile width from the batch width alone: the narrowest of 16 / 32 / 64
-// columns that covers k (wider batches take several 64-column tiles).
-static int width_bn(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+// Tile width from the batch width alone: the vector path for k <= 2 (up to
+// 4 columns it is one of the measured candidates), else the narrowest MFMA
+// tile of 16 / 32 / 64 columns that covers k (wider batches take several
+// 64-column tiles).
+static int mfma_bn(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+static int width_bn(int k) { return k <= 2 ? 1 : mfma_bn(k); }
+
+// One depth's forward / backward GEMM launch with column width bn (1: the
+// vector path).
+template <typename T>
+void Handle::launch_fwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
+                        void* scr, int bn) {
+  if (bn == 1)
+    kern::launch_fwd_gemv<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
+                             D.pF.as<int>(), D.tF, ld, k, scr, st);
+  else
+    kern::launch_fwd_gemm<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
+                             D.pF.as<int>(), D.tF, ld, k, scr, bn, st);
+}
+template <typename T>
+void Handle::launch_bwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
+                        void* scr, int bn) {
+  if (bn == 1)
+    kern::launch_bwd_gemv<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
+                             D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm, st);
+  else
+    kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
+                             D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm, bn, st);
+}
 
 const std::vector<Handle::TileChoice>& Handle::tile_plan(const LayerSet& set, int k) {
   GraphKey key{&set, k};
@@ -669,7 +695,7 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
   hipEvent_t e0, e1;
   HELM_HIP(hipEventCreate(&e0));
   HELM_HIP(hipEventCreate(&e1));
-  const int widths[3] = {16, 32, 64};
+  const int widths[4] = {1, 16, 32, 64};
   auto time_us = [&](auto&& launch) {
     double best = 1e30;
     for (int rep = 0; rep < 3; ++rep) {
@@ -683,7 +709,7 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
     }
     return best;
   };
-  const int dflt = width_bn(k);
+  const int widest = mfma_bn(k);
   for (int d = 0; d <= set.max_depth; ++d) {
     const DepthList& D = *set.depth[d];
     TileChoice& c = plan[d];
@@ -697,21 +723,19 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
       continue;
     }
     double bf = 1e30, bb = 1e30;
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < 4; ++w) {
       const int bn = widths[w];
-      if (bn > dflt) continue;
+      if (bn > widest || (bn == 1 && k > 4)) continue;
       if (D.nL > 0) {
         double t = time_us([&] {
-          kern::launch_fwd_gemm<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
-                                   D.pF.as<int>(), D.tF, ld, k, scr, bn, st);
+          launch_fwd<T>(D, fr, ld, k, scr, bn);
         });
         c.t_fwd[w] = t;
         if (t < bf) { bf = t; c.fwd_bn = bn; }
       }
       if (D.bwd_bm == 32 && bn == 16) continue;   // not a distinct tile
       double t = time_us([&] {
-        kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
-                                 D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm, bn, st);
+        launch_bwd<T>(D, fr, ld, k, scr, bn);
       });
       c.t_bwd[w] = t;
       if (t < bb) { bb = t; c.bwd_bn = bn; }
@@ -753,8 +777,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
       const int* ids = D.idsL.as<int>();
       const SolveTask* tk = D.tasksL.as<SolveTask>();
       a = prof_begin();
-      kern::launch_fwd_gemm<T>(fr, ids, tk, D.nL, D.pF.as<int>(), D.tF, ld, k, scr,
-                               tp[d].fwd_bn, st);
+      launch_fwd<T>(D, fr, ld, k, scr, tp[d].fwd_bn);
       // factor block read once; pivots read, Z written, boundary updates
       // written and the children's updates of the boundary rows read
       prof_end(K_FWD_GEMM, a, 8.0 * D.fl_sbs * kk,
@@ -772,8 +795,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     const int* ids = D.ids.as<int>();
     const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin();
-    kern::launch_bwd_gemm<T>(fr, ids, tk, D.n, D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm,
-                             tp[d].bwd_bn, st);
+    launch_bwd<T>(D, fr, ld, k, scr, tp[d].bwd_bn);
     // factor block read once; X(B) rows read, Z(S) read, X(S) written
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);

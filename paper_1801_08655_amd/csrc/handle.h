@@ -112,11 +112,12 @@ struct Handle {
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
   void clear_graphs();
-  // column-tile widths of the substitution GEMMs per depth, per (set, k)
+  // column-tile widths of the substitution GEMMs per depth, per (set, k);
+  // width 1 is the vector path (k <= 4)
   struct TileChoice {
     int fwd_bn = 64, bwd_bn = 64;
     bool tuned = false;
-    double t_fwd[3] = {0, 0, 0}, t_bwd[3] = {0, 0, 0};   // us per width 16/32/64
+    double t_fwd[4] = {0, 0, 0, 0}, t_bwd[4] = {0, 0, 0, 0};   // us per width 1/16/32/64
   };
   std::map<GraphKey, std::vector<TileChoice>> tiles;
   // measured choices shared by every depth list of the same front-size
@@ -125,6 +126,10 @@ struct Handle {
   const std::vector<TileChoice>& tile_plan(const LayerSet& set, int k);
   template <typename T> void autotune_t(const LayerSet& set, int k,
                                         std::vector<TileChoice>& plan);
+  template <typename T> void launch_fwd(const DepthList& D, const FrontDev* fr,
+                                        const LayerDev* ld, int k, void* scr, int bn);
+  template <typename T> void launch_bwd(const DepthList& D, const FrontDev* fr,
+                                        const LayerDev* ld, int k, void* scr, int bn);
 
   // kernel timing (HELM_FLAG_PROFILE)
   bool profile = false;

@@ -55,6 +55,16 @@ template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int* prefix, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bn, hipStream_t st);
+// vector path of the substitutions for k <= 4 columns (same tiles and
+// scratch layout as launch_fwd_gemm / launch_bwd_gemm with 64-row tiles)
+template <typename T>
+void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     void* scratch, hipStream_t st);
+template <typename T>
+void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     void* scratch, int bm, hipStream_t st);
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int* prefix, int total, const LayerDev* layers, int k,

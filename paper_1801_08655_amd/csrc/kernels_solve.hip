@@ -214,7 +214,172 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vector path for batches of KC <= KV columns (a template argument): the GEMMs above would pad
+// the columns to a 16-wide MFMA tile, so at k <= 4 the substitutions are
+// done with plain FMAs while streaming the factor blocks once, which makes
+// them bound by HBM bandwidth.  The tile and K-chunk decomposition (and the
+// scratch layout of split fronts) is the one of the MFMA kernels, so the
+// reduction kernels are shared.
+// ---------------------------------------------------------------------------
+constexpr int KV = 4;
+
+// forward: one 64-row tile of one front and one K chunk per block; wave w
+// takes the pivot columns kb + w, kb + w + 4, ... and the 4 partial sums of
+// a row are added in LDS in fixed order.
+template <typename T, int KC>
+__global__ void __launch_bounds__(256)
+k_fwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
+           const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+           const LayerDev* __restrict__ layers, int k, void* scratch) {
+  using C = C_t<T>;
+  __shared__ C red[3][64][KC];
+  const int mt = blockIdx.x;
+  const int a = find_segment(prefix, n_ids, mt);
+  const FrontDev f = fronts[ids[a]];
+  const SolveTask tk = tasks[a];
+  const LayerDev& L = layers[f.layer];
+  const int n = f.s + f.b;
+  const int local = mt - prefix[a];
+  const int chunk = local % tk.nch_f;
+  const int m0 = (local / tk.nch_f) * 64;
+  const int kb = chunk * tk.kc_f;
+  const int ke = min(f.s, kb + tk.kc_f);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = m0 + lane;
+  const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
+  const C* X = reinterpret_cast<const C*>(L.X) + (long long)f.off * KC;
+  C acc[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) acc[c] = czero<C>();
+  // q is the same for the whole wave: the right-hand-side values are
+  // loaded once per wave (scalar loads), the factor column by every lane
+  const int q0 = __builtin_amdgcn_readfirstlane(kb + w);
+  if (m < n) {
+#pragma unroll 4
+    for (int q = q0; q < ke; q += 4) {
+      const C fa = FT[m + (long long)q * n];
+      const C* xq = X + (long long)q * KC;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, xq[c]);
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) red[w - 1][lane][c] = acc[c];
+  }
+  __syncthreads();
+  if (w != 0 || m >= n) return;
+  C* Z = reinterpret_cast<C*>(L.Wt);
+  C* Uo = ub_ptr<T>(L, f.ub_parity);
+  C* S = reinterpret_cast<C*>(scratch);
+  const ChildSum<T> cs(fronts, f, L);
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const C z = cadd(cadd(acc[c], red[0][lane][c]), cadd(red[1][lane][c], red[2][lane][c]));
+    if (tk.nch_f > 1) S[(tk.scr_f + (long long)chunk * n + m) * KC + c] = z;
+    else if (m < f.s) Z[(long long)(f.off + m) * KC + c] = z;
+    else Uo[(f.ub + m - f.s) * KC + c] = cadd(z, cs(m, c, KC));
+  }
+}
+
+template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int mask) {
+  return __shfl_xor(v, mask, 64);
+}
+
+// backward: one BM-row tile (BM = 32 or 64) and one K chunk per block; each
+// 16-lane quarter of a wave takes one row at a time (BM/16 rows per
+// quarter), its lanes walk the boundary index q (contiguous in the stored
+// block) and a butterfly over the quarter sums the row.
+template <typename T, int KC>
+__global__ void __launch_bounds__(256)
+k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
+           const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+           const LayerDev* __restrict__ layers, int k, void* scratch, int bm) {
+  using C = C_t<T>;
+  const int mt = blockIdx.x;
+  const int a = find_segment(prefix, n_ids, mt);
+  const FrontDev f = fronts[ids[a]];
+  const SolveTask tk = tasks[a];
+  const LayerDev& L = layers[f.layer];
+  const int n = f.s + f.b;
+  const int local = mt - prefix[a];
+  const int chunk = local % tk.nch_b;
+  const int m0 = (local / tk.nch_b) * bm;
+  const int kb = chunk * tk.kc_b;
+  const int ke = min(f.b, kb + tk.kc_b);
+  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;   // 16 groups of 16 lanes
+  const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
+  C* X = reinterpret_cast<C*>(L.X);
+  const C* Z = reinterpret_cast<const C*>(L.Wt);
+  C* S = reinterpret_cast<C*>(scratch);
+  const int* B = L.bidx + f.bidx;
+  for (int m = m0 + g; m < m0 + bm && m < f.s; m += 16) {
+    C acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = czero<C>();
+    const C* col = FT + f.s + (long long)m * n;
+#pragma unroll 4
+    for (int q = kb + gl; q < ke; q += 16) {
+      const C fa = col[q];
+      const C* xb = X + (long long)B[q] * KC;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, xb[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        acc[c].x += shfl_xor_t(acc[c].x, off);
+        acc[c].y += shfl_xor_t(acc[c].y, off);
+      }
+    }
+    if (gl < KC) {
+      C z = acc[0];
+#pragma unroll
+      for (int c = 1; c < KC; ++c)
+        if (gl == c) z = acc[c];
+      const long long idx = (long long)(f.off + m) * KC + gl;
+      if (tk.nch_b > 1) S[(tk.scr_b + (long long)chunk * f.s + m) * KC + gl] = z;
+      else X[idx] = cadd(Z[idx], z);
+    }
+  }
+}
+
 }  // namespace
+
+template <typename T>
+void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     void* scratch, hipStream_t st) {
+  if (total_tiles <= 0) return;
+#define HELM_FWDV(KC_)                                                                     \
+  hipLaunchKernelGGL((k_fwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,   \
+                     tasks, n, prefix, layers, k, scratch)
+  switch (k) {
+    case 1: HELM_FWDV(1); break;
+    case 2: HELM_FWDV(2); break;
+    case 3: HELM_FWDV(3); break;
+    default: HELM_FWDV(4); break;
+  }
+#undef HELM_FWDV
+}
+template <typename T>
+void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
+                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     void* scratch, int bm, hipStream_t st) {
+  if (total_tiles <= 0) return;
+#define HELM_BWDV(KC_)                                                                     \
+  hipLaunchKernelGGL((k_bwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,   \
+                     tasks, n, prefix, layers, k, scratch, bm)
+  switch (k) {
+    case 1: HELM_BWDV(1); break;
+    case 2: HELM_BWDV(2); break;
+    case 3: HELM_BWDV(3); break;
+    default: HELM_BWDV(4); break;
+  }
+#undef HELM_BWDV
+}
 
 template <typename T>
 void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
@@ -293,6 +458,16 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                                      const void*, hipStream_t);
 HELM_INST_SOLVE(float)
 HELM_INST_SOLVE(double)
+
+#define HELM_INST_GEMV(T)                                                            \
+  template void launch_fwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
+                                   int, const int*, int, const LayerDev*, int,       \
+                                   void*, hipStream_t);                              \
+  template void launch_bwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
+                                   int, const int*, int, const LayerDev*, int,       \
+                                   void*, int, hipStream_t);
+HELM_INST_GEMV(float)
+HELM_INST_GEMV(double)
 
 }  // namespace kern
 }  // namespace helm

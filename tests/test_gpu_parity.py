@@ -204,5 +204,5 @@ def test_autotuned_tiles_give_the_same_solution():
     print(ch[:4])
     assert ch and all(c["tuned"] for c in ch)
     assert {c["fwd_bn"] for c in ch} <= {16, 32} and {c["bwd_bn"] for c in ch} <= {16, 32}
-    assert any(c["t_fwd_us"][0] > 0 and c["t_fwd_us"][1] > 0 for c in ch)
+    assert any(c["t_fwd_us"][1] > 0 and c["t_fwd_us"][2] > 0 for c in ch)
     assert all(c["tuned"] == 0 for c in a.tile_choices())
