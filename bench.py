@@ -127,6 +127,29 @@ def roofline(stats, precision, workload):
             "traffic": traffic, "launches": st["launches"], "avg_launch_ms": avg_ms}
 
 
+def small_k_probe(s, wl, torch, layer=5, reps=3):
+    """One-column local solves of an interior layer (the HBM-bound regime of
+    the substitutions): algorithmic bytes of the forward / backward GEMM
+    classes per event-timed second, against the 8 TB/s HBM peak."""
+    _, _, lo, hi = s.layer_info(layer)
+    r = torch.randn((1, hi - lo + 1, wl.n[1], wl.n[0]), dtype=torch.complex128,
+                    device="cuda")
+    s.layer_solve(layer, r)
+    torch.cuda.synchronize()
+    s.kernel_stats(reset=True)
+    for _ in range(reps):
+        s.layer_solve(layer, r)
+    torch.cuda.synchronize()
+    ks = s.kernel_stats(reset=True)
+    out = {"layer": layer, "k": 1, "solves": reps}
+    for name in ("solve_fwd_gemm", "solve_bwd_gemm"):
+        st = ks[name]
+        gbs = st["bytes"] / max(st["total_ms"], 1e-9) / 1e6
+        out[name] = {"ms_per_solve": st["total_ms"] / reps, "GB/s": gbs,
+                     "frac_hbm": gbs * 1e9 / PEAK["hbm"]}
+    return out
+
+
 def cpu_baseline():
     """The oracle (global sparse assembly + SuperLU direct solve, complex128)
     on the same workload recipe at the largest grid it finishes in ~15 s."""
@@ -367,6 +390,7 @@ def main():
         err = float(d.max())
     rl = roofline({k: v for k, v in kstats.items() if k.startswith("solve_")}, "mixed",
                   wl.name)
+    small = small_k_probe(s, wl, torch)
     out = {
         "metric": METRIC,
         "value": value,
@@ -398,6 +422,7 @@ def main():
         "layer_solves_per_step": info["layer_solves"],
         "pcie_inclusive": pcie,
         "roofline": rl,
+        "hbm_bound_k1": small,
         "kernels": kstats,
         "factor_kernels": fstats,
     }

@@ -248,6 +248,8 @@ void Handle::factorize_t() {
   fac.clear();
   bytes_factors = 0;
   factor_flops = 0;
+  HELM_REQUIRE(!opt.hbm_budget_bytes || plan_factor_elems(G) * elem <= opt.hbm_budget_bytes,
+               HELM_ENOMEM, "factors exceed the memory budget");
   for (int l = 0; l < L; ++l) {
     fac.emplace_back(new DevMem);
     fac.back()->alloc((size_t)G.layers[l].fac_elems * elem);

@@ -166,3 +166,44 @@ def test_batch_entry_point_rejects_bad_problems():
     bo = _lib.helm_batch_options()
     L.helm_batch_default_options(ctypes.byref(bo))
     assert bo.slots == 64 and bo.opt.precision == pt.HELM_MIXED
+
+
+def test_factorize_rejects_bad_models_before_any_device_call():
+    """Non-finite or non-positive squared slowness, null arguments and an
+    impossible layer split are refused with HELM_EINVAL on the host."""
+    import numpy as np
+    L = pt.lib()
+    n = 12
+    g = _lib.helm_grid(n, n, n, 1.0 / (n - 1))
+    o = pt.options()
+    h = ctypes.c_void_p()
+    good = np.full((n, n, n), 1.0)
+    for bad_val in (np.nan, np.inf, 0.0, -1.0):
+        m = good.copy()
+        m[3, 4, 5] = bad_val
+        st = L.helm_factorize(ctypes.byref(g), m.ctypes.data, 10.0, 2, 2, ctypes.byref(o),
+                              ctypes.byref(h))
+        assert st == pt.HELM_EINVAL, bad_val
+        assert "squared slowness" in L.helm_last_error().decode()
+    assert L.helm_factorize(None, good.ctypes.data, 10.0, 2, 2, ctypes.byref(o),
+                            ctypes.byref(h)) == pt.HELM_EINVAL
+    assert L.helm_factorize(ctypes.byref(g), None, 10.0, 2, 2, ctypes.byref(o),
+                            ctypes.byref(h)) == pt.HELM_EINVAL
+    # 9 layers cannot split 8 interior planes
+    st = L.helm_factorize(ctypes.byref(g), good.ctypes.data, 10.0, 2, 9, ctypes.byref(o),
+                          ctypes.byref(h))
+    assert st == pt.HELM_EINVAL
+
+
+def test_entry_points_reject_null_handles():
+    L = pt.lib()
+    x = ctypes.c_double()
+    assert L.helm_solve(None, 1, ctypes.byref(x), ctypes.byref(x), None) == pt.HELM_EINVAL
+    assert L.helm_solve_dev(None, 1, ctypes.byref(x), ctypes.byref(x), None) == pt.HELM_EINVAL
+    assert L.helm_solve_points(None, 1, ctypes.byref(x), ctypes.byref(x), ctypes.byref(x),
+                               None) == pt.HELM_EINVAL
+    assert L.helm_layer_solve_dev(None, 0, 1, ctypes.byref(x), ctypes.byref(x)) == pt.HELM_EINVAL
+    assert L.helm_kernel_stats(None, None, 0, None, 0) == pt.HELM_EINVAL
+    assert L.helm_tile_choices(None, None, 0, None) == pt.HELM_EINVAL
+    assert L.helm_set_solve_options(None, None) == pt.HELM_EINVAL
+    assert L.helm_free(None) == pt.HELM_OK
