@@ -322,6 +322,8 @@ def main():
             args.slots = 64
         batch_bench(args, torch, pt)
         return
+    log("[calibration] attainable device rates")
+    attain = pt.device_peaks(0)
     wl = workload(args.workload)
     m = wl.m()
     srcs = wl.point_sources(args.rhs)
@@ -391,6 +393,10 @@ def main():
     rl = roofline({k: v for k, v in kstats.items() if k.startswith("solve_")}, "mixed",
                   wl.name)
     small = small_k_probe(s, wl, torch)
+    rl["attainable_peak"] = attain["mfma_f32_tflops"]
+    rl["frac_of_attainable"] = rl["achieved"] / attain["mfma_f32_tflops"]
+    for name in ("solve_fwd_gemm", "solve_bwd_gemm"):
+        small[name]["frac_of_attainable_read"] = small[name]["GB/s"] / attain["hbm_read_gbps"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -423,6 +429,7 @@ def main():
         "pcie_inclusive": pcie,
         "roofline": rl,
         "hbm_bound_k1": small,
+        "attainable": attain,
         "kernels": kstats,
         "factor_kernels": fstats,
     }

@@ -185,12 +185,11 @@ int helm_kernel_stats(helm_handle* h, helm_kernel_stat* out, int max, int* count
 /* Column-tile choices of the substitution GEMMs: one record per (layer set,
  * batch width k, depth of the front trees), for the sets used so far.  A
  * layer set is described by its number of layers.  fwd_bn / bwd_bn are the
- * tile widths in use: 16, 32 or 64 columns on the matrix cores, or 1 for the
- * vector path (default up to 2 columns, a candidate up to 4); when the
- * choice was measured
- * (HELM_FLAG_AUTOTUNE), t_fwd_us / t_bwd_us hold the timed launch of each
- * width in the order 1, 16, 32, 64 (0 where a width was not tried).  Writes
- * up to `max` records and the total to *count. */
+ * tile kinds in use: 16, 32 or 64 for MFMA tiles of that many columns, 1
+ * for the vector path (default up to 2 columns, a candidate up to 4); when
+ * the choice was measured (HELM_FLAG_AUTOTUNE), t_fwd_us / t_bwd_us hold the
+ * timed launch of each kind in the order 1, 16, 32, 64 (0 where a kind was
+ * not tried).  Writes up to `max` records and the total to *count. */
 typedef struct {
   int    set_layers, k, depth, fronts;
   double mean_s, mean_b;   /* mean pivot / boundary size of the depth's fronts */
@@ -199,6 +198,17 @@ typedef struct {
 } helm_tile_choice;
 
 int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count);
+
+/* Calibration: the attainable rates of the device, measured with the
+ * instruction shapes and access widths the solver uses.  Matrix cores:
+ * back-to-back v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 on 8
+ * independent accumulators per wave, 8 workgroups of 4 waves per compute
+ * unit (TFLOP/s).  HBM: a streaming 16-byte read of 2 GiB and a copy of
+ * 2 GiB (bytes read + written per second, GB/s).  Best of three runs each.
+ * Any output pointer may be NULL.  Allocates 4 GiB of device memory for the
+ * duration of the call. */
+int helm_device_peaks(int device, double* mfma_f32_tflops, double* mfma_f64_tflops,
+                      double* hbm_read_gbps, double* hbm_copy_gbps);
 
 /* Change the online-stage options of a factorized handle (gmres_tol,
  * gmres_max_iter, ir_tol, ir_max_steps, inner_tol, max_rhs, flags); the

@@ -62,6 +62,15 @@ def node_indices(nodes: Sequence, n) -> np.ndarray:
     return np.array(out, dtype=np.int64)
 
 
+def device_peaks(device: int = 0) -> dict:
+    """Attainable matrix-core rates and HBM bandwidth of the device (see
+    helm_device_peaks in include/helm.h)."""
+    v = [ctypes.c_double() for _ in range(4)]
+    check(lib().helm_device_peaks(device, *[ctypes.byref(x) for x in v]), "helm_device_peaks")
+    return {"mfma_f32_tflops": v[0].value, "mfma_f64_tflops": v[1].value,
+            "hbm_read_gbps": v[2].value, "hbm_copy_gbps": v[3].value}
+
+
 def _ptr(t) -> int:
     """Device pointer of a contiguous torch tensor (complex128 / float64)."""
     if not t.is_contiguous():

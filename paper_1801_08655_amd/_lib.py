@@ -22,7 +22,7 @@ EXPORTED = [
     "helm_solve", "helm_solve_dev", "helm_solve_points", "helm_free",
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
-    "helm_set_solve_options", "helm_tile_choices",
+    "helm_set_solve_options", "helm_tile_choices", "helm_device_peaks",
     # include/helm_serve.h
     "helm_server_default_options", "helm_server_create", "helm_server_add_model",
     "helm_server_submit", "helm_server_wait", "helm_server_poll", "helm_server_get_stats",
@@ -236,6 +236,8 @@ def lib():
     L.helm_set_solve_options.restype = I
     L.helm_tile_choices.argtypes = [H, ctypes.POINTER(helm_tile_choice), I, ctypes.POINTER(I)]
     L.helm_tile_choices.restype = I
+    L.helm_device_peaks.argtypes = [I] + [ctypes.POINTER(D)] * 4
+    L.helm_device_peaks.restype = I
     SV = ctypes.c_void_p
     L.helm_server_default_options.argtypes = [ctypes.POINTER(helm_server_options)]
     L.helm_server_default_options.restype = None

@@ -30,11 +30,23 @@ void DevMem::release() {
 
 namespace {
 
+// set-up copies (plans, tables): complete before the host vector goes away
 template <typename V>
 void upload(DevMem& d, const std::vector<V>& h, hipStream_t st) {
   d.alloc(h.size() * sizeof(V));
-  if (!h.empty())
+  if (!h.empty()) {
     HELM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, st));
+    HELM_HIP(hipStreamSynchronize(st));
+  }
+}
+
+// Tile map of a prefix array over items: entry t = (a, t - prefix[a]) for
+// prefix[a] <= t < prefix[a + 1].
+std::vector<int2> tile_map(const std::vector<int>& prefix) {
+  std::vector<int2> m(prefix.empty() ? 0 : (size_t)prefix.back());
+  for (size_t a = 0; a + 1 < prefix.size(); ++a)
+    for (int t = prefix[a]; t < prefix[a + 1]; ++t) m[t] = make_int2((int)a, t - prefix[a]);
+  return m;
 }
 
 std::vector<double2> to_d2(const std::vector<cd>& v) {
@@ -369,10 +381,10 @@ void Handle::factorize_t() {
         roff[a + 1] = roff[a] + F.s;
       }
       upload(fd.ids, v, st);
-      upload(fd.pFull, fd.pFull_h, st);
-      upload(fd.pCol, fd.pCol_h, st);
-      upload(fd.pRow, pRow, st);
-      upload(fd.pStore, pStore, st);
+      upload(fd.pFull, tile_map(fd.pFull_h), st);
+      upload(fd.pCol, tile_map(fd.pCol_h), st);
+      upload(fd.pRow, tile_map(pRow), st);
+      upload(fd.pStore, tile_map(pStore), st);
       upload(fd.panel_off, poff, st);
       upload(fd.perm_off, roff, st);
       const FrontDev* fr = fronts.as<FrontDev>();
@@ -384,11 +396,11 @@ void Handle::factorize_t() {
         front_elems += n * n;
       }
       hipEvent_t e0 = prof_begin();
-      kern::launch_extend_add<T>(fr, ids, fd.n, fd.pFull.as<int>(), fd.pFull_h[fd.n], ld,
+      kern::launch_extend_add<T>(fr, ids, fd.n, fd.pFull.as<int2>(), fd.pFull_h[fd.n], ld,
                                  ws0.p, ws1.p, st);
       prof_end(K_EXTEND_ADD, e0, 0, 2 * front_elems * elem);
       e0 = prof_begin();
-      kern::launch_orig_entries<T>(fr, ids, fd.n, fd.pRow.as<int>(), pRow[fd.n], ld,
+      kern::launch_orig_entries<T>(fr, ids, fd.n, fd.pRow.as<int2>(), pRow[fd.n], ld,
                                    ws0.p, ws1.p, grid, st);
       prof_end(K_ORIG, e0, 0, 0);
       const int smax = fd.s_sorted[0];
@@ -410,23 +422,23 @@ void Handle::factorize_t() {
                               status.as<int>(), st);
         prof_end(K_PANEL, e1, 0, 0);
         e1 = prof_begin();
-        kern::launch_swap_JO<T>(fr, ids, n_act, fd.pCol.as<int>(), fd.pCol_h[n_act], k,
+        kern::launch_swap_JO<T>(fr, ids, n_act, fd.pCol.as<int2>(), fd.pCol_h[n_act], k,
                                 nb, ws0.p, ws1.p, Dbuf.p, ipiv.as<int>(),
                                 fd.panel_off.as<long long>(), fd.perm_off.as<long long>(),
                                 st);
         prof_end(K_SWAP_JO, e1, 0, 0);
         e1 = prof_begin();
-        kern::launch_sweep_gemm<T>(fr, ids, n_act, fd.pFull.as<int>(), fd.pFull_h[n_act],
+        kern::launch_sweep_gemm<T>(fr, ids, n_act, fd.pFull.as<int2>(), fd.pFull_h[n_act],
                                    k, nb, ws0.p, ws1.p, st);
         prof_end(K_SWEEP_GEMM, e1, sw_flops, sw_bytes);
         e1 = prof_begin();
-        kern::launch_update_OJ<T>(fr, ids, n_act, fd.pCol.as<int>(), fd.pCol_h[n_act], k,
+        kern::launch_update_OJ<T>(fr, ids, n_act, fd.pCol.as<int2>(), fd.pCol_h[n_act], k,
                                   nb, ws0.p, ws1.p, Dbuf.p, fd.panel_off.as<long long>(),
                                   st);
         prof_end(K_UPDATE_OJ, e1, 0, 0);
       }
       hipEvent_t e2 = prof_begin();
-      kern::launch_store_factor<T>(fr, ids, fd.n, fd.pStore.as<int>(), pStore[fd.n], ld,
+      kern::launch_store_factor<T>(fr, ids, fd.n, fd.pStore.as<int2>(), pStore[fd.n], ld,
                                    ws0.p, ws1.p, perm.as<int>(),
                                    fd.perm_off.as<long long>(), st);
       prof_end(K_STORE, e2, 0, 0);
@@ -566,14 +578,14 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
     D->nL = (int)nl;
     upload(D->ids, ids, st);
     upload(D->tasks, tasks, st);
-    upload(D->pBw, pBw, st);
-    upload(D->rB, rB, st);
+    upload(D->pBw, tile_map(pBw), st);
+    upload(D->rB, tile_map(rB), st);
     upload(D->idsS, idsS, st);
     upload(D->idsL, idsL, st);
     upload(D->tasksL, tasksL, st);
-    upload(D->pSB, pSB, st);
-    upload(D->pF, pF, st);
-    upload(D->rF, rF, st);
+    upload(D->pSB, tile_map(pSB), st);
+    upload(D->pF, tile_map(pF), st);
+    upload(D->rF, tile_map(rF), st);
     D->tSB = pSB.back();
     D->tF = pF.back();
     D->tBw = pBw.back();
@@ -642,20 +654,20 @@ void Handle::launch_fwd(const DepthList& D, const FrontDev* fr, const LayerDev* 
                         void* scr, int bn) {
   if (bn == 1)
     kern::launch_fwd_gemv<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
-                             D.pF.as<int>(), D.tF, ld, k, scr, st);
+                             D.pF.as<int2>(), D.tF, ld, k, scr, st);
   else
     kern::launch_fwd_gemm<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
-                             D.pF.as<int>(), D.tF, ld, k, scr, bn, st);
+                             D.pF.as<int2>(), D.tF, ld, k, scr, bn, st);
 }
 template <typename T>
 void Handle::launch_bwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
                         void* scr, int bn) {
   if (bn == 1)
     kern::launch_bwd_gemv<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
-                             D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm, st);
+                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, st);
   else
     kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
-                             D.pBw.as<int>(), D.tBw, ld, k, scr, D.bwd_bm, bn, st);
+                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, bn, st);
 }
 
 const std::vector<Handle::TileChoice>& Handle::tile_plan(const LayerSet& set, int k) {
@@ -771,7 +783,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     hipEvent_t a = nullptr;
     if (D.nS > 0) {
       a = prof_begin();
-      kern::launch_fwd_gather<T>(fr, D.idsS.as<int>(), D.nS, D.pSB.as<int>(), D.tSB, ld, k,
+      kern::launch_fwd_gather<T>(fr, D.idsS.as<int>(), D.nS, D.pSB.as<int2>(), D.tSB, ld, k,
                                  st);
       prof_end(K_FWD_GATHER, a, 0, 3.0 * D.fs_s * kk * e);
     }
@@ -786,7 +798,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
                D.fl_sbs * e + (2.0 * D.fl_s + D.fl_b + D.fs_b) * kk * e);
       if (D.tRF > 0) {
         a = prof_begin();
-        kern::launch_fwd_reduce<T>(fr, ids, tk, D.nL, D.rF.as<int>(), D.tRF, ld, k, scr, st);
+        kern::launch_fwd_reduce<T>(fr, ids, tk, D.nL, D.rF.as<int2>(), D.tRF, ld, k, scr, st);
         prof_end(K_FWD_REDUCE, a, 0, 0);
       }
     }
@@ -803,7 +815,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
     if (D.tRB > 0) {
       a = prof_begin();
-      kern::launch_bwd_reduce<T>(fr, ids, tk, D.n, D.rB.as<int>(), D.tRB, ld, k, scr, st);
+      kern::launch_bwd_reduce<T>(fr, ids, tk, D.n, D.rB.as<int2>(), D.tRB, ld, k, scr, st);
       prof_end(K_BWD_REDUCE, a, 0, 0);
     }
   }

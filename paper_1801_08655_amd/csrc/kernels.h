@@ -15,11 +15,11 @@ struct ReadTerms {
 // --- factorization (kernels_factor.hip) -------------------------------------
 template <typename T>
 void launch_extend_add(const FrontDev* fronts, const int* ids, int n_ids,
-                       const int* prefix, int total, const LayerDev* layers,
+                       const int2* tmap, int total, const LayerDev* layers,
                        void* ws0, void* ws1, hipStream_t st);
 template <typename T>
 void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
-                         const int* prefix, int total, const LayerDev* layers,
+                         const int2* tmap, int total, const LayerDev* layers,
                          void* ws0, void* ws1, const GridDev& g, hipStream_t st);
 template <typename T>
 void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
@@ -28,54 +28,54 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
                   const long long* perm_off, int* status, hipStream_t st);
 template <typename T>
 void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
-                    const int* prefix, int total, int k, int nb, void* ws0,
+                    const int2* tmap, int total, int k, int nb, void* ws0,
                     void* ws1, const void* D, const int* ipiv,
                     const long long* panel_off, const long long* perm_off,
                     hipStream_t st);
 template <typename T>
 void launch_sweep_gemm(const FrontDev* fronts, const int* ids, int n_active,
-                       const int* prefix, int total, int k, int nb, void* ws0,
+                       const int2* tmap, int total, int k, int nb, void* ws0,
                        void* ws1, hipStream_t st);
 template <typename T>
 void launch_update_OJ(const FrontDev* fronts, const int* ids, int n_active,
-                      const int* prefix, int total, int k, int nb, void* ws0,
+                      const int2* tmap, int total, int k, int nb, void* ws0,
                       void* ws1, const void* D, const long long* panel_off,
                       hipStream_t st);
 template <typename T>
 void launch_store_factor(const FrontDev* fronts, const int* ids, int n_ids,
-                         const int* prefix, int total, const LayerDev* layers,
+                         const int2* tmap, int total, const LayerDev* layers,
                          void* ws0, void* ws1, const int* perm,
                          const long long* perm_off, hipStream_t st);
 
 // --- substitutions (kernels_solve.hip) --------------------------------------
 template <typename T>
-void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
+void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tmap,
                        int total, const LayerDev* layers, int k, hipStream_t st);
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bn, hipStream_t st);
 // vector path of the substitutions for k <= 4 columns (same tiles and
 // scratch layout as launch_fwd_gemm / launch_bwd_gemm with 64-row tiles)
 template <typename T>
 void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, hipStream_t st);
 template <typename T>
 void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bm, hipStream_t st);
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                       const int* prefix, int total, const LayerDev* layers, int k,
+                       const int2* tmap, int total, const LayerDev* layers, int k,
                        const void* scratch, hipStream_t st);
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bm, int bn, hipStream_t st);
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                       const int* prefix, int total, const LayerDev* layers, int k,
+                       const int2* tmap, int total, const LayerDev* layers, int k,
                        const void* scratch, hipStream_t st);
 
 // --- volumes, traces, Krylov (kernels_volume.hip) ---------------------------

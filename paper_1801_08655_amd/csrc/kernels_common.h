@@ -71,15 +71,10 @@ template <> __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
 }
 template <> __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
 
-// largest i in [0, n) with prefix[i] <= x  (prefix has n + 1 entries, prefix[0] = 0)
-__device__ __forceinline__ int find_segment(const int* __restrict__ prefix, int n, int x) {
-  int lo = 0, hi = n;  // invariant prefix[lo] <= x < prefix[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= x) lo = mid; else hi = mid;
-  }
-  return lo;
-}
+// Launches over variable-size items (fronts, their tiles and chunks) index
+// their blocks through a tile map built on the host: entry t holds the item
+// of block t and the block's index within that item, so a block finds its
+// work with one load.
 
 // ---------------------------------------------------------------------------
 // MFMA 16x16x4 (one block).  Lane l supplies A[l%16][l/16] and B[l/16][l%16];

@@ -34,14 +34,15 @@ __device__ __forceinline__ C_t<T>* front_ptr(void* ws0, void* ws1, const FrontDe
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_extend_add(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-             int n_ids, const int* __restrict__ prefix,
+             int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, void* ws0, void* ws1) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_ids, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
   const int nt = (n + GT - 1) / GT;
-  const int tile = blockIdx.x - prefix[a];
+  const int tile = tm.y;
   const int i0 = (tile % nt) * GT, j0 = (tile / nt) * GT;
   __shared__ int inv_r[2][GT], inv_c[2][GT];
   const LayerDev& L = layers[f.layer];
@@ -96,13 +97,14 @@ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) { return cdiv(a, b
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_orig_entries(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-               int n_ids, const int* __restrict__ prefix,
+               int n_ids, const int2* __restrict__ tmap,
                const LayerDev* __restrict__ layers, void* ws0, void* ws1,
                GridDev g) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_ids, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
-  const int r = (blockIdx.x - prefix[a]) * 256 + threadIdx.x;
+  const int r = tm.y * 256 + threadIdx.x;
   if (r >= f.s) return;
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
@@ -289,15 +291,16 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-          int n_active, const int* __restrict__ prefix, int k, int nb,
+          int n_active, const int2* __restrict__ tmap, int k, int nb,
           void* ws0, void* ws1, const void* D_base, const int* __restrict__ ipiv_base,
           const long long* __restrict__ panel_off, const long long* __restrict__ perm_off) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_active, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
   const int nbf = (f.s - k) < nb ? (f.s - k) : nb;
-  const int c0 = (blockIdx.x - prefix[a]) * GT;
+  const int c0 = tm.y * GT;
   C* F = front_ptr<T>(ws0, ws1, f);
   const int* ipiv = ipiv_base + perm_off[a];
   const C* D = reinterpret_cast<const C*>(D_base) + panel_off[a];
@@ -344,16 +347,17 @@ k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-             int n_active, const int* __restrict__ prefix, int k, int nb,
+             int n_active, const int2* __restrict__ tmap, int k, int nb,
              void* ws0, void* ws1) {
   using C = C_t<T>;
   __shared__ GemmSmem<T, 64> sm;
-  const int a = find_segment(prefix, n_active, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
   const int nbf = (f.s - k) < nb ? (f.s - k) : nb;
   const int nt = (n + GT - 1) / GT;
-  const int tile = blockIdx.x - prefix[a];
+  const int tile = tm.y;
   const int i0 = (tile % nt) * GT;   // C rows
   const int j0 = (tile / nt) * GT;   // C columns
   C* F = front_ptr<T>(ws0, ws1, f);
@@ -379,15 +383,16 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_update_OJ(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-            int n_active, const int* __restrict__ prefix, int k, int nb,
+            int n_active, const int2* __restrict__ tmap, int k, int nb,
             void* ws0, void* ws1, const void* D_base,
             const long long* __restrict__ panel_off) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_active, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
   const int nbf = (f.s - k) < nb ? (f.s - k) : nb;
-  const int r0 = (blockIdx.x - prefix[a]) * GT;
+  const int r0 = tm.y * GT;
   C* F = front_ptr<T>(ws0, ws1, f);
   const C* D = reinterpret_cast<const C*>(D_base) + panel_off[a];
   __shared__ C V[GT][NBMAX + 1];
@@ -426,15 +431,16 @@ k_update_OJ(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_store_factor(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-               int n_ids, const int* __restrict__ prefix,
+               int n_ids, const int2* __restrict__ tmap,
                const LayerDev* __restrict__ layers, void* ws0, void* ws1,
                const int* __restrict__ perm_base, const long long* __restrict__ perm_off) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_ids, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
   const int nrt = (n + GT - 1) / GT;
-  const int tile = blockIdx.x - prefix[a];
+  const int tile = tm.y;
   const int i0 = (tile % nrt) * GT, j0 = (tile / nrt) * GT;
   const C* F = front_ptr<T>(ws0, ws1, f);
   C* FT = reinterpret_cast<C*>(layers[f.layer].fac) + f.fac;
@@ -455,19 +461,19 @@ k_store_factor(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_extend_add(const FrontDev* fronts, const int* ids, int n_ids,
-                       const int* prefix, int total, const LayerDev* layers,
+                       const int2* tmap, int total, const LayerDev* layers,
                        void* ws0, void* ws1, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_extend_add<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_ids, prefix, layers, ws0, ws1);
+                     n_ids, tmap, layers, ws0, ws1);
 }
 template <typename T>
 void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
-                         const int* prefix, int total, const LayerDev* layers,
+                         const int2* tmap, int total, const LayerDev* layers,
                          void* ws0, void* ws1, const GridDev& g, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_orig_entries<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_ids, prefix, layers, ws0, ws1, g);
+                     n_ids, tmap, layers, ws0, ws1, g);
 }
 template <typename T>
 void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
@@ -481,62 +487,62 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
 }
 template <typename T>
 void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
-                    const int* prefix, int total, int k, int nb, void* ws0,
+                    const int2* tmap, int total, int k, int nb, void* ws0,
                     void* ws1, const void* D, const int* ipiv,
                     const long long* panel_off, const long long* perm_off,
                     hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_swap_JO<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_active, prefix, k, nb, ws0, ws1, D, ipiv, panel_off, perm_off);
+                     n_active, tmap, k, nb, ws0, ws1, D, ipiv, panel_off, perm_off);
 }
 template <typename T>
 void launch_sweep_gemm(const FrontDev* fronts, const int* ids, int n_active,
-                       const int* prefix, int total, int k, int nb, void* ws0,
+                       const int2* tmap, int total, int k, int nb, void* ws0,
                        void* ws1, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_sweep_gemm<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_active, prefix, k, nb, ws0, ws1);
+                     n_active, tmap, k, nb, ws0, ws1);
 }
 template <typename T>
 void launch_update_OJ(const FrontDev* fronts, const int* ids, int n_active,
-                      const int* prefix, int total, int k, int nb, void* ws0,
+                      const int2* tmap, int total, int k, int nb, void* ws0,
                       void* ws1, const void* D, const long long* panel_off,
                       hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_update_OJ<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_active, prefix, k, nb, ws0, ws1, D, panel_off);
+                     n_active, tmap, k, nb, ws0, ws1, D, panel_off);
 }
 template <typename T>
 void launch_store_factor(const FrontDev* fronts, const int* ids, int n_ids,
-                         const int* prefix, int total, const LayerDev* layers,
+                         const int2* tmap, int total, const LayerDev* layers,
                          void* ws0, void* ws1, const int* perm,
                          const long long* perm_off, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_store_factor<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_ids, prefix, layers, ws0, ws1, perm, perm_off);
+                     n_ids, tmap, layers, ws0, ws1, perm, perm_off);
 }
 
 #define HELM_INST_FACTOR(T)                                                        \
-  template void launch_extend_add<T>(const FrontDev*, const int*, int, const int*, \
+  template void launch_extend_add<T>(const FrontDev*, const int*, int, const int2*, \
                                      int, const LayerDev*, void*, void*,           \
                                      hipStream_t);                                 \
   template void launch_orig_entries<T>(const FrontDev*, const int*, int,          \
-                                       const int*, int, const LayerDev*, void*,    \
+                                       const int2*, int, const LayerDev*, void*,    \
                                        void*, const GridDev&, hipStream_t);        \
   template void launch_panel<T>(const FrontDev*, const int*, int, int, int, void*, \
                                 void*, void*, const long long*, void*, int*, int*, \
                                 const long long*, int*, hipStream_t);              \
-  template void launch_swap_JO<T>(const FrontDev*, const int*, int, const int*,    \
+  template void launch_swap_JO<T>(const FrontDev*, const int*, int, const int2*,    \
                                   int, int, int, void*, void*, const void*,        \
                                   const int*, const long long*, const long long*,  \
                                   hipStream_t);                                    \
-  template void launch_sweep_gemm<T>(const FrontDev*, const int*, int, const int*, \
+  template void launch_sweep_gemm<T>(const FrontDev*, const int*, int, const int2*, \
                                      int, int, int, void*, void*, hipStream_t);    \
-  template void launch_update_OJ<T>(const FrontDev*, const int*, int, const int*,  \
+  template void launch_update_OJ<T>(const FrontDev*, const int*, int, const int2*,  \
                                     int, int, int, void*, void*, const void*,      \
                                     const long long*, hipStream_t);                \
   template void launch_store_factor<T>(const FrontDev*, const int*, int,          \
-                                       const int*, int, const LayerDev*, void*,    \
+                                       const int2*, int, const LayerDev*, void*,    \
                                        void*, const int*, const long long*,        \
                                        hipStream_t);
 HELM_INST_FACTOR(float)

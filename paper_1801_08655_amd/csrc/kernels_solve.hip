@@ -56,13 +56,14 @@ template <typename T> struct ChildSum {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-             int n_ids, const int* __restrict__ prefix,
+             int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, int k) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_ids, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const LayerDev& L = layers[f.layer];
-  const int r0 = (blockIdx.x - prefix[a]) * RT;
+  const int r0 = tm.y * RT;
   C* X = reinterpret_cast<C*>(L.X);
   const ChildSum<T> cs(fronts, f, L);
   const int rows = (f.s - r0) < RT ? (f.s - r0) : RT;
@@ -79,19 +80,20 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T, int BN>
 __global__ void __launch_bounds__(256)
 k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-           const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+           const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
   constexpr int BM = FWD_BM;
   __shared__ GemmSmem<T, BM, BN> sm;
   const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
-  const int a = find_segment(prefix, n_ids, mt);
+  const int2 tm = tmap[mt];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
-  const int local = mt - prefix[a];
+  const int local = tm.y;
   const int chunk = local % tk.nch_f;
   const int m0 = (local / tk.nch_f) * BM, n0 = nt * BN;
   const int kb = chunk * tk.kc_f;
@@ -124,15 +126,16 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-             const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+             const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, int k, const void* scratch) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_ids, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
-  const int r0 = (blockIdx.x - prefix[a]) * RT;
+  const int r0 = tm.y * RT;
   const int rows = min(RT, n - r0);
   const C* S = reinterpret_cast<const C*>(scratch);
   C* Z = reinterpret_cast<C*>(L.Wt);
@@ -154,18 +157,19 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T, int BM, int BN>
 __global__ void __launch_bounds__(256)
 k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-           const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+           const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
   __shared__ GemmSmem<T, BM, BN> sm;
   const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
-  const int a = find_segment(prefix, n_ids, mt);
+  const int2 tm = tmap[mt];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
-  const int local = mt - prefix[a];
+  const int local = tm.y;
   const int chunk = local % tk.nch_b;
   const int m0 = (local / tk.nch_b) * BM, n0 = nt * BN;
   const int kb = chunk * tk.kc_b;
@@ -192,14 +196,15 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-             const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+             const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, int k, const void* scratch) {
   using C = C_t<T>;
-  const int a = find_segment(prefix, n_ids, blockIdx.x);
+  const int2 tm = tmap[blockIdx.x];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
-  const int r0 = (blockIdx.x - prefix[a]) * RT;
+  const int r0 = tm.y * RT;
   const int rows = min(RT, f.s - r0);
   const C* S = reinterpret_cast<const C*>(scratch);
   C* X = reinterpret_cast<C*>(L.X);
@@ -230,17 +235,18 @@ constexpr int KV = 4;
 template <typename T, int KC>
 __global__ void __launch_bounds__(256)
 k_fwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-           const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+           const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
   __shared__ C red[3][64][KC];
   const int mt = blockIdx.x;
-  const int a = find_segment(prefix, n_ids, mt);
+  const int2 tm = tmap[mt];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
-  const int local = mt - prefix[a];
+  const int local = tm.y;
   const int chunk = local % tk.nch_f;
   const int m0 = (local / tk.nch_f) * 64;
   const int kb = chunk * tk.kc_f;
@@ -294,16 +300,17 @@ template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int mask) {
 template <typename T, int KC>
 __global__ void __launch_bounds__(256)
 k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
-           const SolveTask* __restrict__ tasks, int n_ids, const int* __restrict__ prefix,
+           const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch, int bm) {
   using C = C_t<T>;
   const int mt = blockIdx.x;
-  const int a = find_segment(prefix, n_ids, mt);
+  const int2 tm = tmap[mt];
+  const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
-  const int local = mt - prefix[a];
+  const int local = tm.y;
   const int chunk = local % tk.nch_b;
   const int m0 = (local / tk.nch_b) * bm;
   const int kb = chunk * tk.kc_b;
@@ -350,12 +357,12 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 
 template <typename T>
 void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, hipStream_t st) {
   if (total_tiles <= 0) return;
 #define HELM_FWDV(KC_)                                                                     \
   hipLaunchKernelGGL((k_fwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,   \
-                     tasks, n, prefix, layers, k, scratch)
+                     tasks, n, tmap, layers, k, scratch)
   switch (k) {
     case 1: HELM_FWDV(1); break;
     case 2: HELM_FWDV(2); break;
@@ -366,12 +373,12 @@ void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
 }
 template <typename T>
 void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bm, hipStream_t st) {
   if (total_tiles <= 0) return;
 #define HELM_BWDV(KC_)                                                                     \
   hipLaunchKernelGGL((k_bwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,   \
-                     tasks, n, prefix, layers, k, scratch, bm)
+                     tasks, n, tmap, layers, k, scratch, bm)
   switch (k) {
     case 1: HELM_BWDV(1); break;
     case 2: HELM_BWDV(2); break;
@@ -382,40 +389,40 @@ void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
 }
 
 template <typename T>
-void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int* prefix,
+void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tmap,
                        int total, const LayerDev* layers, int k, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_fwd_gather<T>, dim3(total), dim3(256), 0, st, fr, ids, n,
-                     prefix, layers, k);
+                     tmap, layers, k);
 }
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bn, hipStream_t st) {
   if (total_tiles <= 0) return;
   const int ntn = (k + bn - 1) / bn;
   const dim3 grid(total_tiles * ntn);
   if (bn == 16)
     hipLaunchKernelGGL((k_fwd_gemm<T, 16>), grid, dim3(256), 0, st, fr, ids, tasks, n,
-                       prefix, layers, k, scratch);
+                       tmap, layers, k, scratch);
   else if (bn == 32)
     hipLaunchKernelGGL((k_fwd_gemm<T, 32>), grid, dim3(256), 0, st, fr, ids, tasks, n,
-                       prefix, layers, k, scratch);
+                       tmap, layers, k, scratch);
   else
     hipLaunchKernelGGL((k_fwd_gemm<T, 64>), grid, dim3(256), 0, st, fr, ids, tasks, n,
-                       prefix, layers, k, scratch);
+                       tmap, layers, k, scratch);
 }
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                       const int* prefix, int total, const LayerDev* layers, int k,
+                       const int2* tmap, int total, const LayerDev* layers, int k,
                        const void* scratch, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_fwd_reduce<T>, dim3(total), dim3(256), 0, st, fr, ids, tasks, n,
-                     prefix, layers, k, scratch);
+                     tmap, layers, k, scratch);
 }
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                     const int* prefix, int total_tiles, const LayerDev* layers, int k,
+                     const int2* tmap, int total_tiles, const LayerDev* layers, int k,
                      void* scratch, int bm, int bn, hipStream_t st) {
   if (total_tiles <= 0) return;
   // a 32 x 16 tile has fewer MFMA blocks than waves: use 32 columns there
@@ -424,7 +431,7 @@ void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks,
   const dim3 grid(total_tiles * ntn);
 #define HELM_BWD(BM_, BN_)                                                              \
   hipLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_>), grid, dim3(256), 0, st, fr, ids, tasks, \
-                     n, prefix, layers, k, scratch)
+                     n, tmap, layers, k, scratch)
   if (bm == 32) {
     if (bn == 32) HELM_BWD(32, 32); else HELM_BWD(32, 64);
   } else {
@@ -434,40 +441,41 @@ void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks,
 }
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
-                       const int* prefix, int total, const LayerDev* layers, int k,
+                       const int2* tmap, int total, const LayerDev* layers, int k,
                        const void* scratch, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_bwd_reduce<T>, dim3(total), dim3(256), 0, st, fr, ids, tasks, n,
-                     prefix, layers, k, scratch);
+                     tmap, layers, k, scratch);
 }
 
 #define HELM_INST_SOLVE(T)                                                           \
-  template void launch_fwd_gather<T>(const FrontDev*, const int*, int, const int*,   \
+  template void launch_fwd_gather<T>(const FrontDev*, const int*, int, const int2*,   \
                                      int, const LayerDev*, int, hipStream_t);        \
   template void launch_fwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
-                                   int, const int*, int, const LayerDev*, int,       \
+                                   int, const int2*, int, const LayerDev*, int,       \
                                    void*, int, hipStream_t);                         \
   template void launch_fwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
-                                     int, const int*, int, const LayerDev*, int,     \
+                                     int, const int2*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);                      \
   template void launch_bwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
-                                   int, const int*, int, const LayerDev*, int,       \
+                                   int, const int2*, int, const LayerDev*, int,       \
                                    void*, int, int, hipStream_t);                    \
   template void launch_bwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
-                                     int, const int*, int, const LayerDev*, int,     \
+                                     int, const int2*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);
 HELM_INST_SOLVE(float)
 HELM_INST_SOLVE(double)
 
 #define HELM_INST_GEMV(T)                                                            \
   template void launch_fwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
-                                   int, const int*, int, const LayerDev*, int,       \
+                                   int, const int2*, int, const LayerDev*, int,       \
                                    void*, hipStream_t);                              \
   template void launch_bwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
-                                   int, const int*, int, const LayerDev*, int,       \
+                                   int, const int2*, int, const LayerDev*, int,       \
                                    void*, int, hipStream_t);
 HELM_INST_GEMV(float)
 HELM_INST_GEMV(double)
+
 
 }  // namespace kern
 }  // namespace helm
