@@ -1,0 +1,54 @@
+"""The headline workload at its full size (200^3, L = 20, 64 sources, the
+launch configuration of bench.py), checked with properties that hold at any
+size, the oracle supplying the operator:
+
+* the oracle's own assembly of H gives |f - H u| / |f| for sampled columns
+  of the GPU solution; the refinement stops at an estimated error of 1e-6,
+  and its residual must be below that;
+* reciprocity of the symmetric operator: for neighbouring sources s, r the
+  field of s at r equals the field of r at s."""
+
+import numpy as np
+import pytest
+
+from helm_inputs import workload
+from oracle.discretization import Problem, point_source_rhs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.filterwarnings("ignore::DeprecationWarning")]
+
+torch = pytest.importorskip("torch")
+
+
+def test_layered_200_residual_and_reciprocity():
+    import paper_1801_08655_amd as pt
+    wl = workload("layered-200")
+    m = wl.m()
+    srcs = wl.point_sources(64)
+    s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
+                  pml_local=wl.pml_local, pml_C=wl.pml_C, ir_tol=1e-10, inner_tol=1e-3,
+                  inner_tol_refine=1e-4, err_target=1e-6, ir_max_steps=4,
+                  flags=pt._lib.HELM_FLAG_AUTOTUNE)
+    u, info = s.solve_points(srcs, info=True)
+    print(info)
+    assert info["ir_steps"] >= 2 and info["est_error_max"] <= 1e-6
+    sample = [0, 9, 36, 63]
+    cols = {c: u[c].cpu().numpy().ravel() for c in sample + [1, 8]}
+    s.close()
+    del u
+    torch.cuda.empty_cache()
+    pb = Problem(m, wl.h, wl.omega, wl.pml, wl.pml_C)
+    H = pb.operator()
+    F = point_source_rhs(pb.shape, [srcs[c] for c in sample], wl.h)
+    for j, c in enumerate(sample):
+        r = F[:, j] - H @ cols[c]
+        rel = np.linalg.norm(r) / np.linalg.norm(F[:, j])
+        print(f"column {c} oracle residual {rel:.2e}")
+        assert rel <= 1e-6
+    nx, ny, _ = wl.n
+    idx = lambda p: p[0] + nx * (p[1] + ny * p[2])
+    for a, b in ((0, 1), (0, 8), (1, 9), (8, 9)):
+        uab = cols[a][idx(srcs[b])]
+        uba = cols[b][idx(srcs[a])]
+        print(f"reciprocity {a}-{b}: {abs(uab - uba) / abs(uab):.2e}")
+        assert abs(uab - uba) <= 1e-5 * abs(uab)
