@@ -245,6 +245,12 @@ def serve_bench(args, torch, pt):
     rate = 0.75 * nominal["rhs_per_s"] / mean_r
     scaled = run(poisson_requests(args.serve_requests, rate, len(models), cands, seed=1807),
                  "75% of capacity")
+    # an idle server: one single-source request per model at a time (the
+    # lane runs it at width 1)
+    idle = []
+    for mid in range(len(models)):
+        _, inf = srv.submit(mid, cands[17:18]).wait()
+        idle.append(inf["latency_ms"])
     st = srv.stats()
     srv.close()
     for s in solvers:
@@ -260,6 +266,7 @@ def serve_bench(args, torch, pt):
         "factor_s": factor_s,
         "nominal_rate_50_per_s": nominal,
         "scaled_rate": dict(scaled, rate_req_per_s=rate),
+        "idle_single_source_latency_ms": idle,
         "server": st,
     }
     print(json.dumps(out), flush=True)

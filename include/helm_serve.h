@@ -14,9 +14,12 @@
  *    in the model's FIFO queue and enter free slots of the lane between
  *    refinement steps, while the columns already in the lane continue;
  *    all slots of a lane share every layer-solve launch.
- *  - Each step applies one polarized solve to every slot (Algorithm 2,
- *    complex64 factors for HELM_MIXED handles) and then the FP64 residual
- *    r = f - H u.  A column leaves its slot, and its volume is copied to the
+ *  - Each step applies one polarized solve to every occupied slot
+ *    (Algorithm 2, complex64 factors for HELM_MIXED handles) and then the
+ *    FP64 residual r = f - H u.  Occupied slots are kept at the front of the
+ *    lane and a step runs at the narrowest width of 1, 2, 4, ... up to the
+ *    slot count that covers them, so a lightly loaded lane does not pay for
+ *    its empty slots.  A column leaves its slot, and its volume is copied to the
  *    request's output, when its relative residual reaches ir_tol or its
  *    estimated error reaches err_target, or after ir_max_steps steps
  *    (request status HELM_ENOCONV).  The first step of a column uses the
@@ -27,9 +30,10 @@
  *    rounding order of the GEMM tiles, which does not depend on the
  *    neighbouring columns either).
  *  - Memory admission: a model is admitted with the largest slot count (at
- *    most `slots`) whose workspace, with the factors, fits the server's
- *    budget; a model that does not fit with one slot is refused with
- *    HELM_ENOMEM.
+ *    most `slots`) whose workspace (that of the full width plus the
+ *    interface vectors of the narrower widths), with the factors, fits the
+ *    server's budget; a model that does not fit with one slot is refused
+ *    with HELM_ENOMEM.
  *
  * Thread safety: all calls may be made from any host thread.  A handle
  * given to a server must not be used through any other call, nor freed,

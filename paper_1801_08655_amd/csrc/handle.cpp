@@ -229,15 +229,19 @@ size_t plan_factor_elems(const Geometry& G) {
   return s;
 }
 
+// FP64 interface vectors of one column: Krylov basis (up to 16 + 2 vectors)
+// and sweep temporaries (about 8), each 2 pair vectors of (L-1) x 2 planes
+size_t plan_pair_bytes_per_rhs(const Geometry& G) {
+  const size_t pv = (size_t)std::max(G.L - 1, 0) * 2 * G.nx * G.ny * 16;
+  return pv * 2 * (18 + 8);
+}
+
 size_t plan_bytes_per_rhs(const Geometry& G, size_t elem) {
   // local solve vectors of every layer (X, Wt, Ub even/odd)
   size_t per = 0;
   for (const auto& P : G.layers)
     per += ((size_t)P.n_loc + P.wt_rows + P.ub_rows[0] + P.ub_rows[1]) * elem;
-  // FP64 interface vectors: Krylov basis (up to 16 + 2 vectors) and sweep
-  // temporaries (about 8), each 2 pair vectors of (L-1) x 2 planes
-  size_t pv = (size_t)std::max(G.L - 1, 0) * 2 * G.nx * G.ny * 16;
-  per += pv * 2 * (18 + 8);
+  per += plan_pair_bytes_per_rhs(G);
   // FP64 volumes: f, u, r, correction
   per += (size_t)G.nx * G.ny * G.nz * 16 * 4;
   return per;

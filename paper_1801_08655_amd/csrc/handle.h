@@ -164,5 +164,6 @@ struct Handle {
 
 size_t plan_factor_elems(const Geometry& G);
 size_t plan_bytes_per_rhs(const Geometry& G, size_t elem);
+size_t plan_pair_bytes_per_rhs(const Geometry& G);
 
 }  // namespace helm

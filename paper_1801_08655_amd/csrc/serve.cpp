@@ -2,13 +2,14 @@
 // factorizations (contracts in include/helm_serve.h).
 //
 // One lane per model: K column slots in FP64 volumes F (source), U (iterate),
-// R (residual) and D (correction), a Method of width K on the handle's
-// stream, and a host thread.  A lane step is one refinement step over all K
-// slots (Method::refine_step); between steps finished columns are copied
-// out and queued columns take their slots.  Empty slots hold zero volumes,
-// which every stage of the solve maps to zero (GMRES treats a zero
-// right-hand side as converged), so they cost launch width but do not
-// change the other columns.
+// R (residual) and D (correction), Methods of widths 1, 2, 4, ..., K on the
+// handle's stream, and a host thread.  A lane step is one refinement step
+// over the occupied slots, which are kept at the front (Method::refine_step
+// at the narrowest width covering them); between steps finished columns are
+// copied out, the last live slots move into their places, and queued
+// columns take the free slots.  Empty slots inside the width hold zero
+// volumes, which every stage of the solve maps to zero (GMRES treats a zero
+// right-hand side as converged), so they never change the other columns.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -42,6 +43,17 @@ void Server::finish_column(Request* r, int status, int nsteps, double rel, doubl
   }
 }
 
+// The Method of the narrowest width (1, 2, 4, ... up to K) that covers the
+// occupied slots; one is created per width on first use.
+Method& Lane::method_for(int occ) {
+  int w = 1;
+  while (w < occ) w *= 2;
+  w = std::min(w, K);
+  auto it = methods.find(w);
+  if (it == methods.end()) it = methods.emplace(w, std::make_unique<Method>(h->impl, w)).first;
+  return *it->second;
+}
+
 void Server::run_lane(Lane& ln) {
   Handle& H = ln.h->impl;
   (void)hipSetDevice(H.device);
@@ -53,6 +65,7 @@ void Server::run_lane(Lane& ln) {
   std::vector<int> fresh;
   struct Done { int slot, status, steps; double rel, est; };
   std::vector<Done> done;
+  std::vector<std::pair<int, int>> moves;   // (from, to) slot moves after a step
   while (true) {
     fresh.clear();
     {
@@ -62,9 +75,9 @@ void Server::run_lane(Lane& ln) {
       });
       if (stop) return;
       if (ln.retire && ln.occupied() == 0 && ln.queue.empty()) return;
-      // admission: queued columns take the free slots, oldest request first
-      for (int s = 0; s < ln.K && !ln.queue.empty(); ++s) {
-        if (ln.slots[s].req) continue;
+      // admission: queued columns take the free slots (after the occupied
+      // ones, which are kept at the front), oldest request first
+      for (int s = ln.occupied(); s < ln.K && !ln.queue.empty(); ++s) {
         Request* r = ln.queue.front();
         const int c = r->next_col++;
         ln.slots[s] = Slot{r, c, 0, 0.0};
@@ -75,7 +88,9 @@ void Server::run_lane(Lane& ln) {
         if (r->next_col == r->n) ln.queue.pop_front();
       }
     }
+    const int occ = ln.occupied();
     done.clear();
+    moves.clear();
     int step_status = HELM_OK;
     std::string step_error;
     try {
@@ -97,39 +112,61 @@ void Server::run_lane(Lane& ln) {
         HELM_HIP(hipMemcpyAsync(R + s * N, F + s * N, col_bytes, hipMemcpyDeviceToDevice,
                                 H.st));
       }
-      std::vector<double> tol(ln.K, 0.0);
-      for (int s = 0; s < ln.K; ++s)
+      // one refinement step over the occupied slots 0..occ-1 at the
+      // narrowest width covering them (the extra columns are empty)
+      Method& M = ln.method_for(occ);
+      const int w = M.k;
+      std::vector<double> tol(w, 0.0);
+      for (int s = 0; s < w; ++s)
         tol[s] = fp64 ? H.opt.gmres_tol
                       : (ln.slots[s].steps == 0 ? H.opt.inner_tol : H.opt.inner_tol_refine);
-      ln.M->refine_step(F, U, R, ln.D.as<double2>(), tol, nm, nullptr);
-      for (int s = 0; s < ln.K; ++s) {
+      M.refine_step(F, U, R, ln.D.as<double2>(), tol, nm, nullptr);
+      std::vector<char> fin(ln.K, 0);
+      for (int s = 0; s < occ; ++s) {
         Slot& sl = ln.slots[s];
-        if (!sl.req) continue;
         const int st = sl.steps++;
         const double rel = nm.rel[s];
         const double est = fp64 ? 0.0 : refinement_error(st, sl.dprev, nm.dn[s], nm.un[s]);
         sl.dprev = nm.dn[s];
-        bool fin;
+        bool f;
         int status = HELM_OK;
         if (fp64) {
           // one step: GMRES to gmres_tol (a single layer is a direct solve)
-          fin = true;
-          if (H.G.L > 1 && !(ln.M->last_resid.size() > (size_t)s &&
-                             ln.M->last_resid[s] <= H.opt.gmres_tol))
+          f = true;
+          if (H.G.L > 1 && !(M.last_resid.size() > (size_t)s && M.last_resid[s] <= H.opt.gmres_tol))
             status = HELM_ENOCONV;
         } else {
           const bool ok = rel <= H.opt.ir_tol || (H.opt.err_target > 0 && est <= H.opt.err_target);
-          fin = ok || sl.steps >= std::max(1, H.opt.ir_max_steps);
+          f = ok || sl.steps >= std::max(1, H.opt.ir_max_steps);
           if (!ok) status = HELM_ENOCONV;
         }
-        if (!std::isfinite(rel)) { fin = true; status = HELM_ENOCONV; }
-        if (!fin) continue;
+        if (!std::isfinite(rel)) { f = true; status = HELM_ENOCONV; }
+        if (!f) continue;
+        fin[s] = 1;
         HELM_HIP(hipMemcpyAsync(sl.req->out + (long long)sl.col * N, U + s * N, col_bytes,
                                 hipMemcpyDefault, H.st));
         HELM_HIP(hipMemsetAsync(F + s * N, 0, col_bytes, H.st));
         HELM_HIP(hipMemsetAsync(U + s * N, 0, col_bytes, H.st));
         HELM_HIP(hipMemsetAsync(R + s * N, 0, col_bytes, H.st));
         done.push_back(Done{s, status, sl.steps, rel, est});
+      }
+      // keep the occupied slots at the front: the last live slots move down
+      // into the holes (their three volumes are copied, the source cleared)
+      int lo = 0, hi = occ - 1;
+      while (true) {
+        while (lo < hi && !fin[lo]) ++lo;
+        while (hi > lo && fin[hi]) --hi;
+        if (lo >= hi || !fin[lo] || fin[hi]) break;
+        for (double2* V : {F, U, R}) {
+          HELM_HIP(hipMemcpyAsync(V + lo * N, V + hi * N, col_bytes, hipMemcpyDeviceToDevice,
+                                  H.st));
+          HELM_HIP(hipMemsetAsync(V + hi * N, 0, col_bytes, H.st));
+        }
+        moves.push_back({hi, lo});
+        fin[lo] = 0;
+        fin[hi] = 1;
+        ++lo;
+        --hi;
       }
       HELM_HIP(hipStreamSynchronize(H.st));
     } catch (const Error& e) {
@@ -140,7 +177,6 @@ void Server::run_lane(Lane& ln) {
       step_error = e.what();
     }
     std::lock_guard<std::mutex> lk(mu);
-    const int occ = ln.occupied();
     ++steps;
     slot_steps += occ;
     if (step_status != HELM_OK) {
@@ -165,6 +201,10 @@ void Server::run_lane(Lane& ln) {
       finish_column(sl.req, d.status, d.steps, d.rel, d.est);
       sl = Slot{};
     }
+    for (const auto& mv : moves) {
+      ln.slots[mv.second] = ln.slots[mv.first];
+      ln.slots[mv.first] = Slot{};
+    }
   }
 }
 
@@ -181,7 +221,9 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   // memory admission: the largest slot count whose workspace fits
   int K = std::max(1, max_slots);
   auto fits = [&](int k) {
-    const size_t ws = per * (size_t)k;
+    // the lane's full-width workspace plus the Krylov and sweep vectors of
+    // its narrower widths (together at most those of one more full width)
+    const size_t ws = (per + plan_pair_bytes_per_rhs(H.G)) * (size_t)k;
     if (opt.hbm_budget_bytes) return reserved + H.bytes_factors + ws <= opt.hbm_budget_bytes;
     return ws <= (size_t)(0.9 * (double)free_b);
   };
@@ -191,7 +233,7 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   ln->model = (int)lanes.size();
   ln->h = h;
   ln->K = K;
-  ln->bytes = H.bytes_factors + per * (size_t)K;
+  ln->bytes = H.bytes_factors + (per + plan_pair_bytes_per_rhs(H.G)) * (size_t)K;
   const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
   const size_t vol = (size_t)N * K * sizeof(double2);
   ln->F.alloc(vol);
@@ -202,8 +244,9 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   ln->amps_d.alloc(K * sizeof(double2));
   for (DevMem* d : {&ln->F, &ln->U, &ln->R}) HELM_HIP(hipMemsetAsync(d->p, 0, vol, H.st));
   HELM_HIP(hipStreamSynchronize(H.st));
-  h->method.reset();   // the lane's Method owns the solve workspace from here
-  ln->M.reset(new Method(H, K));
+  h->method.reset();   // the lane's Methods own the solve workspace from here
+  H.ensure_workspace(K);
+  ln->methods.emplace(K, std::make_unique<Method>(H, K));
   ln->slots.assign(K, Slot{});
   ln->node_h.assign(K, 0);
   ln->amp_h.assign(K, make_double2(0, 0));
@@ -275,7 +318,7 @@ void Server::remove_model(int model) {
   Handle& H = ln->h->impl;
   (void)hipSetDevice(H.device);
   HELM_HIP(hipStreamSynchronize(H.st));
-  ln->M.reset();
+  ln->methods.clear();
   for (DevMem* d : {&ln->F, &ln->U, &ln->R, &ln->D, &ln->nodes_d, &ln->amps_d}) d->release();
   std::lock_guard<std::mutex> lk(mu);
   reserved -= ln->bytes;
@@ -305,7 +348,7 @@ void Server::shutdown() {
     if (l->gone) continue;
     (void)hipSetDevice(l->h->impl.device);
     (void)hipStreamSynchronize(l->h->impl.st);
-    l->M.reset();
+    l->methods.clear();
   }
 }
 

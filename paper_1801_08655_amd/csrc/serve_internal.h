@@ -3,6 +3,7 @@
 
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -41,7 +42,8 @@ struct Lane {
   size_t bytes = 0;
   bool retire = false;          // leave the loop once idle (model removed)
   bool gone = false;            // thread joined, memory released
-  std::unique_ptr<Method> M;
+  std::map<int, std::unique_ptr<Method>> methods;   // by width (1, 2, 4, ..., K)
+  Method& method_for(int occupied);
   DevMem F, U, R, D, nodes_d, amps_d;
   std::vector<Slot> slots;
   std::deque<Request*> queue;   // requests with columns not yet in a slot
