@@ -206,3 +206,27 @@ def test_autotuned_tiles_give_the_same_solution():
     assert {c["fwd_bn"] for c in ch} <= {16, 32} and {c["bwd_bn"] for c in ch} <= {16, 32}
     assert any(c["t_fwd_us"][1] > 0 and c["t_fwd_us"][2] > 0 for c in ch)
     assert all(c["tuned"] == 0 for c in a.tile_choices())
+
+
+@pytest.mark.parametrize("name,precision,tol", [("homogeneous-25", "fp64", 1e-9),
+                                                ("layered-28", "fp64", 1e-9),
+                                                ("layered-28", "mixed", 1e-6)])
+def test_solution_matches_stored_oracle_samples(name, precision, tol):
+    """Sampled nodes of the solution against tests/golden (written from the
+    oracle's direct solve by tests/golden/make_golden.py)."""
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "make_golden.py")
+    spec = importlib.util.spec_from_file_location("make_golden", path)
+    g = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(g)
+    srcs, rows = g.read(name)
+    wl = workload(name)
+    s = _solver(wl, precision)
+    u = s.solve_points(srcs).cpu().numpy()
+    nx, ny, nz = wl.n
+    u = u.reshape(len(srcs), -1)
+    scale = max(abs(v) for *_, v in rows)
+    worst = max(abs(u[c, i + nx * (j + ny * k)] - v) for c, i, j, k, v in rows) / scale
+    print(name, precision, "max sampled deviation", worst)
+    assert worst <= tol

@@ -307,3 +307,46 @@ def test_single_layer_is_global_solve():
     pt = PolarizedTraces(pb, 1, 4)
     up, iters, _ = pt.solve(F[:, 0].reshape(pb.shape))
     assert relative_error(up.ravel(), u)[0] <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# stored fixtures (tests/golden)
+# --------------------------------------------------------------------------
+
+def _golden():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "make_golden.py")
+    spec = importlib.util.spec_from_file_location("make_golden", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("name", ["homogeneous-25", "layered-28"])
+def test_oracle_reproduces_its_stored_fields(name):
+    """The stored samples were written by tests/golden/make_golden.py from
+    the oracle; a change of the oracle's arithmetic shows up here."""
+    g = _golden()
+    srcs, rows = g.read(name)
+    wl, srcs2, U = g.solve(name)
+    assert [tuple(s) for s in srcs2] == srcs
+    nx, ny, _ = wl.n
+    scale = max(abs(v) for *_, v in rows)
+    for c, i, j, k, v in rows:
+        assert abs(U[i + nx * (j + ny * k), c] - v) <= 1e-12 * scale
+
+
+def test_iteration_count_within_the_papers_range():
+    """Plausibility, not parity: the polarized-traces GMRES of the oracle on
+    the homogeneous 25^3 problem reaches the paper's stopping residual 1e-7
+    within the paper's reported iteration counts (plus a margin of 2)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_iterations.txt")
+    counts = [int(l.split()[-1]) for l in open(path) if l.strip() and not l.startswith("#")]
+    wl = workload("homogeneous-25")
+    pb = Problem(wl.m(), wl.h, wl.omega, wl.pml, wl.pml_C)
+    f = point_source_rhs(pb.shape, wl.sources, wl.h)[:, 0].reshape(pb.shape)
+    pt_cpu = PolarizedTraces(pb, wl.n_layers, wl.pml_local)
+    _, iters, _ = pt_cpu.solve(f, tol=1e-7)
+    assert 1 <= iters <= max(counts) + 2
