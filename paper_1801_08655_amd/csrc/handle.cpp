@@ -61,6 +61,25 @@ int tiles16(long long n) { return (int)((n + 15) / 16); }
 
 }  // namespace
 
+EventPair::EventPair() {
+  HELM_HIP(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    a = nullptr;
+    throw Error{HELM_EHIP, "hipEventCreate failed"};
+  }
+}
+EventPair::~EventPair() {
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+}
+double EventPair::elapsed_ms(hipStream_t) const {
+  HELM_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  HELM_HIP(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
 void Handle::clear_graphs() {
   for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
   graphs.clear();
@@ -710,20 +729,15 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
       off += b;
     }
   }
-  hipEvent_t e0, e1;
-  HELM_HIP(hipEventCreate(&e0));
-  HELM_HIP(hipEventCreate(&e1));
+  EventPair ev;
   const int widths[4] = {1, 16, 32, 64};
   auto time_us = [&](auto&& launch) {
     double best = 1e30;
     for (int rep = 0; rep < 3; ++rep) {
-      HELM_HIP(hipEventRecord(e0, st));
+      HELM_HIP(hipEventRecord(ev.a, st));
       launch();
-      HELM_HIP(hipEventRecord(e1, st));
-      HELM_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      HELM_HIP(hipEventElapsedTime(&ms, e0, e1));
-      best = std::min(best, 1e3 * (double)ms);
+      HELM_HIP(hipEventRecord(ev.b, st));
+      best = std::min(best, 1e3 * ev.elapsed_ms(st));
     }
     return best;
   };
@@ -770,8 +784,6 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
     }
   }
   HELM_HIP(hipStreamSynchronize(st));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
 }
 
 template <typename T>

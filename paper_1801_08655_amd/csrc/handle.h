@@ -23,6 +23,17 @@ struct DevMem {
   template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
+// A pair of timing events, destroyed with the scope that owns them.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair();
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+  ~EventPair();
+  // milliseconds between recording a and b on the stream
+  double elapsed_ms(hipStream_t st) const;
+};
+
 // Fronts of one depth over a set of layers, for the substitutions.
 struct DepthList {
   int n = 0;

@@ -76,11 +76,18 @@ extern "C" int helm_device_peaks(int device, double* mfma_f32_tflops, double* mf
                                  double* hbm_read_gbps, double* hbm_copy_gbps) {
   return guard([&] {
     HELM_HIP(hipSetDevice(device));
-    hipStream_t st;
-    HELM_HIP(hipStreamCreate(&st));
-    hipEvent_t e0, e1;
-    HELM_HIP(hipEventCreate(&e0));
-    HELM_HIP(hipEventCreate(&e1));
+    struct OwnedStream {
+      hipStream_t s = nullptr;
+      ~OwnedStream() {
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+      }
+    } os;
+    HELM_HIP(hipStreamCreate(&os.s));
+    hipStream_t st = os.s;
+    EventPair ev;
     int cus = 0;
     HELM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     const int blocks = std::max(1, cus) * 8, threads = 256;
@@ -94,13 +101,10 @@ extern "C" int helm_device_peaks(int device, double* mfma_f32_tflops, double* mf
     auto best_ms = [&](auto&& launch) {
       float best = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
-        HELM_HIP(hipEventRecord(e0, st));
+        HELM_HIP(hipEventRecord(ev.a, st));
         launch();
-        HELM_HIP(hipEventRecord(e1, st));
-        HELM_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        HELM_HIP(hipEventElapsedTime(&ms, e0, e1));
-        best = std::min(best, ms);
+        HELM_HIP(hipEventRecord(ev.b, st));
+        best = std::min(best, (float)ev.elapsed_ms(st));
       }
       return (double)best;
     };
@@ -129,9 +133,6 @@ extern "C" int helm_device_peaks(int device, double* mfma_f32_tflops, double* mf
     if (hbm_copy_gbps) *hbm_copy_gbps = 2.0 * (double)bytes / ms / 1e6;
     HELM_HIP(hipGetLastError());
     HELM_HIP(hipStreamSynchronize(st));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipStreamDestroy(st);
     return HELM_OK;
   });
 }

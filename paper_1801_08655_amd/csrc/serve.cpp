@@ -284,6 +284,8 @@ Request* Server::submit(int model, int n, const int64_t* nodes, const double* am
     r->amps[c] = make_double2(amps[2 * c], amps[2 * c + 1]);
   }
   std::lock_guard<std::mutex> lk(mu);
+  // the model may have been removed since the check above
+  HELM_REQUIRE(!stop && !ln->retire, HELM_EINVAL, "model removed or server stopping");
   r->id = next_id++;
   r->info.status = HELM_OK;
   r->info.n_rhs = n;
