@@ -230,3 +230,26 @@ def test_solution_matches_stored_oracle_samples(name, precision, tol):
     worst = max(abs(u[c, i + nx * (j + ny * k)] - v) for c, i, j, k, v in rows) / scale
     print(name, precision, "max sampled deviation", worst)
     assert worst <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-6)])
+def test_non_cubic_grid_matches_direct(precision, tol):
+    """nx, ny and nz all different (and not multiples of the tile sizes),
+    an uneven layer split and sources off the axes."""
+    from helm_inputs import smooth_random_model, omega_for_ppw
+    import paper_1801_08655_amd as pt
+    nx, ny, nz = 23, 18, 29
+    h = 1.0 / 22
+    p, L = 4, 3
+    m = smooth_random_model((nx, ny, nz), 0.2, 3.0, 0.8, 1.2, 77)
+    om = omega_for_ppw(0.8, h, 10.0)
+    srcs = [(6, 9, 7), (15, 5, 20), (11, 12, 14)]
+    pb = Problem(m, h, om, p, 25.0)
+    assert pb.shape == (nz, ny, nx)
+    ref = SparseLU(pb.operator()).solve(point_source_rhs(pb.shape, srcs, h))
+    s = pt.Solver(m, h, om, p, L, precision=precision, pml_C=25.0, pml_local=3)
+    u = s.solve_points(srcs).cpu().numpy()
+    assert u.shape == (3, nz, ny, nx)
+    err = relative_error(u.reshape(3, -1).T, ref)
+    print(precision, "non-cubic err", err)
+    assert err.max() <= tol
