@@ -170,6 +170,7 @@ k_orig_entries(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // --------------------------------------------------------------------------
 constexpr int PANEL_THREADS = 1024;
 constexpr int NBMAX = 64;
+constexpr int PB = 8;   // column block of the panel LU
 
 template <typename T>
 __global__ void __launch_bounds__(PANEL_THREADS)
@@ -200,63 +201,103 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   __shared__ int red_i[PANEL_THREADS / 64];
   __shared__ int piv_row;
   __syncthreads();
-  for (int c = 0; c < nbf; ++c) {
-    // arg max |P[r][c]|, r >= c (ties: smallest row, so the choice is
-    // reproducible)
-    double best = -1.0;
-    int bi = R;
-    for (int r = c + t; r < R; r += PANEL_THREADS) {
-      double v = cabs2(P[r + (long long)c * R]);
-      if (v > best) { best = v; bi = r; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      double ov = __shfl_down(best, off);
-      int oi = __shfl_down(bi, off);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if ((t & 63) == 0) { red_v[t >> 6] = best; red_i[t >> 6] = bi; }
-    __syncthreads();
-    if (t == 0) {
-      double bv = red_v[0];
-      int bidx = red_i[0];
-      for (int w = 1; w < PANEL_THREADS / 64; ++w)
-        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bidx)) {
-          bv = red_v[w];
-          bidx = red_i[w];
+  // Blocked right-looking LU of the panel: columns in blocks of PB; inside
+  // a block every column is pivoted, scaled and applied to the block's
+  // remaining columns; then the block rows of the trailing columns are
+  // solved with the block's unit lower triangle and the trailing columns
+  // get one rank-PB update (one pass over them per block instead of one per
+  // column).
+  __shared__ C U12[PB][NBMAX];
+  for (int c0 = 0; c0 < nbf; c0 += PB) {
+    const int c1 = (c0 + PB < nbf) ? c0 + PB : nbf;
+    for (int c = c0; c < c1; ++c) {
+      // arg max |P[r][c]|, r >= c (ties: smallest row, so the choice is
+      // reproducible)
+      double best = -1.0;
+      int bi = R;
+      for (int r = c + t; r < R; r += PANEL_THREADS) {
+        double v = cabs2(P[r + (long long)c * R]);
+        if (v > best) { best = v; bi = r; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_down(best, off);
+        int oi = __shfl_down(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if ((t & 63) == 0) { red_v[t >> 6] = best; red_i[t >> 6] = bi; }
+      __syncthreads();
+      if (t == 0) {
+        double bv = red_v[0];
+        int bidx = red_i[0];
+        for (int w = 1; w < PANEL_THREADS / 64; ++w)
+          if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bidx)) {
+            bv = red_v[w];
+            bidx = red_i[w];
+          }
+        if (!(bv > 0.0) || !isfinite(bv)) {
+          atomicExch(status, 1);   // zero or non-finite pivot
+          bidx = c;
         }
-      if (!(bv > 0.0) || !isfinite(bv)) {
-        atomicExch(status, 1);   // zero or non-finite pivot
-        bidx = c;
+        piv_row = bidx;
+        ipiv[c] = bidx;
+        if (bidx != c) {
+          int tmp = perm[k + c];
+          perm[k + c] = perm[k + bidx];
+          perm[k + bidx] = tmp;
+        }
       }
-      piv_row = bidx;
-      ipiv[c] = bidx;
-      if (bidx != c) {
-        int tmp = perm[k + c];
-        perm[k + c] = perm[k + bidx];
-        perm[k + bidx] = tmp;
+      __syncthreads();
+      const int p = piv_row;
+      if (p != c)
+        for (int cc = t; cc < nbf; cc += PANEL_THREADS) {
+          C x = P[c + (long long)cc * R];
+          P[c + (long long)cc * R] = P[p + (long long)cc * R];
+          P[p + (long long)cc * R] = x;
+        }
+      __syncthreads();
+      C piv = P[c + (long long)c * R];
+      if (cabs2(piv) == 0.0) piv = cmake<C>(1.0, 0.0);
+      const C one = cmake<C>(1.0, 0.0);
+      const C ipv = cdiv(one, piv);
+      for (int r = c + 1 + t; r < R; r += PANEL_THREADS)
+        P[r + (long long)c * R] = cmul(P[r + (long long)c * R], ipv);
+      __syncthreads();
+      // rank-1 update of the block's remaining columns
+      const int rows = R - c - 1, cols = c1 - c - 1;
+      for (long long e = t; e < (long long)rows * cols; e += PANEL_THREADS) {
+        int r = c + 1 + (int)(e % rows), cc = c + 1 + (int)(e / rows);
+        C& x = P[r + (long long)cc * R];
+        cfms(x, P[r + (long long)c * R], P[c + (long long)cc * R]);
+      }
+      __syncthreads();
+    }
+    if (c1 >= nbf) break;
+    const int W = nbf - c1, bw = c1 - c0;
+    // block rows of the trailing columns: U12 = L11^-1 A12 (unit lower)
+    for (int cc = t; cc < W; cc += PANEL_THREADS) {
+      const long long col = (long long)(c1 + cc) * R;
+      for (int i = 0; i < bw; ++i) {
+        C x = P[c0 + i + col];
+        for (int j = 0; j < i; ++j) cfms(x, P[c0 + i + (long long)(c0 + j) * R], U12[j][cc]);
+        U12[i][cc] = x;
+        P[c0 + i + col] = x;
       }
     }
     __syncthreads();
-    const int p = piv_row;
-    if (p != c)
-      for (int cc = t; cc < nbf; cc += PANEL_THREADS) {
-        C x = P[c + (long long)cc * R];
-        P[c + (long long)cc * R] = P[p + (long long)cc * R];
-        P[p + (long long)cc * R] = x;
+    // rank-bw update of the trailing columns below the block
+    for (int r = c1 + t; r < R; r += PANEL_THREADS) {
+      C l[PB];
+#pragma unroll
+      for (int j = 0; j < PB; ++j)
+        l[j] = j < bw ? P[r + (long long)(c0 + j) * R] : czero<C>();
+      for (int cc = 0; cc < W; ++cc) {
+        C& x = P[r + (long long)(c1 + cc) * R];
+        C y = x;
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+          if (j < bw) cfms(y, l[j], U12[j][cc]);
+        x = y;
       }
-    __syncthreads();
-    C piv = P[c + (long long)c * R];
-    if (cabs2(piv) == 0.0) piv = cmake<C>(1.0, 0.0);
-    const C one = cmake<C>(1.0, 0.0);
-    const C ipv = cdiv(one, piv);
-    for (int r = c + 1 + t; r < R; r += PANEL_THREADS)
-      P[r + (long long)c * R] = cmul(P[r + (long long)c * R], ipv);
-    __syncthreads();
-    const int rows = R - c - 1, cols = nbf - c - 1;
-    for (long long e = t; e < (long long)rows * cols; e += PANEL_THREADS) {
-      int r = c + 1 + (int)(e % rows), cc = c + 1 + (int)(e / rows);
-      C& x = P[r + (long long)cc * R];
-      cfms(x, P[r + (long long)c * R], P[c + (long long)cc * R]);
     }
     __syncthreads();
   }
