@@ -112,6 +112,17 @@ typedef struct {
                                 (|d_k|/|u| * q/(1-q), q = |d_k|/|d_{k-1}|);
                                 1 when only one step was taken               */
   int    ir_gmres_iters[8];  /* GMRES iterations of each refinement step     */
+  /* Per right-hand side: arrays of n_rhs entries owned by the caller, each
+   * may be NULL; set them before the call (they survive the call's reset of
+   * the other fields) and the solve fills them. */
+  double* rhs_rel_residual;  /* final FP64 |f - H u| / |f| of each column    */
+  double* rhs_est_error;     /* mixed: estimated relative error of each
+                                column (as est_error_max); 0 for FP64         */
+  int*    rhs_ir_steps;      /* refinement step at which the column first met
+                                ir_tol or err_target (the steps taken if it
+                                never did; 1 for FP64)                        */
+  int*    rhs_gmres_iters;   /* GMRES iterations in which the column was
+                                still active, summed over refinement steps   */
 } helm_solve_info;
 
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,

@@ -109,7 +109,7 @@ class Solver:
             fh = np.ascontiguousarray(f, dtype=np.complex128)
             k = fh.size // self.N
             uh = np.empty_like(fh)
-            inf = _lib.helm_solve_info()
+            inf = _lib.helm_solve_info().attach(k)
             st = lib().helm_solve(self._h, k, fh.ctypes.data, uh.ctypes.data,
                                   ctypes.byref(inf))
             self._check_solve(st)
@@ -119,7 +119,7 @@ class Solver:
             raise TypeError("f must be complex128")
         k = f.numel() // self.N
         u = torch.empty_like(f)
-        inf = _lib.helm_solve_info()
+        inf = _lib.helm_solve_info().attach(k)
         st = lib().helm_solve_dev(self._h, k, _ptr(f), _ptr(u), ctypes.byref(inf))
         self._check_solve(st)
         return (u, inf.as_dict()) if info else u
@@ -135,7 +135,7 @@ class Solver:
             np.ascontiguousarray(amplitudes, dtype=np.complex128)
         u = out if out is not None else torch.empty((r, nz, ny, nx), dtype=torch.complex128,
                                                     device="cuda")
-        inf = _lib.helm_solve_info()
+        inf = _lib.helm_solve_info().attach(r)
         st = lib().helm_solve_points(self._h, r, idx.ctypes.data, amp.ctypes.data, _ptr(u),
                                      ctypes.byref(inf))
         self._check_solve(st)

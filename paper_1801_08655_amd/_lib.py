@@ -77,13 +77,31 @@ class helm_solve_info(ctypes.Structure):
         ("ir_residual", ctypes.c_double * 8),
         ("est_error_max", ctypes.c_double),
         ("ir_gmres_iters", ctypes.c_int * 8),
+        ("rhs_rel_residual", ctypes.c_void_p),
+        ("rhs_est_error", ctypes.c_void_p),
+        ("rhs_ir_steps", ctypes.c_void_p),
+        ("rhs_gmres_iters", ctypes.c_void_p),
     ]
+    PER_RHS = ("rhs_rel_residual", "rhs_est_error", "rhs_ir_steps", "rhs_gmres_iters")
+
+    def attach(self, n):
+        """Per-right-hand-side output arrays for n columns (kept alive here)."""
+        import numpy as np
+        self._arrays = {"rhs_rel_residual": np.zeros(n), "rhs_est_error": np.zeros(n),
+                        "rhs_ir_steps": np.zeros(n, dtype=np.int32),
+                        "rhs_gmres_iters": np.zeros(n, dtype=np.int32)}
+        for name, a in self._arrays.items():
+            setattr(self, name, a.ctypes.data if n else None)
+        return self
 
     def as_dict(self):
-        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_
+             if name not in self.PER_RHS}
         n = max(1, min(8, self.ir_steps))
         d["ir_residual"] = list(self.ir_residual[:n])
         d["ir_gmres_iters"] = list(self.ir_gmres_iters[:n])
+        for name, a in getattr(self, "_arrays", {}).items():
+            d[name] = a.tolist()
         return d
 
 

@@ -153,8 +153,17 @@ int helm_solve_dev(helm_handle* h, int n_rhs, const double* f_dev, double* u_dev
     Handle& H = h->impl;
     HELM_HIP(hipSetDevice(H.device));
     if (info) {
+      // the caller's per-right-hand-side arrays survive the reset
+      double* rr = info->rhs_rel_residual;
+      double* re = info->rhs_est_error;
+      int* rs = info->rhs_ir_steps;
+      int* rg = info->rhs_gmres_iters;
       std::memset(info, 0, sizeof(*info));
       info->n_rhs = n_rhs;
+      info->rhs_rel_residual = rr;
+      info->rhs_est_error = re;
+      info->rhs_ir_steps = rs;
+      info->rhs_gmres_iters = rg;
     }
     const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
     const long long ls0 = H.layer_solves;
@@ -166,7 +175,7 @@ int helm_solve_dev(helm_handle* h, int n_rhs, const double* f_dev, double* u_dev
       Method& M = method_for(h, k);
       const double2* f = reinterpret_cast<const double2*>(f_dev) + (long long)c0 * N;
       double2* u = reinterpret_cast<double2*>(u_dev) + (long long)c0 * N;
-      int s = M.solve(f, u, info);
+      int s = M.solve(f, u, info, c0);
       if (s != HELM_OK) status = s;
     }
     HELM_HIP(hipStreamSynchronize(H.st));

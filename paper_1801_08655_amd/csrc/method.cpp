@@ -221,6 +221,7 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
   HELM_HIP(hipStreamSynchronize(H.st));
   for (int c = 0; c < k; ++c) bnorm[c] = std::sqrt(std::max(hh[c].x, 0.0));
   std::vector<char> active(k, 1);
+  col_iters.assign(k, 0);
   int total = 0;
   bool first = true;
   int status = HELM_OK;
@@ -283,6 +284,7 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
       bool any_run = false;
       for (int c = 0; c < k; ++c) {
         if (!run[c]) { scl[c] = 0.0; continue; }
+        ++col_iters[c];
         std::vector<cd>& Hc = Hm[c];
         auto Hat = [&](int r_, int c_) -> cd& { return Hc[(size_t)r_ * m + c_]; };
         for (int i = 0; i <= j; ++i) {
@@ -375,6 +377,7 @@ int Method::polarized_solve(const double2* f, double2* u, const std::vector<doub
                             int max_iter, int restart, helm_solve_info* info) {
   const int L = H.G.L;
   double t0 = now_ms();
+  col_iters.assign(k, 0);
   if (L == 1) {
     scatter_sources(f);
     H.solve_layers(*set_all, k);
@@ -464,18 +467,22 @@ void Method::ensure_volumes() {
   }
 }
 
-// Full online solve of k columns (device arrays).
-int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
+// Full online solve of k columns (device arrays).  col0 is the index of the
+// first column in the caller's per-right-hand-side arrays of info.
+int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0) {
   const helm_options& o = H.opt;
   const int restart = gmres_restart(o.gmres_max_iter);
   ensure_volumes();
   double2* r = vr.as<double2>();
-  std::vector<double> rel;
+  std::vector<double> rel, est_c(k, 0.0);
+  std::vector<int> steps_c(k, 0), iters_c(k, 0);
   int status = HELM_OK;
   double t0 = now_ms();
   if (H.prec == HELM_FP64) {
     int it0 = info ? info->gmres_iters : 0;
     status = polarized_solve(f, u, o.gmres_tol, o.gmres_max_iter, restart, info);
+    if (col_iters.size() == (size_t)k) iters_c = col_iters;
+    std::fill(steps_c.begin(), steps_c.end(), 1);
     double tr = now_ms();
     residual(f, u, r, rel);
     if (info) {
@@ -506,6 +513,10 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
         mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
         double est = refinement_error(it, dprev[c], nm.dn[c], nm.un[c]);
         emx = std::max(emx, est);
+        est_c[c] = est;
+        if (col_iters.size() == (size_t)k) iters_c[c] += col_iters[c];
+        const bool met = rel[c] <= o.ir_tol || (o.err_target > 0 && est <= o.err_target);
+        if (steps_c[c] == 0 && met) steps_c[c] = steps;
       }
       dprev = nm.dn;
       if (info && it < 8) {
@@ -519,12 +530,20 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info) {
       }
     }
     if (info) info->ir_steps = std::max(info->ir_steps, steps);
+    for (int c = 0; c < k; ++c)
+      if (steps_c[c] == 0) steps_c[c] = steps;
   }
   if (info) {
     double mx = 0;
     for (double v : rel) mx = std::max(mx, v);
     info->rel_residual_max = std::max(info->rel_residual_max, mx);
     info->t_total_ms += now_ms() - t0;
+    for (int c = 0; c < k && c < (int)rel.size(); ++c) {
+      if (info->rhs_rel_residual) info->rhs_rel_residual[col0 + c] = rel[c];
+      if (info->rhs_est_error) info->rhs_est_error[col0 + c] = est_c[c];
+      if (info->rhs_ir_steps) info->rhs_ir_steps[col0 + c] = steps_c[c];
+      if (info->rhs_gmres_iters) info->rhs_gmres_iters[col0 + c] = iters_c[c];
+    }
   }
   return status;
 }

@@ -18,6 +18,7 @@ struct Method {
   const LayerSet* set_lower = nullptr;
   std::vector<const LayerSet*> single;
   std::vector<double> last_resid;
+  std::vector<int> col_iters;   // GMRES iterations per column (last call)
   // Krylov basis and temporaries, grown on demand and kept between calls
   std::vector<std::unique_ptr<DevMem>> basis;
   DevMem gw, gr;
@@ -57,7 +58,7 @@ struct Method {
   void ensure_volumes();
   void residual(const double2* f, const double2* u, double2* r, std::vector<double>& rel);
   void norms(const double2* x, std::vector<double>& out);
-  int solve(const double2* f, double2* u, helm_solve_info* info);
+  int solve(const double2* f, double2* u, helm_solve_info* info, int col0 = 0);
   int gmres_restart(int max_iter) const;
 };
 

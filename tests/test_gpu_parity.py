@@ -253,3 +253,30 @@ def test_non_cubic_grid_matches_direct(precision, tol):
     err = relative_error(u.reshape(3, -1).T, ref)
     print(precision, "non-cubic err", err)
     assert err.max() <= tol
+
+
+def test_per_rhs_info():
+    """The per-column records: residuals match an independent FP64 residual
+    of the oracle, the mixed path records its estimated errors and steps."""
+    wl = workload("layered-28")
+    pb = _problem(wl)
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12)]
+    F = point_source_rhs(pb.shape, srcs, wl.h)
+    H = pb.operator()
+    for precision in ("fp64", "mixed"):
+        s = _solver(wl, precision, err_target=1e-6)
+        u, info = s.solve_points(srcs, info=True)
+        U = u.cpu().numpy().reshape(len(srcs), -1).T
+        rel = np.linalg.norm(F - H @ U, axis=0) / np.linalg.norm(F, axis=0)
+        print(precision, info["rhs_rel_residual"], rel, info["rhs_ir_steps"],
+              info["rhs_gmres_iters"], info["rhs_est_error"])
+        assert len(info["rhs_rel_residual"]) == 3
+        assert np.allclose(info["rhs_rel_residual"], rel, rtol=1e-3, atol=1e-15)
+        assert max(info["rhs_rel_residual"]) == pytest.approx(info["rel_residual_max"])
+        assert all(1 <= g <= info["gmres_iters"] for g in info["rhs_gmres_iters"])
+        assert all(1 <= st <= info["ir_steps"] for st in info["rhs_ir_steps"])
+        if precision == "mixed":
+            assert max(info["rhs_est_error"]) <= 1e-6
+        else:
+            assert info["rhs_est_error"] == [0.0, 0.0, 0.0]
+        s.close()
