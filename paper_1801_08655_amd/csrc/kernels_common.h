@@ -224,11 +224,15 @@ template <typename T, int BM, int BN = GT> struct WaveAcc {
 // A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
 template <typename T, int BM, int BN>
 __device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN>& sm,
-                                          WaveAcc<T, BM, BN>& acc, int wr, int wc, int lane) {
+                                          WaveAcc<T, BM, BN>& acc, int wr, int wc, int lane,
+                                          int kvalid) {
   using G = WaveGrid<BM, BN>;
   const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
   for (int p = 0; p < GK / 2; ++p) {
+    // a partial last K step: the sub-steps past its valid complex columns
+    // (zero-filled in LDS) are skipped; kvalid is the same for the block
+    if (2 * p >= kvalid) break;
     const int kk = 4 * p + lq;
     T a[G::MB], b1[G::NB], b2[G::NB];
 #pragma unroll
@@ -268,7 +272,7 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN>& sm, WaveAcc<T, BM
     __syncthreads();
     if (k0 + GK < kend)
       stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
-    mfma_step<T, BM, BN>(sm, acc, wr, wc, lane);
+    mfma_step<T, BM, BN>(sm, acc, wr, wc, lane, kend - k0);
     __syncthreads();
   }
 }

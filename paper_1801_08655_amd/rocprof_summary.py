@@ -3,6 +3,7 @@
     python -m paper_1801_08655_amd.rocprof_summary stats <dir> [--match REGEX]
     python -m paper_1801_08655_amd.rocprof_summary traffic <fetch_dir> <write_dir>
         --kernel REGEX --copy REGEX --copy-bytes N --class NAME --out FILE
+    python -m paper_1801_08655_amd.rocprof_summary mfma <dir> --class LABEL=REGEX ...
 
 ``stats`` prints the per-kernel table of a ``--kernel-trace --stats`` run.
 ``traffic`` combines a ``--pmc FETCH_SIZE`` run and a ``--pmc WRITE_SIZE``
@@ -127,6 +128,40 @@ def cmd_traffic(a):
     print(open(a.out).read())
 
 
+def cmd_mfma(a):
+    """Matrix-core counters of the dispatches matching each class regex: the
+    executed MFMA flops (SQ_INSTS_VALU_MFMA_MOPS_F32 x 512, or _F64) and the
+    busy fraction of the matrix cores, SQ_VALU_MFMA_BUSY_CYCLES (summed over
+    the SIMDs) over SIMDs x the active cycles of one XCD (GRBM_GUI_ACTIVE is
+    summed over the XCDs), over the last N dispatches."""
+    acc = {}
+    for path in _find(a.dir, "*counter_collection.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                key = int(r.get("Dispatch_Id", 0) or 0)
+                d = acc.setdefault(key, {"name": r["Kernel_Name"],
+                                         "t": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+                d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    disp = [acc[k] for k in sorted(acc)]
+    print("| class | dispatches | executed MFMA GFLOP / dispatch | MFMA busy | executed TFLOP/s |")
+    print("|---|---|---|---|---|")
+    for spec in a.cls:
+        label, rx = spec.split("=", 1)
+        sel = [d for d in disp if re.search(rx, d["name"])]
+        if a.last:
+            sel = sel[-a.last:]
+        if not sel:
+            continue
+        mops = sum(d.get(f"SQ_INSTS_VALU_MFMA_MOPS_{a.dtype}", 0.0) for d in sel)
+        busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in sel)
+        active = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in sel)
+        t = sum(d["t"] for d in sel)
+        flops = 512.0 * mops
+        util = busy / (active / a.xcds * a.simds) if active else float("nan")
+        print(f"| {label} | {len(sel)} | {flops / len(sel) / 1e9:.2f} | {util:.3f} | "
+              f"{flops / t / 1e3:.1f} |")
+
+
 def read_traffic(path):
     """Parsed ``key: value`` file written by ``traffic`` (None if missing)."""
     if not os.path.exists(path):
@@ -160,8 +195,16 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--note", default="")
     t.add_argument("--last", type=int, default=0)
+    m = sub.add_parser("mfma")
+    m.add_argument("dir")
+    m.add_argument("--class", dest="cls", action="append", required=True,
+                   help="LABEL=REGEX of a kernel class (repeatable)")
+    m.add_argument("--last", type=int, default=0)
+    m.add_argument("--dtype", default="F32")
+    m.add_argument("--simds", type=int, default=1024)
+    m.add_argument("--xcds", type=int, default=8)
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "mfma": cmd_mfma}[a.cmd](a)
 
 
 if __name__ == "__main__":
