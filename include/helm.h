@@ -263,7 +263,8 @@ int helm_apply_operator_dev(helm_handle* h, int k, const double* f_dev,
  *   op 1: P M x = x + P (U x_up, 0)                        (Alg. 7 + P),
  *   op 2: U x_up                                            (Alg. 10),
  *   op 3: the polarized right-hand side (f_down, f_up) of a volume source
- *         (Alg. 2 lines 2-8); `in_dev` is then k volumes (RHS-major).
+ *         (the first steps of Alg. 2); `in_dev` is then k volumes
+ *         (RHS-major).
  * For ops 0-1 `in_dev`/`out_dev` hold [x_down | x_up], each a pair vector. */
 int helm_polarized_op_dev(helm_handle* h, int op, int k, const double* in_dev,
                           double* out_dev);

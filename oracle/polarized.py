@@ -26,7 +26,8 @@ R8  Interface sources (the plane deltas of Section "Formulation" scaled to
       J_bot^l(a, b) = -B b on plane e_l,  +B a on plane e_l + 1.
     Then G^l (f^l + J_top^l(u_{l-1}) + J_bot^l(u_l)) equals the global
     solution on the bulk planes and vanishes on the local PML planes (the
-    exact Green's representation of Algorithm 2, lines 10-12).
+    exact Green's representation that the online stage of Algorithm 2 uses to
+    rebuild the volume).
 R9  Read-outs R_top^l(w) = (w(s_l - 1), w(s_l)), R_bot^l(w) = (w(e_l), w(e_l + 1)).
 R10 Blocks of the polarized matrix (the "algebraic operations and
     permutations" the paper defers to the 2D paper), for pair vectors x:
@@ -214,7 +215,7 @@ class PolarizedTraces:
         return fd, fu
 
     def reconstruct(self, f: np.ndarray, traces: np.ndarray) -> np.ndarray:
-        """Volume from interface traces (Algorithm 2, lines 10-14)."""
+        """Volume from interface traces (the reconstruction step of Algorithm 2)."""
         u = np.zeros_like(f)
         for l, g in enumerate(self.geo):
             src = self.restrict_source(l, f)

@@ -1,7 +1,7 @@
 // Volume, interface-trace and Krylov kernels of the online stage.
 //
-//  * source partition f^l = f chi_l (Algorithm 2, line 3) and the volume
-//    reconstruction (lines 10-14) between the global grid (RHS-major, FP64)
+//  * source partition f^l = f chi_l (Algorithm 2) and the volume
+//    reconstruction (the last step of Algorithm 2) between the global grid (RHS-major, FP64)
 //    and a layer's solve vector (ND order, columns fastest, working precision);
 //  * interface sources: the plane deltas of Section "Formulation" scaled to
 //    this discretisation (coefficient B = 1/(h^2 beta_x beta_y), the matrix

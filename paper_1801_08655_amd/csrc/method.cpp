@@ -166,7 +166,8 @@ void Method::scatter_sources(const double2* f) {
   }
 }
 
-// (f_down, f_up) from the volume source f (Algorithm 2, lines 2-8)
+// (f_down, f_up) from the volume source f (the first steps of Algorithm 2:
+// local solves of the partitioned source and their interface read-outs)
 void Method::polarized_rhs(const double2* f, double2* fd, double2* fu) {
   const int L = H.G.L;
   scatter_sources(f);
@@ -177,7 +178,7 @@ void Method::polarized_rhs(const double2* f, double2* fd, double2* fu) {
   }
 }
 
-// u = volume from traces (Algorithm 2, lines 10-14)
+// u = volume from traces (the reconstruction that ends Algorithm 2)
 void Method::reconstruct(const double2* f, const double2* tr, double2* u) {
   const int L = H.G.L;
   scatter_sources(f);

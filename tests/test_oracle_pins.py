@@ -242,7 +242,8 @@ def homog25():
 def test_green_representation_is_exact(homog25):
     """Reading R8: local solves with the interface measures reproduce the global
     solution in each layer's bulk and vanish on its local PML planes
-    (Algorithm 2 lines 10-12; exactness stated in the SIE reduction section)."""
+    (the reconstruction step of Algorithm 2; exactness stated in the SIE
+    reduction section)."""
     wl, pb, f, u, pt = homog25
     tr = pt.traces_of(u)
     scale = np.abs(u).max()
