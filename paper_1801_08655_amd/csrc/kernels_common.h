@@ -18,6 +18,42 @@ template <typename C> __device__ __forceinline__ C cmake(double re, double im) {
   return z;
 }
 template <typename C> __device__ __forceinline__ C czero() { return cmake<C>(0, 0); }
+
+// Global-memory loads and stores through address-space-1 pointers.  A
+// pointer read from a device structure is generic to the compiler, which
+// then emits FLAT instructions; those also count against the LDS wait
+// counter, so the LDS waits of an MFMA loop would wait for every global
+// prefetch in flight.  Through these helpers the compiler emits
+// global_load / global_store.  Only for pointers into device memory.
+#define HELM_AS1 __attribute__((address_space(1)))
+template <typename C> __device__ __forceinline__ C ld(const C* p) {
+  typedef typename C::value_type E;
+  typedef E V __attribute__((ext_vector_type(2)));
+  const V v = *(const HELM_AS1 V*)p;
+  C r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+__device__ __forceinline__ int ld(const int* p) { return *(const HELM_AS1 int*)p; }
+
+// A complex zero in device memory (room for complex128), the load address
+// of the masked-off lanes of ld_or_zero.
+static __device__ __align__(16) double kZeroC[2] = {0.0, 0.0};
+
+// *p when ok, else zero, as one unconditional load (no branch), so that a
+// run of such loads is issued back to back and waited for once.
+template <typename C> __device__ __forceinline__ C ld_or_zero(bool ok, const C* p) {
+  return ld(ok ? p : reinterpret_cast<const C*>(kZeroC));
+}
+template <typename C> __device__ __forceinline__ void st(C* p, C v) {
+  typedef typename C::value_type E;
+  typedef E V __attribute__((ext_vector_type(2)));
+  V w;
+  w.x = v.x;
+  w.y = v.y;
+  *(HELM_AS1 V*)p = w;
+}
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) {
   C z; z.x = a.x + b.x; z.y = a.y + b.y; return z;
 }
@@ -117,8 +153,8 @@ template <typename T>
 __device__ __forceinline__ C_t<T> view_at(const View<T>& v, int r, int k) {
   C_t<T> val = czero<C_t<T>>();
   if (r < v.nr && k < v.nk) {
-    const long long kk = v.kmap ? (long long)v.kmap[k] : (long long)k;
-    val = v.base[(long long)r * v.sr + kk * v.sk];
+    const long long kk = v.kmap ? (long long)ld(v.kmap + k) : (long long)k;
+    val = ld(v.base + (long long)r * v.sr + kk * v.sk);
   }
   return val;
 }
@@ -150,15 +186,37 @@ template <int BM, int BN> struct WaveGrid {
                 "wave sub-tile must be whole MFMA blocks");
 };
 
-// Per-thread staging registers for one K step of both operands.
+// Per-thread staging registers for one K step of both operands, and the
+// resolved K indices of this thread's Q elements for the step after it.
 template <typename T, int BM, int BN = GT> struct Stage {
   static constexpr int NP = BM * GK / 256, NQ = BN * GK / 256;
   C_t<T> p[NP], q[NQ];
+  int qk[NQ];
 };
 
+// K indices of this thread's Q elements for the step at k0 (through the row
+// map of an indirect view), -1 past the valid range.  They are loaded one K
+// step ahead of the values they address, so that the value loads of a step
+// never wait for an index load.
+template <typename T, int BM, int BN, bool FAST_C>
+__device__ __forceinline__ void stage_index(Stage<T, BM, BN>& g, const View<T>& qv, int k0,
+                                            int kend) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < Stage<T, BM, BN>::NQ; ++it) {
+    const int e = t + it * 256;
+    const int kq = FAST_C ? e / BN : e % GK;
+    const int k = k0 + kq;
+    int kk = -1;
+    if (k < kend && k < qv.nk) kk = qv.kmap ? ld(qv.kmap + k) : k;
+    g.qk[it] = kk;
+  }
+}
+
 // Global loads of the BM x GK block of P (rows r0.., k0..) and the GK x BN
-// block of Q (columns c0.., k0..).  FAST_R / FAST_C: consecutive threads walk
-// the rows of P / the columns of Q (the contiguous dimension in memory).
+// block of Q (columns c0.., K indices from stage_index).  FAST_R / FAST_C:
+// consecutive threads walk the rows of P / the columns of Q (the contiguous
+// dimension in memory).
 template <typename T, int BM, int BN, bool FAST_R, bool FAST_C>
 __device__ __forceinline__ void stage_load(Stage<T, BM, BN>& g, const View<T>& pv,
                                            const View<T>& qv, int r0, int c0, int k0,
@@ -174,9 +232,12 @@ __device__ __forceinline__ void stage_load(Stage<T, BM, BN>& g, const View<T>& p
 #pragma unroll
   for (int it = 0; it < Stage<T, BM, BN>::NQ; ++it) {
     const int e = t + it * 256;
-    int c, kq;
-    if (FAST_C) { c = e % BN; kq = e / BN; } else { kq = e % GK; c = e / GK; }
-    g.q[it] = (k0 + kq < kend) ? view_at(qv, c0 + c, k0 + kq) : czero<C_t<T>>();
+    const int c = FAST_C ? e % BN : e / GK;
+    const int kk = g.qk[it];
+    C_t<T> val = czero<C_t<T>>();
+    if (kk >= 0 && c0 + c < qv.nr)
+      val = ld(qv.base + (long long)(c0 + c) * qv.sr + (long long)kk * qv.sk);
+    g.q[it] = val;
   }
 }
 
@@ -266,12 +327,16 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN>& sm, WaveAcc<T, BM
   acc.zero();
   if (kbeg >= kend) return;
   Stage<T, BM, BN> g;
+  stage_index<T, BM, BN, Q_FAST_C>(g, qv, kbeg, kend);
   stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
+  stage_index<T, BM, BN, Q_FAST_C>(g, qv, kbeg + GK, kend);
   for (int k0 = kbeg; k0 < kend; k0 += GK) {
     stage_store<T, BM, BN, P_FAST_R, Q_FAST_C>(sm, g);
     __syncthreads();
-    if (k0 + GK < kend)
+    if (k0 + GK < kend) {
       stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
+      stage_index<T, BM, BN, Q_FAST_C>(g, qv, k0 + 2 * GK, kend);
+    }
     mfma_step<T, BM, BN>(sm, acc, wr, wc, lane, kend - k0);
     __syncthreads();
   }

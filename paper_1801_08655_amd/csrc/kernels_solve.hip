@@ -44,8 +44,8 @@ template <typename T> struct ChildSum {
 #pragma unroll
     for (int slot = 0; slot < 2; ++slot)
       if (inv[slot]) {
-        const int q = inv[slot][row];
-        if (q >= 0) v = cadd(v, Uc[(cub[slot] + q) * k + col]);
+        const int q = ld(inv[slot] + row);
+        if (q >= 0) v = cadd(v, ld(Uc + (cub[slot] + q) * k + col));
       }
     return v;
   }
@@ -68,10 +68,105 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const ChildSum<T> cs(fronts, f, L);
   const int rows = (f.s - r0) < RT ? (f.s - r0) : RT;
   const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
-  for (int rr = r0 + ty; rr < r0 + rows; rr += 256 / GT)
-    for (int c = tx; c < k; c += GT) {
-      C& x = X[(long long)(f.off + rr) * k + c];
-      x = cadd(x, cs(rr, c, k));
+  // the RT / 4 rows of this thread: child rows first, then every value, then
+  // the stores (one latency per group of loads, not one per element)
+  constexpr int RPT = RT / (256 / GT);
+  int q[2][RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int rr = r0 + ty + j * (256 / GT);
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl)
+      q[sl][j] = (rr < r0 + rows && cs.inv[sl]) ? ld(cs.inv[sl] + rr) : -1;
+  }
+  for (int c = tx; c < k; c += GT) {
+    C v[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int rr = r0 + ty + j * (256 / GT);
+      C u[2];
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl)
+        u[sl] = ld_or_zero(q[sl][j] >= 0, cs.Uc + (cs.cub[sl] + q[sl][j]) * k + c);
+      const C x = ld_or_zero(rr < r0 + rows, X + (long long)(f.off + rr) * k + c);
+      v[j] = cadd(x, cadd(cadd(czero<C>(), u[0]), u[1]));
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int rr = r0 + ty + j * (256 / GT);
+      if (rr < r0 + rows) st(X + (long long)(f.off + rr) * k + c, v[j]);
+    }
+  }
+}
+
+// Output rows and columns (tile offsets) of this lane's accumulators, in the
+// order of WaveAcc: row i = 4 bm + v, column j = bn.
+template <typename T, int BM, int BN> struct LaneOut {
+  using G = WaveGrid<BM, BN>;
+  static constexpr int NR = G::MB * 4, NC = G::NB;
+  int r[NR], c[NC];
+  __device__ __forceinline__ LaneOut() {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wr = wave / G::WC, wc = wave % G::WC;
+#pragma unroll
+    for (int bm = 0; bm < G::MB; ++bm)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) r[bm * 4 + v] = wr * G::RW + bm * 16 + Mfma<T>::row(lane, v);
+#pragma unroll
+    for (int bn = 0; bn < G::NB; ++bn) c[bn] = wc * G::CW + bn * 16 + (lane & 15);
+  }
+};
+
+template <typename T, int BM, int BN>
+__device__ __forceinline__ C_t<T> acc_at(const WaveAcc<T, BM, BN>& acc, int i, int j) {
+  C_t<T> z;
+  z.x = acc.re[i / 4][j][i % 4];
+  z.y = acc.im[i / 4][j][i % 4];
+  return z;
+}
+
+// Forward GEMM epilogue of an unsplit front: pivot rows to Z, boundary rows
+// to the update buffer with the children's updates added.  The child rows of
+// all of this lane's outputs are loaded first, then the child values, then
+// the results are stored, so that the latencies of each group of loads
+// overlap instead of following one another output by output.
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void fwd_epilogue(const WaveAcc<T, BM, BN>& acc, const FrontDev& f,
+                                             const ChildSum<T>& cs, C_t<T>* Z, C_t<T>* Uo,
+                                             int m0, int n0, int k) {
+  using C = C_t<T>;
+  using O = LaneOut<T, BM, BN>;
+  const O o;
+  const int n = f.s + f.b;
+  int q[2][O::NR];
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i) {
+    const int gm = m0 + o.r[i];
+    const bool bnd = gm >= f.s && gm < n;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) q[sl][i] = (bnd && cs.inv[sl]) ? ld(cs.inv[sl] + gm) : -1;
+  }
+  C add[O::NR][O::NC];
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+    for (int j = 0; j < O::NC; ++j) {
+      const int gc = n0 + o.c[j];
+      C u[2];
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl)
+        u[sl] = ld_or_zero(q[sl][i] >= 0 && gc < k, cs.Uc + (cs.cub[sl] + q[sl][i]) * k + gc);
+      add[i][j] = cadd(cadd(czero<C>(), u[0]), u[1]);
+    }
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+    for (int j = 0; j < O::NC; ++j) {
+      const int gm = m0 + o.r[i], gc = n0 + o.c[j];
+      if (gm >= n || gc >= k) continue;
+      const C z = acc_at(acc, i, j);
+      if (gm < f.s) st(Z + (long long)(f.off + gm) * k + gc, z);
+      else st(Uo + (f.ub + gm - f.s) * k + gc, cadd(z, add[i][j]));
     }
 }
 
@@ -105,22 +200,20 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> qv{X + (long long)f.off * k, 1, (long long)k, k, f.s};
   WaveAcc<T, BM, BN> acc;
   gemm_tile<T, BM, true, true>(sm, acc, pv, qv, m0, n0, kb, ke);
-  C* Z = reinterpret_cast<C*>(L.Wt);
-  C* Uo = ub_ptr<T>(L, f.ub_parity);
-  C* S = reinterpret_cast<C*>(scratch);
-  const ChildSum<T> cs(fronts, f, L);
-  for_each_acc<T, BM>(acc, [&](int r, int c, C z) {
-    const int gm = m0 + r, gc = n0 + c;
-    if (gm >= n || gc >= k) return;
-    if (tk.nch_f > 1) {
-      S[(tk.scr_f + (long long)chunk * n + gm) * k + gc] = z;
-    } else if (gm < f.s) {
-      Z[(long long)(f.off + gm) * k + gc] = z;
-    } else {
-      Uo[(f.ub + gm - f.s) * k + gc] = cadd(z, cs(gm, gc, k));
-    }
-  });
+  if (tk.nch_f > 1) {
+    C* S = reinterpret_cast<C*>(scratch);
+    for_each_acc<T, BM>(acc, [&](int r, int c, C z) {
+      const int gm = m0 + r, gc = n0 + c;
+      if (gm < n && gc < k) st(S + (tk.scr_f + (long long)chunk * n + gm) * k + gc, z);
+    });
+    return;
+  }
+  fwd_epilogue<T, BM, BN>(acc, f, ChildSum<T>(fronts, f, L), reinterpret_cast<C*>(L.Wt),
+                          ub_ptr<T>(L, f.ub_parity), m0, n0, k);
 }
+
+// elements per thread and pass of the split-K reductions
+constexpr int RED_EPT = 4;
 
 // forward, step 3 (split fronts only): sum the chunk partials in order
 template <typename T>
@@ -141,13 +234,27 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   const ChildSum<T> cs(fronts, f, L);
-  for (int e = threadIdx.x; e < rows * k; e += 256) {
-    const int gm = r0 + e / k, gc = e % k;
-    C z = czero<C>();
-    for (int ch = 0; ch < tk.nch_f; ++ch)
-      z = cadd(z, S[(tk.scr_f + (long long)ch * n + gm) * k + gc]);
-    if (gm < f.s) Z[(long long)(f.off + gm) * k + gc] = z;
-    else Uo[(f.ub + gm - f.s) * k + gc] = cadd(z, cs(gm, gc, k));
+  // RED_EPT elements per thread at a time: all their loads, then the stores
+  for (int e0 = 0; e0 < rows * k; e0 += 256 * RED_EPT) {
+    C z[RED_EPT];
+#pragma unroll
+    for (int j = 0; j < RED_EPT; ++j) {
+      const int e = e0 + threadIdx.x + j * 256;
+      z[j] = czero<C>();
+      if (e >= rows * k) continue;
+      const int gm = r0 + e / k, gc = e % k;
+      for (int ch = 0; ch < tk.nch_f; ++ch)
+        z[j] = cadd(z[j], ld(S + (tk.scr_f + (long long)ch * n + gm) * k + gc));
+      if (gm >= f.s) z[j] = cadd(z[j], cs(gm, gc, k));
+    }
+#pragma unroll
+    for (int j = 0; j < RED_EPT; ++j) {
+      const int e = e0 + threadIdx.x + j * 256;
+      if (e >= rows * k) continue;
+      const int gm = r0 + e / k, gc = e % k;
+      if (gm < f.s) st(Z + (long long)(f.off + gm) * k + gc, z[j]);
+      else st(Uo + (f.ub + gm - f.s) * k + gc, z[j]);
+    }
   }
 }
 
@@ -182,15 +289,35 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> qv{X, 1, (long long)k, k, f.b, L.bidx + f.bidx};
   WaveAcc<T, BM, BN> acc;
   gemm_tile<T, BM, false, true>(sm, acc, pv, qv, m0, n0, kb, ke);
-  C* S = reinterpret_cast<C*>(scratch);
+  if (tk.nch_b > 1) {
+    C* S = reinterpret_cast<C*>(scratch);
+    for_each_acc<T, BM>(acc, [&](int r, int c, C z) {
+      const int gm = m0 + r, gc = n0 + c;
+      if (gm < f.s && gc < k) st(S + (tk.scr_b + (long long)chunk * f.s + gm) * k + gc, z);
+    });
+    return;
+  }
+  // X(S) = Z(S) + product: every Z value of the lane is loaded before the
+  // first store (X and Z are distinct buffers, but the compiler cannot tell)
+  using O = LaneOut<T, BM, BN>;
+  const O o;
   const C* Z = reinterpret_cast<const C*>(L.Wt);
-  for_each_acc<T, BM>(acc, [&](int r, int c, C z) {
-    const int gm = m0 + r, gc = n0 + c;
-    if (gm >= f.s || gc >= k) return;
-    const long long idx = (long long)(f.off + gm) * k + gc;
-    if (tk.nch_b > 1) S[(tk.scr_b + (long long)chunk * f.s + gm) * k + gc] = z;
-    else X[idx] = cadd(Z[idx], z);
-  });
+  C zv[O::NR][O::NC];
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+    for (int j = 0; j < O::NC; ++j) {
+      const int gm = m0 + o.r[i], gc = n0 + o.c[j];
+      zv[i][j] = ld_or_zero(gm < f.s && gc < k, Z + (long long)(f.off + gm) * k + gc);
+    }
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+    for (int j = 0; j < O::NC; ++j) {
+      const int gm = m0 + o.r[i], gc = n0 + o.c[j];
+      if (gm < f.s && gc < k)
+        st(X + (long long)(f.off + gm) * k + gc, cadd(zv[i][j], acc_at(acc, i, j)));
+    }
 }
 
 template <typename T>
@@ -209,13 +336,25 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* S = reinterpret_cast<const C*>(scratch);
   C* X = reinterpret_cast<C*>(L.X);
   const C* Z = reinterpret_cast<const C*>(L.Wt);
-  for (int e = threadIdx.x; e < rows * k; e += 256) {
-    const int gm = r0 + e / k, gc = e % k;
-    const long long idx = (long long)(f.off + gm) * k + gc;
-    C z = Z[idx];
-    for (int ch = 0; ch < tk.nch_b; ++ch)
-      z = cadd(z, S[(tk.scr_b + (long long)ch * f.s + gm) * k + gc]);
-    X[idx] = z;
+  for (int e0 = 0; e0 < rows * k; e0 += 256 * RED_EPT) {
+    C z[RED_EPT];
+#pragma unroll
+    for (int j = 0; j < RED_EPT; ++j) {
+      const int e = e0 + threadIdx.x + j * 256;
+      z[j] = czero<C>();
+      if (e >= rows * k) continue;
+      const int gm = r0 + e / k, gc = e % k;
+      z[j] = ld(Z + (long long)(f.off + gm) * k + gc);
+      for (int ch = 0; ch < tk.nch_b; ++ch)
+        z[j] = cadd(z[j], ld(S + (tk.scr_b + (long long)ch * f.s + gm) * k + gc));
+    }
+#pragma unroll
+    for (int j = 0; j < RED_EPT; ++j) {
+      const int e = e0 + threadIdx.x + j * 256;
+      if (e >= rows * k) continue;
+      const int gm = r0 + e / k, gc = e % k;
+      st(X + (long long)(f.off + gm) * k + gc, z[j]);
+    }
   }
 }
 
@@ -264,10 +403,10 @@ k_fwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   if (m < n) {
 #pragma unroll 4
     for (int q = q0; q < ke; q += 4) {
-      const C fa = FT[m + (long long)q * n];
+      const C fa = ld(FT + m + (long long)q * n);
       const C* xq = X + (long long)q * KC;
 #pragma unroll
-      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, xq[c]);
+      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, ld(xq + c));
     }
   }
   if (w > 0) {
@@ -280,12 +419,26 @@ k_fwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   C* S = reinterpret_cast<C*>(scratch);
   const ChildSum<T> cs(fronts, f, L);
+  C add[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) add[c] = czero<C>();
+  if (tk.nch_f == 1 && m >= f.s) {
+    // the row's children's updates, loaded before any store
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int q = cs.inv[sl] ? ld(cs.inv[sl] + m) : -1;
+      if (q >= 0) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) add[c] = cadd(add[c], ld(cs.Uc + (cs.cub[sl] + q) * KC + c));
+      }
+    }
+  }
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     const C z = cadd(cadd(acc[c], red[0][lane][c]), cadd(red[1][lane][c], red[2][lane][c]));
-    if (tk.nch_f > 1) S[(tk.scr_f + (long long)chunk * n + m) * KC + c] = z;
-    else if (m < f.s) Z[(long long)(f.off + m) * KC + c] = z;
-    else Uo[(f.ub + m - f.s) * KC + c] = cadd(z, cs(m, c, KC));
+    if (tk.nch_f > 1) st(S + (tk.scr_f + (long long)chunk * n + m) * KC + c, z);
+    else if (m < f.s) st(Z + (long long)(f.off + m) * KC + c, z);
+    else st(Uo + (f.ub + m - f.s) * KC + c, cadd(z, add[c]));
   }
 }
 
@@ -328,10 +481,10 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     const C* col = FT + f.s + (long long)m * n;
 #pragma unroll 4
     for (int q = kb + gl; q < ke; q += 16) {
-      const C fa = col[q];
-      const C* xb = X + (long long)B[q] * KC;
+      const C fa = ld(col + q);
+      const C* xb = X + (long long)ld(B + q) * KC;
 #pragma unroll
-      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, xb[c]);
+      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, ld(xb + c));
     }
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
@@ -347,8 +500,8 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       for (int c = 1; c < KC; ++c)
         if (gl == c) z = acc[c];
       const long long idx = (long long)(f.off + m) * KC + gl;
-      if (tk.nch_b > 1) S[(tk.scr_b + (long long)chunk * f.s + m) * KC + gl] = z;
-      else X[idx] = cadd(Z[idx], z);
+      if (tk.nch_b > 1) st(S + (tk.scr_b + (long long)chunk * f.s + m) * KC + gl, z);
+      else st(X + idx, cadd(ld(Z + idx), z));
     }
   }
 }
