@@ -281,35 +281,50 @@ template <typename T, int BM, int BN = GT> struct WaveAcc {
   }
 };
 
-// One K step (GK complex = 2 GK real) of MFMAs for this wave; lane l supplies
-// A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
+// One sub-step (4 real K = 2 complex) of MFMAs for this wave: lane l
+// supplies A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void mfma_sub(const GemmSmem<T, BM, BN>& sm,
+                                         WaveAcc<T, BM, BN>& acc, int wr, int wc, int li,
+                                         int kk) {
+  using G = WaveGrid<BM, BN>;
+  T a[G::MB], b1[G::NB], b2[G::NB];
+#pragma unroll
+  for (int bm = 0; bm < G::MB; ++bm) a[bm] = sm.P[wr * G::RW + bm * 16 + li][kk];
+#pragma unroll
+  for (int bn = 0; bn < G::NB; ++bn) {
+    b1[bn] = sm.Q1[kk][wc * G::CW + bn * 16 + li];
+    b2[bn] = sm.Q2[kk][wc * G::CW + bn * 16 + li];
+  }
+#pragma unroll
+  for (int bm = 0; bm < G::MB; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < G::NB; ++bn) {
+      acc.re[bm][bn] = Mfma<T>::op(a[bm], b1[bn], acc.re[bm][bn]);
+      acc.im[bm][bn] = Mfma<T>::op(a[bm], b2[bn], acc.im[bm][bn]);
+    }
+}
+
+// One K step (GK complex = 2 GK real) of MFMAs for this wave.  A full
+// complex64 step is straight-line code, so the compiler can issue the LDS
+// reads of later sub-steps under the MFMAs of earlier ones (for complex128
+// the extra registers cost more than that gains); otherwise the sub-steps
+// past the valid complex columns of a partial last step (zero-filled in LDS)
+// are skipped (kvalid is the same for the whole block).
 template <typename T, int BM, int BN>
 __device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN>& sm,
                                           WaveAcc<T, BM, BN>& acc, int wr, int wc, int lane,
                                           int kvalid) {
-  using G = WaveGrid<BM, BN>;
   const int li = lane & 15, lq = lane >> 4;
+  if (sizeof(T) == 4 && kvalid >= GK) {
 #pragma unroll
-  for (int p = 0; p < GK / 2; ++p) {
-    // a partial last K step: the sub-steps past its valid complex columns
-    // (zero-filled in LDS) are skipped; kvalid is the same for the block
-    if (2 * p >= kvalid) break;
-    const int kk = 4 * p + lq;
-    T a[G::MB], b1[G::NB], b2[G::NB];
+    for (int p = 0; p < GK / 2; ++p) mfma_sub<T, BM, BN>(sm, acc, wr, wc, li, 4 * p + lq);
+  } else {
 #pragma unroll
-    for (int bm = 0; bm < G::MB; ++bm) a[bm] = sm.P[wr * G::RW + bm * 16 + li][kk];
-#pragma unroll
-    for (int bn = 0; bn < G::NB; ++bn) {
-      b1[bn] = sm.Q1[kk][wc * G::CW + bn * 16 + li];
-      b2[bn] = sm.Q2[kk][wc * G::CW + bn * 16 + li];
+    for (int p = 0; p < GK / 2; ++p) {
+      if (2 * p >= kvalid) break;
+      mfma_sub<T, BM, BN>(sm, acc, wr, wc, li, 4 * p + lq);
     }
-#pragma unroll
-    for (int bm = 0; bm < G::MB; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < G::NB; ++bn) {
-        acc.re[bm][bn] = Mfma<T>::op(a[bm], b1[bn], acc.re[bm][bn]);
-        acc.im[bm][bn] = Mfma<T>::op(a[bm], b2[bn], acc.im[bm][bn]);
-      }
   }
 }
 

@@ -99,6 +99,15 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   }
 }
 
+// Occupancy floor (waves per SIMD) asked of the compiler for the
+// substitution GEMM tiles: 4 for the complex64 tiles, which then fit in 128
+// registers without spilling (at its default the compiler spends up to
+// ~160 on hoisting LDS reads and drops to 3 waves, which measured slower);
+// no floor for the 64 x 64 and the complex128 tiles, which would spill.
+template <typename T, int BM, int BN> constexpr int gemm_waves() {
+  return (sizeof(T) == 4 && !(BM == 64 && BN == 64)) ? 4 : 1;
+}
+
 // Output rows and columns (tile offsets) of this lane's accumulators, in the
 // order of WaveAcc: row i = 4 bm + v, column j = bn.
 template <typename T, int BM, int BN> struct LaneOut {
@@ -150,14 +159,20 @@ __device__ __forceinline__ void fwd_epilogue(const WaveAcc<T, BM, BN>& acc, cons
 #pragma unroll
   for (int i = 0; i < O::NR; ++i)
 #pragma unroll
-    for (int j = 0; j < O::NC; ++j) {
-      const int gc = n0 + o.c[j];
-      C u[2];
+    for (int j = 0; j < O::NC; ++j) add[i][j] = czero<C>();
+  if (cs.inv[0] || cs.inv[1]) {   // uniform: leaves have no children
 #pragma unroll
-      for (int sl = 0; sl < 2; ++sl)
-        u[sl] = ld_or_zero(q[sl][i] >= 0 && gc < k, cs.Uc + (cs.cub[sl] + q[sl][i]) * k + gc);
-      add[i][j] = cadd(cadd(czero<C>(), u[0]), u[1]);
-    }
+    for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+      for (int j = 0; j < O::NC; ++j) {
+        const int gc = n0 + o.c[j];
+        C u[2];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl)
+          u[sl] = ld_or_zero(q[sl][i] >= 0 && gc < k, cs.Uc + (cs.cub[sl] + q[sl][i]) * k + gc);
+        add[i][j] = cadd(cadd(add[i][j], u[0]), u[1]);
+      }
+  }
 #pragma unroll
   for (int i = 0; i < O::NR; ++i)
 #pragma unroll
@@ -173,7 +188,7 @@ __device__ __forceinline__ void fwd_epilogue(const WaveAcc<T, BM, BN>& acc, cons
 // forward, step 2: [X(S); Ub] = [F11^-1 w_S; Ub - F21 F11^-1 w_S], the K
 // (pivot) dimension optionally split into chunks (partials to scratch).
 template <typename T, int BN>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<T, FWD_BM, BN>(), 8)))
 k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
@@ -262,7 +277,7 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // through the front's boundary index list, the K (boundary) dimension
 // optionally split.  Fronts without boundary (roots) just copy Z(S).
 template <typename T, int BM, int BN>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<T, BM, BN>(), 8)))
 k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
