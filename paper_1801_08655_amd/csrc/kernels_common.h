@@ -168,11 +168,26 @@ __device__ __forceinline__ C_t<T> view_at(const View<T>& v, int r, int k) {
 // BN (columns of the tile: right-hand sides in the substitutions) is 64, 32
 // or 16; narrow tiles keep the matrix cores busy on useful columns when a
 // batch has fewer than 64 columns.
-constexpr int PSTR = 2 * GK + 4;   // row stride of P (padding against bank conflicts)
-template <typename T, int BM, int BN = GT> struct GemmSmem {
-  T P[BM][PSTR];
-  T Q1[2 * GK][BN + 4];
-  T Q2[2 * GK][BN + 4];
+//
+// LDS layout and bank conflicts.  An MFMA operand read has lane l at
+// (row base + l % 16, k 4p + l / 16) of P and at (k 4p + l / 16, column
+// base + l % 16) of Q.  P is stored in one of two layouts, chosen by the
+// order in which the global loads deliver it:
+//  - k-major, P[2k + {0,1}][r], when consecutive threads hold consecutive
+//    rows (the stored factor columns of the forward GEMM): the staging
+//    stores then hit consecutive banks;
+//  - row-major, P[r][2k + {0,1}], when consecutive threads hold consecutive
+//    k (the transposed block of the backward GEMM).
+// A k-major row of W elements is padded to 48 (W <= 32) or 80 (W = 64)
+// elements: the four k rows of one read then start 16, 32 and 48 banks
+// apart (mod 64), so the 64 lanes touch 64 distinct banks.  The row-major
+// stride 2 GK + 2 puts the 16 rows of a read on even banks, offset by k.
+constexpr int PSTR = 2 * GK + 2;
+template <int W> constexpr int kmajor_stride() { return W == 64 ? 80 : 48; }
+template <typename T, int BM, int BN = GT, bool PKM = false> struct GemmSmem {
+  T P[PKM ? 2 * GK : BM][PKM ? kmajor_stride<BM>() : PSTR];
+  T Q1[2 * GK][kmajor_stride<BN>()];
+  T Q2[2 * GK][kmajor_stride<BN>()];
 };
 
 // The 4 waves of a block tile it as WR x WC sub-tiles of RW x CW, each made
@@ -242,7 +257,7 @@ __device__ __forceinline__ void stage_load(Stage<T, BM, BN>& g, const View<T>& p
 }
 
 template <typename T, int BM, int BN, bool FAST_R, bool FAST_C>
-__device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN>& sm,
+__device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN, FAST_R>& sm,
                                             const Stage<T, BM, BN>& g) {
   const int t = threadIdx.x;
 #pragma unroll
@@ -250,8 +265,13 @@ __device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN>& sm,
     const int e = t + it * 256;
     int r, k;
     if (FAST_R) { r = e % BM; k = e / BM; } else { k = e % GK; r = e / GK; }
-    sm.P[r][2 * k] = g.p[it].x;
-    sm.P[r][2 * k + 1] = g.p[it].y;
+    if (FAST_R) {
+      sm.P[2 * k][r] = g.p[it].x;
+      sm.P[2 * k + 1][r] = g.p[it].y;
+    } else {
+      sm.P[r][2 * k] = g.p[it].x;
+      sm.P[r][2 * k + 1] = g.p[it].y;
+    }
   }
 #pragma unroll
   for (int it = 0; it < Stage<T, BM, BN>::NQ; ++it) {
@@ -283,14 +303,17 @@ template <typename T, int BM, int BN = GT> struct WaveAcc {
 
 // One sub-step (4 real K = 2 complex) of MFMAs for this wave: lane l
 // supplies A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
-template <typename T, int BM, int BN>
-__device__ __forceinline__ void mfma_sub(const GemmSmem<T, BM, BN>& sm,
+template <typename T, int BM, int BN, bool PKM>
+__device__ __forceinline__ void mfma_sub(const GemmSmem<T, BM, BN, PKM>& sm,
                                          WaveAcc<T, BM, BN>& acc, int wr, int wc, int li,
                                          int kk) {
   using G = WaveGrid<BM, BN>;
   T a[G::MB], b1[G::NB], b2[G::NB];
 #pragma unroll
-  for (int bm = 0; bm < G::MB; ++bm) a[bm] = sm.P[wr * G::RW + bm * 16 + li][kk];
+  for (int bm = 0; bm < G::MB; ++bm) {
+    const int r = wr * G::RW + bm * 16 + li;
+    a[bm] = PKM ? sm.P[kk][r] : sm.P[r][kk];
+  }
 #pragma unroll
   for (int bn = 0; bn < G::NB; ++bn) {
     b1[bn] = sm.Q1[kk][wc * G::CW + bn * 16 + li];
@@ -311,19 +334,19 @@ __device__ __forceinline__ void mfma_sub(const GemmSmem<T, BM, BN>& sm,
 // the extra registers cost more than that gains); otherwise the sub-steps
 // past the valid complex columns of a partial last step (zero-filled in LDS)
 // are skipped (kvalid is the same for the whole block).
-template <typename T, int BM, int BN>
-__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN>& sm,
+template <typename T, int BM, int BN, bool PKM>
+__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN, PKM>& sm,
                                           WaveAcc<T, BM, BN>& acc, int wr, int wc, int lane,
                                           int kvalid) {
   const int li = lane & 15, lq = lane >> 4;
   if (sizeof(T) == 4 && kvalid >= GK) {
 #pragma unroll
-    for (int p = 0; p < GK / 2; ++p) mfma_sub<T, BM, BN>(sm, acc, wr, wc, li, 4 * p + lq);
+    for (int p = 0; p < GK / 2; ++p) mfma_sub<T, BM, BN, PKM>(sm, acc, wr, wc, li, 4 * p + lq);
   } else {
 #pragma unroll
     for (int p = 0; p < GK / 2; ++p) {
       if (2 * p >= kvalid) break;
-      mfma_sub<T, BM, BN>(sm, acc, wr, wc, li, 4 * p + lq);
+      mfma_sub<T, BM, BN, PKM>(sm, acc, wr, wc, li, 4 * p + lq);
     }
   }
 }
@@ -333,7 +356,8 @@ __device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN>& sm,
 // of the next K step are issued before the matrix-core work of the current
 // one, so their latency overlaps the MFMAs.
 template <typename T, int BM, bool P_FAST_R, bool Q_FAST_C, int BN>
-__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN>& sm, WaveAcc<T, BM, BN>& acc,
+__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN, P_FAST_R>& sm,
+                                          WaveAcc<T, BM, BN>& acc,
                                           const View<T>& pv, const View<T>& qv,
                                           int r0, int c0, int kbeg, int kend) {
   using G = WaveGrid<BM, BN>;
@@ -352,7 +376,7 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN>& sm, WaveAcc<T, BM
       stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
       stage_index<T, BM, BN, Q_FAST_C>(g, qv, k0 + 2 * GK, kend);
     }
-    mfma_step<T, BM, BN>(sm, acc, wr, wc, lane, kend - k0);
+    mfma_step<T, BM, BN, P_FAST_R>(sm, acc, wr, wc, lane, kend - k0);
     __syncthreads();
   }
 }

@@ -391,7 +391,7 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              int n_active, const int2* __restrict__ tmap, int k, int nb,
              void* ws0, void* ws1) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T, 64> sm;
+  __shared__ GemmSmem<T, 64, 64, false> sm;
   const int2 tm = tmap[blockIdx.x];
   const int a = tm.x;
   const FrontDev f = fronts[ids[a]];

@@ -194,7 +194,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
   constexpr int BM = FWD_BM;
-  __shared__ GemmSmem<T, BM, BN> sm;
+  __shared__ GemmSmem<T, BM, BN, true> sm;
   const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int2 tm = tmap[mt];
@@ -282,7 +282,7 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T, BM, BN> sm;
+  __shared__ GemmSmem<T, BM, BN, false> sm;
   const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int2 tm = tmap[mt];
