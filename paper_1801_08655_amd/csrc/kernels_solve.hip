@@ -462,15 +462,18 @@ template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int mask) {
 }
 
 // backward: one BM-row tile (BM = 32 or 64) and one K chunk per block; each
-// 16-lane quarter of a wave takes one row at a time (BM/16 rows per
-// quarter), its lanes walk the boundary index q (contiguous in the stored
-// block) and a butterfly over the quarter sums the row.
+// 16-lane quarter of a wave takes the rows m0 + g, m0 + g + 16, ... (BM/16
+// of them) together: its lanes walk the boundary index q (contiguous in the
+// stored block), load X(B[q]) once for all those rows and the factor entry
+// of every row, so that several independent factor loads are in flight per
+// lane; a butterfly over the quarter sums each row.
 template <typename T, int KC>
 __global__ void __launch_bounds__(256)
 k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch, int bm) {
   using C = C_t<T>;
+  constexpr int RPG = 4;   // rows per quarter for BM = 64
   const int mt = blockIdx.x;
   const int2 tm = tmap[mt];
   const int a = tm.x;
@@ -489,31 +492,48 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* Z = reinterpret_cast<const C*>(L.Wt);
   C* S = reinterpret_cast<C*>(scratch);
   const int* B = L.bidx + f.bidx;
-  for (int m = m0 + g; m < m0 + bm && m < f.s; m += 16) {
-    C acc[KC];
+  bool row_ok[RPG];
+  const C* col[RPG];
 #pragma unroll
-    for (int c = 0; c < KC; ++c) acc[c] = czero<C>();
-    const C* col = FT + f.s + (long long)m * n;
-#pragma unroll 4
-    for (int q = kb + gl; q < ke; q += 16) {
-      const C fa = ld(col + q);
-      const C* xb = X + (long long)ld(B + q) * KC;
+  for (int r = 0; r < RPG; ++r) {
+    const int m = m0 + g + 16 * r;
+    row_ok[r] = 16 * r < bm && m < f.s;
+    col[r] = FT + f.s + (long long)(row_ok[r] ? m : 0) * n;
+  }
+  C acc[RPG][KC];
 #pragma unroll
-      for (int c = 0; c < KC; ++c) cfma(acc[c], fa, ld(xb + c));
-    }
+  for (int r = 0; r < RPG; ++r)
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[r][c] = czero<C>();
+#pragma unroll 2
+  for (int q = kb + gl; q < ke; q += 16) {
+    const C* xb = X + (long long)ld(B + q) * KC;
+    C fa[RPG], xv[KC];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) fa[r] = ld_or_zero(row_ok[r], col[r] + q);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) xv[c] = ld(xb + c);
+#pragma unroll
+    for (int r = 0; r < RPG; ++r)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) cfma(acc[r][c], fa[r], xv[c]);
+  }
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
       for (int off = 8; off > 0; off >>= 1) {
-        acc[c].x += shfl_xor_t(acc[c].x, off);
-        acc[c].y += shfl_xor_t(acc[c].y, off);
+        acc[r][c].x += shfl_xor_t(acc[r][c].x, off);
+        acc[r][c].y += shfl_xor_t(acc[r][c].y, off);
       }
     }
-    if (gl < KC) {
-      C z = acc[0];
+    if (row_ok[r] && gl < KC) {
+      const int m = m0 + g + 16 * r;
+      C z = acc[r][0];
 #pragma unroll
       for (int c = 1; c < KC; ++c)
-        if (gl == c) z = acc[c];
+        if (gl == c) z = acc[r][c];
       const long long idx = (long long)(f.off + m) * KC + gl;
       if (tk.nch_b > 1) st(S + (tk.scr_b + (long long)chunk * f.s + m) * KC + gl, z);
       else st(X + idx, cadd(ld(Z + idx), z));
