@@ -467,13 +467,13 @@ template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int mask) {
 // stored block), load X(B[q]) once for all those rows and the factor entry
 // of every row, so that several independent factor loads are in flight per
 // lane; a butterfly over the quarter sums each row.
-template <typename T, int KC>
+template <typename T, int KC, int RPG>
 __global__ void __launch_bounds__(256)
 k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
-           const LayerDev* __restrict__ layers, int k, void* scratch, int bm) {
+           const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  constexpr int RPG = 4;   // rows per quarter for BM = 64
+  constexpr int bm = 16 * RPG;   // row tile: RPG rows per quarter
   const int mt = blockIdx.x;
   const int2 tm = tmap[mt];
   const int a = tm.x;
@@ -497,7 +497,7 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 #pragma unroll
   for (int r = 0; r < RPG; ++r) {
     const int m = m0 + g + 16 * r;
-    row_ok[r] = 16 * r < bm && m < f.s;
+    row_ok[r] = m < f.s;
     col[r] = FT + f.s + (long long)(row_ok[r] ? m : 0) * n;
   }
   C acc[RPG][KC];
@@ -565,8 +565,12 @@ void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
                      void* scratch, int bm, hipStream_t st) {
   if (total_tiles <= 0) return;
 #define HELM_BWDV(KC_)                                                                     \
-  hipLaunchKernelGGL((k_bwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,   \
-                     tasks, n, tmap, layers, k, scratch, bm)
+  if (bm == 32)                                                                            \
+    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 2>), dim3(total_tiles), dim3(256), 0, st, fr,   \
+                       ids, tasks, n, tmap, layers, k, scratch);                           \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 4>), dim3(total_tiles), dim3(256), 0, st, fr,   \
+                       ids, tasks, n, tmap, layers, k, scratch)
   switch (k) {
     case 1: HELM_BWDV(1); break;
     case 2: HELM_BWDV(2); break;
