@@ -53,8 +53,8 @@ template <typename T> struct ChildSum {
 
 // forward, step 1 (fronts with children): X(S) += children's updates on the
 // pivot rows, in place.  The boundary rows are summed in the GEMM epilogue.
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
 k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, int k) {
@@ -67,35 +67,36 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   C* X = reinterpret_cast<C*>(L.X);
   const ChildSum<T> cs(fronts, f, L);
   const int rows = (f.s - r0) < RT ? (f.s - r0) : RT;
-  const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
-  // the RT / 4 rows of this thread: child rows first, then every value, then
-  // the stores (one latency per group of loads, not one per element)
-  constexpr int RPT = RT / (256 / GT);
-  int q[2][RPT];
+  const int total = rows * k;
+  // EPT elements (row, column) per thread and pass: child rows first, then
+  // every value, then the stores (one latency per group of loads, not one
+  // per element)
+  constexpr int EPT = 4;
+  for (int e0 = 0; e0 < total; e0 += NT * EPT) {
+    int q[2][EPT], rr[EPT], cc[EPT];
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    const int rr = r0 + ty + j * (256 / GT);
+    for (int j = 0; j < EPT; ++j) {
+      const int e = e0 + (int)threadIdx.x + j * NT;
+      const bool ok = e < total;
+      rr[j] = ok ? r0 + e / k : -1;
+      cc[j] = ok ? e % k : 0;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl)
-      q[sl][j] = (rr < r0 + rows && cs.inv[sl]) ? ld(cs.inv[sl] + rr) : -1;
-  }
-  for (int c = tx; c < k; c += GT) {
-    C v[RPT];
+      for (int sl = 0; sl < 2; ++sl)
+        q[sl][j] = (ok && cs.inv[sl]) ? ld(cs.inv[sl] + rr[j]) : -1;
+    }
+    C v[EPT];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int rr = r0 + ty + j * (256 / GT);
+    for (int j = 0; j < EPT; ++j) {
       C u[2];
 #pragma unroll
       for (int sl = 0; sl < 2; ++sl)
-        u[sl] = ld_or_zero(q[sl][j] >= 0, cs.Uc + (cs.cub[sl] + q[sl][j]) * k + c);
-      const C x = ld_or_zero(rr < r0 + rows, X + (long long)(f.off + rr) * k + c);
+        u[sl] = ld_or_zero(q[sl][j] >= 0, cs.Uc + (cs.cub[sl] + q[sl][j]) * k + cc[j]);
+      const C x = ld_or_zero(rr[j] >= 0, X + (long long)(f.off + rr[j]) * k + cc[j]);
       v[j] = cadd(x, cadd(cadd(czero<C>(), u[0]), u[1]));
     }
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int rr = r0 + ty + j * (256 / GT);
-      if (rr < r0 + rows) st(X + (long long)(f.off + rr) * k + c, v[j]);
-    }
+    for (int j = 0; j < EPT; ++j)
+      if (rr[j] >= 0) st(X + (long long)(f.off + rr[j]) * k + cc[j], v[j]);
   }
 }
 
@@ -231,8 +232,8 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 constexpr int RED_EPT = 4;
 
 // forward, step 3 (split fronts only): sum the chunk partials in order
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
 k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, int k, const void* scratch) {
@@ -250,11 +251,11 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   const ChildSum<T> cs(fronts, f, L);
   // RED_EPT elements per thread at a time: all their loads, then the stores
-  for (int e0 = 0; e0 < rows * k; e0 += 256 * RED_EPT) {
+  for (int e0 = 0; e0 < rows * k; e0 += NT * RED_EPT) {
     C z[RED_EPT];
 #pragma unroll
     for (int j = 0; j < RED_EPT; ++j) {
-      const int e = e0 + threadIdx.x + j * 256;
+      const int e = e0 + (int)threadIdx.x + j * NT;
       z[j] = czero<C>();
       if (e >= rows * k) continue;
       const int gm = r0 + e / k, gc = e % k;
@@ -264,7 +265,7 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     }
 #pragma unroll
     for (int j = 0; j < RED_EPT; ++j) {
-      const int e = e0 + threadIdx.x + j * 256;
+      const int e = e0 + (int)threadIdx.x + j * NT;
       if (e >= rows * k) continue;
       const int gm = r0 + e / k, gc = e % k;
       if (gm < f.s) st(Z + (long long)(f.off + gm) * k + gc, z[j]);
@@ -335,8 +336,8 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
 k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
              const LayerDev* __restrict__ layers, int k, const void* scratch) {
@@ -351,11 +352,11 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* S = reinterpret_cast<const C*>(scratch);
   C* X = reinterpret_cast<C*>(L.X);
   const C* Z = reinterpret_cast<const C*>(L.Wt);
-  for (int e0 = 0; e0 < rows * k; e0 += 256 * RED_EPT) {
+  for (int e0 = 0; e0 < rows * k; e0 += NT * RED_EPT) {
     C z[RED_EPT];
 #pragma unroll
     for (int j = 0; j < RED_EPT; ++j) {
-      const int e = e0 + threadIdx.x + j * 256;
+      const int e = e0 + (int)threadIdx.x + j * NT;
       z[j] = czero<C>();
       if (e >= rows * k) continue;
       const int gm = r0 + e / k, gc = e % k;
@@ -365,7 +366,7 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     }
 #pragma unroll
     for (int j = 0; j < RED_EPT; ++j) {
-      const int e = e0 + threadIdx.x + j * 256;
+      const int e = e0 + (int)threadIdx.x + j * NT;
       if (e >= rows * k) continue;
       const int gm = r0 + e / k, gc = e % k;
       st(X + (long long)(f.off + gm) * k + gc, z[j]);
@@ -584,8 +585,13 @@ template <typename T>
 void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tmap,
                        int total, const LayerDev* layers, int k, hipStream_t st) {
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_fwd_gather<T>, dim3(total), dim3(256), 0, st, fr, ids, n,
-                     tmap, layers, k);
+  // a tile is RT rows x k columns: one wave per tile for few columns
+  if (k <= 4)
+    hipLaunchKernelGGL((k_fwd_gather<T, 64>), dim3(total), dim3(64), 0, st, fr, ids, n,
+                       tmap, layers, k);
+  else
+    hipLaunchKernelGGL((k_fwd_gather<T, 256>), dim3(total), dim3(256), 0, st, fr, ids, n,
+                       tmap, layers, k);
 }
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
@@ -609,8 +615,12 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                        const int2* tmap, int total, const LayerDev* layers, int k,
                        const void* scratch, hipStream_t st) {
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_fwd_reduce<T>, dim3(total), dim3(256), 0, st, fr, ids, tasks, n,
-                     tmap, layers, k, scratch);
+  if (k <= 4)
+    hipLaunchKernelGGL((k_fwd_reduce<T, 64>), dim3(total), dim3(64), 0, st, fr, ids, tasks,
+                       n, tmap, layers, k, scratch);
+  else
+    hipLaunchKernelGGL((k_fwd_reduce<T, 256>), dim3(total), dim3(256), 0, st, fr, ids, tasks,
+                       n, tmap, layers, k, scratch);
 }
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
@@ -636,8 +646,12 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                        const int2* tmap, int total, const LayerDev* layers, int k,
                        const void* scratch, hipStream_t st) {
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_bwd_reduce<T>, dim3(total), dim3(256), 0, st, fr, ids, tasks, n,
-                     tmap, layers, k, scratch);
+  if (k <= 4)
+    hipLaunchKernelGGL((k_bwd_reduce<T, 64>), dim3(total), dim3(64), 0, st, fr, ids, tasks,
+                       n, tmap, layers, k, scratch);
+  else
+    hipLaunchKernelGGL((k_bwd_reduce<T, 256>), dim3(total), dim3(256), 0, st, fr, ids, tasks,
+                       n, tmap, layers, k, scratch);
 }
 
 #define HELM_INST_SOLVE(T)                                                           \
