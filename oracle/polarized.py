@@ -37,7 +37,8 @@ R10 Blocks of the polarized matrix (the "algebraic operations and
       (U x)_j = R_bot^j G^j [J_top^j(x_{j-1}) [j >= 1] + J_bot^j(x_j)] - (x_{j,a}, 0)
     and right-hand side f_down_j = -R_bot^j G^j f^j, f_up_j = -R_top^{j+1} G^{j+1} f^{j+1}.
     Algorithms 4 and 5 are the block forward substitutions for D_down and
-    D_up; Algorithm 6 is L (its last-layer line reads the down-going input);
+    D_up; Algorithm 6 is L (its step for the last layer reads the down-going
+    input);
     Algorithm 10, a garbled copy of Algorithm 6, is read as U, the mirror
     image of L; Algorithms 8 and 9 are the forward operators D_down and D_up
     (their captions are swapped in the paper).

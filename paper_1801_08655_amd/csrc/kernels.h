@@ -89,9 +89,15 @@ template <typename T>
 void launch_local_to_X(const LayerDev& L, const double2* r, int k, hipStream_t st);
 template <typename T>
 void launch_X_to_local(const LayerDev& L, double2* w, int k, hipStream_t st);
+// Interface source sum c0 in0 + c1 in1 + c2 in2 of pair vectors (null
+// entries skipped).
+struct JumpTerms {
+  const double2* in[3];
+  double c[3];
+};
 template <typename T>
-void launch_jump(const LayerDev& L, const double2* in0, const double2* in1,
-                 const double2* B, int bottom, int nx, int ny, int k, hipStream_t st);
+void launch_jump(const LayerDev& L, const JumpTerms& t, const double2* B, int bottom, int nx,
+                 int ny, int k, hipStream_t st);
 template <typename T>
 void launch_readout(const LayerDev& L, int bottom, double sx, const ReadTerms& terms,
                     double2* out, int nx, int ny, int k, hipStream_t st);

@@ -82,12 +82,11 @@ __global__ void k_X_to_local(LayerDev L, double2* __restrict__ w, int k) {
   }
 }
 
-// add the interface source of a pair (a, b) = in0 + in1 (in1 may be null)
+// add the interface source of a pair (a, b) = c0 in0 + c1 in1 + c2 in2 (in1
+// and in2 may be null)
 template <typename T>
-__global__ void k_jump(LayerDev L, const double2* __restrict__ in0,
-                       const double2* __restrict__ in1,
-                       const double2* __restrict__ B, int bottom, int nx, int ny,
-                       int k) {
+__global__ void k_jump(LayerDev L, JumpTerms t, const double2* __restrict__ B, int bottom,
+                       int nx, int ny, int k) {
   using C = C_t<T>;
   C* X = reinterpret_cast<C*>(L.X);
   const long long plane = (long long)nx * ny;
@@ -102,10 +101,13 @@ __global__ void k_jump(LayerDev L, const double2* __restrict__ in0,
        e += (long long)gridDim.x * blockDim.x) {
     const long long sp = e / k;
     const int c = (int)(e % k);
-    double2 a = in0[e], b = in0[e + total];
-    if (in1) {
-      double2 a1 = in1[e], b1 = in1[e + total];
-      a.x += a1.x; a.y += a1.y; b.x += b1.x; b.y += b1.y;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (!t.in[i]) continue;
+      const double2 ai = t.in[i][e], bi = t.in[i][e + total];
+      a.x += t.c[i] * ai.x; a.y += t.c[i] * ai.y;
+      b.x += t.c[i] * bi.x; b.y += t.c[i] * bi.y;
     }
     const double2 cf = B[sp];
     const double2 va = make_double2(sa * (cf.x * a.x - cf.y * a.y), sa * (cf.x * a.y + cf.y * a.x));
@@ -362,11 +364,11 @@ void launch_X_to_local(const LayerDev& L, double2* w, int k, hipStream_t st) {
                      0, st, L, w, k);
 }
 template <typename T>
-void launch_jump(const LayerDev& L, const double2* in0, const double2* in1,
-                 const double2* B, int bottom, int nx, int ny, int k, hipStream_t st) {
+void launch_jump(const LayerDev& L, const JumpTerms& t, const double2* B, int bottom, int nx,
+                 int ny, int k, hipStream_t st) {
   long long n = (long long)nx * ny * k;
-  hipLaunchKernelGGL(k_jump<T>, dim3(grid_for(n)), dim3(256), 0, st, L, in0, in1, B,
-                     bottom, nx, ny, k);
+  hipLaunchKernelGGL(k_jump<T>, dim3(grid_for(n)), dim3(256), 0, st, L, t, B, bottom, nx,
+                     ny, k);
 }
 template <typename T>
 void launch_readout(const LayerDev& L, int bottom, double sx, const ReadTerms& terms,
@@ -426,8 +428,8 @@ void launch_volume_norm2(const double2* x, long long N, int k, double* partial,
   template void launch_local_to_X<T>(const LayerDev&, const double2*, int,           \
                                      hipStream_t);                                   \
   template void launch_X_to_local<T>(const LayerDev&, double2*, int, hipStream_t);   \
-  template void launch_jump<T>(const LayerDev&, const double2*, const double2*,      \
-                               const double2*, int, int, int, int, hipStream_t);     \
+  template void launch_jump<T>(const LayerDev&, const JumpTerms&, const double2*, int, \
+                               int, int, int, hipStream_t);                          \
   template void launch_readout<T>(const LayerDev&, int, double, const ReadTerms&,    \
                                   double2*, int, int, int, hipStream_t);
 HELM_INST_VOL(float)

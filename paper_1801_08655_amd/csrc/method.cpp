@@ -20,9 +20,9 @@
 // layer j+1 (sweep and the second L term) share one right-hand side by
 // linearity.  One application of P costs 2L - 3 sequential layer solves.
 // Since P inverts the block lower-triangular part exactly,
-//   P M x = x + P (U x_up, 0),
-// so every GMRES iteration costs one batched solve over the layers (U) plus
-// the two sweeps.
+//   P M x = x + P (U x_up, 0);
+// the local solves of U are folded into those of the sweeps by linearity
+// (apply_A), so a GMRES iteration costs 2L - 2 sequential layer solves.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -73,12 +73,14 @@ void Method::zero_X(int l) {
 }
 
 template <typename T>
-void Method::jump_t(int l, const double2* a, const double2* b, int bottom) {
-  kern::launch_jump<T>(H.layers_h[l], a, b, H.Bcoef.as<double2>(), bottom, H.G.nx,
-                       H.G.ny, k, H.st);
+void Method::jump_t(int l, const kern::JumpTerms& t, int bottom) {
+  kern::launch_jump<T>(H.layers_h[l], t, H.Bcoef.as<double2>(), bottom, H.G.nx, H.G.ny, k,
+                       H.st);
 }
-void Method::jump(int l, const double2* a, const double2* b, int bottom) {
-  if (H.prec == HELM_FP64) jump_t<double>(l, a, b, bottom); else jump_t<float>(l, a, b, bottom);
+void Method::jump(int l, const double2* a, const double2* b, int bottom, double ca, double cb,
+                  const double2* c, double cc) {
+  const kern::JumpTerms t{{a, b, c}, {ca, cb, cc}};
+  if (H.prec == HELM_FP64) jump_t<double>(l, t, bottom); else jump_t<float>(l, t, bottom);
 }
 
 void Method::readout(int l, int bottom, double sx, const kern::ReadTerms& t, double2* out) {
@@ -146,14 +148,55 @@ void Method::apply_U(const double2* xu, double2* out) {
     readout(l, 1, 1.0, terms(pair(xu, l), -1, 0), pair(out, l));
 }
 
-// out = P M x = x + P (U x_up, 0)
+// out = P M x = x + P (U x_up, 0), with the solves of U folded into the
+// sweeps.  With w = U x_up, the downward sweep's step at layer l
+// (1 <= l <= L-2) is
+//   z_l = R_bot^l G^l J_top^l(z_{l-1}) - w_l
+//       = R_bot^l G^l [J_top^l(z_{l-1} - x_{l-1}) - J_bot^l(x_l)] + (x_{l,a}, 0)
+// (x = x_up), one local solve instead of two, and z_0 = -w_0 takes one solve of
+// layer 0.  The same solve read at the top gives keep_{l-1} - V_{l-1} with
+// V_j = R_top^{j+1} G^{j+1} [J_top^{j+1}(x_j) + J_bot^{j+1}(x_{j+1})]; the upward
+// step at layer j+1 adds J_top(x_j) + J_bot(x_{j+1}) to its sources, which
+// adds V_j back.  The last layer's solve (only keep_{L-2}) keeps its plain
+// source.  Cost: 2L - 2 sequential layer solves and no batched U solve.
 void Method::apply_A(const double2* x, double2* out) {
+  const int L = H.G.L;
   const double2* xd = x;
   const double2* xu = x + Vp;
-  apply_U(xu, y.as<double2>());
-  apply_P(y.as<double2>(), nullptr, zd.as<double2>(), zu.as<double2>());
-  kern::launch_add(out, xd, zd.as<double2>(), Vp, H.st);
-  kern::launch_add(out + Vp, xu, zu.as<double2>(), Vp, H.st);
+  double2* od = zd.as<double2>();
+  double2* ou = zu.as<double2>();
+  double2* kp = keep.as<double2>();
+  if (L >= 2) {
+    // z_down_0 = -(U x_up)_0
+    zero_X(0);
+    jump(0, pair(xu, 0), nullptr, 1, -1.0);
+    solve_single(0);
+    readout(0, 1, 1.0, terms(pair(xu, 0), 1, 0), pair(od, 0));
+    for (int l = 1; l <= L - 2; ++l) {
+      zero_X(l);
+      jump(l, pair(od, l - 1), pair(xu, l - 1), 0, 1.0, -1.0);
+      jump(l, pair(xu, l), nullptr, 1, -1.0);
+      solve_single(l);
+      readout(l, 1, 1.0, terms(pair(xu, l), 1, 0), pair(od, l));
+      readout(l, 0, 1.0, terms(), pair(kp, l - 1));      // keep_{l-1} - V_{l-1}
+    }
+    zero_X(L - 1);
+    jump(L - 1, pair(od, L - 2), nullptr, 0);
+    solve_single(L - 1);
+    readout(L - 1, 0, 1.0, terms(), pair(kp, L - 2));    // keep_{L-2}
+    // upward: z_up_{L-2} = keep_{L-2} - (0, z_down_{L-2,b})
+    readout(L - 1, 0, 0.0, terms(pair(kp, L - 2), 1, 1, pair(od, L - 2), 0, -1),
+            pair(ou, L - 2));
+    for (int j = L - 3; j >= 0; --j) {
+      zero_X(j + 1);
+      jump(j + 1, pair(ou, j + 1), pair(od, j + 1), 1, 1.0, 1.0, pair(xu, j + 1), 1.0);
+      jump(j + 1, pair(xu, j), nullptr, 0);
+      solve_single(j + 1);
+      readout(j + 1, 0, 1.0, terms(pair(kp, j), 1, 1, pair(od, j), 0, -1), pair(ou, j));
+    }
+  }
+  kern::launch_add(out, xd, od, Vp, H.st);
+  kern::launch_add(out + Vp, xu, ou, Vp, H.st);
 }
 
 void Method::scatter_sources(const double2* f) {
@@ -175,6 +218,35 @@ void Method::polarized_rhs(const double2* f, double2* fd, double2* fu) {
   for (int l = 0; l < L; ++l) {
     if (l <= L - 2) readout(l, 1, -1.0, terms(), pair(fd, l));
     if (l >= 1) readout(l, 0, -1.0, terms(), pair(fu, l - 1));
+  }
+}
+
+// (od, ou) = P (f_down, f_up) for the volume source f, with the local solves
+// of the polarized right-hand side folded into the sweeps by linearity:
+//   z_0 = R_bot^0 G^0 f^0,  z_l = R_bot^l G^l [J_top^l(z_{l-1}) + f^l],
+// and the top read-out of the same solve is keep_{l-1} - f_up_{l-1}, which is
+// the term the upward step subtracts.  2L - 2 sequential layer solves and no
+// batched solve over all layers.
+void Method::precondition_source(const double2* f, double2* od, double2* ou) {
+  const int L = H.G.L;
+  double2* kp = keep.as<double2>();
+  for (int l = 0; l <= L - 1; ++l) {
+    zero_X(l);
+    if (H.prec == HELM_FP64)
+      kern::launch_scatter_source<double>(H.layers_h[l], f, H.G.nx, H.G.ny, N, k, H.st);
+    else
+      kern::launch_scatter_source<float>(H.layers_h[l], f, H.G.nx, H.G.ny, N, k, H.st);
+    if (l >= 1) jump(l, pair(od, l - 1), nullptr, 0);
+    solve_single(l);
+    if (l <= L - 2) readout(l, 1, 1.0, terms(), pair(od, l));
+    if (l >= 1) readout(l, 0, 1.0, terms(), pair(kp, l - 1));   // keep_{l-1} - f_up_{l-1}
+  }
+  readout(L - 1, 0, 0.0, terms(pair(kp, L - 2), 1, 1, pair(od, L - 2), 0, -1), pair(ou, L - 2));
+  for (int j = L - 3; j >= 0; --j) {
+    zero_X(j + 1);
+    jump(j + 1, pair(ou, j + 1), pair(od, j + 1), 1);
+    solve_single(j + 1);
+    readout(j + 1, 0, 1.0, terms(pair(kp, j), 1, 1, pair(od, j), 0, -1), pair(ou, j));
   }
 }
 
@@ -395,9 +467,7 @@ int Method::polarized_solve(const double2* f, double2* u, const std::vector<doub
     bpol.alloc((size_t)2 * Vp * sizeof(double2));
     xpol.alloc((size_t)2 * Vp * sizeof(double2));
   }
-  double2* fdv = fpol.as<double2>();
-  polarized_rhs(f, fdv, fdv + Vp);
-  apply_P(fdv, fdv + Vp, bpol.as<double2>(), bpol.as<double2>() + Vp);
+  precondition_source(f, bpol.as<double2>(), bpol.as<double2>() + Vp);
   HELM_HIP(hipStreamSynchronize(H.st));
   double t1 = now_ms();
   int iters = 0;

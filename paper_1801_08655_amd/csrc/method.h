@@ -29,8 +29,10 @@ struct Method {
   double2* pair(double2* v, int j) const;
   const double2* pair(const double2* v, int j) const;
   void zero_X(int l);
-  template <typename T> void jump_t(int l, const double2* a, const double2* b, int bottom);
-  void jump(int l, const double2* a, const double2* b, int bottom);
+  template <typename T> void jump_t(int l, const kern::JumpTerms& t, int bottom);
+  // X^l += J_top or J_bot (bottom) of ca a + cb b + cc c (b, c may be null)
+  void jump(int l, const double2* a, const double2* b, int bottom, double ca = 1.0,
+            double cb = 1.0, const double2* c = nullptr, double cc = 1.0);
   void readout(int l, int bottom, double sx, const kern::ReadTerms& t, double2* out);
   static kern::ReadTerms terms(const double2* a = nullptr, double ca = 0, double cb = 0,
                                const double2* b = nullptr, double cb_a = 0,
@@ -42,6 +44,7 @@ struct Method {
   void apply_A(const double2* x, double2* out);
   void scatter_sources(const double2* f);
   void polarized_rhs(const double2* f, double2* fd, double2* fu);
+  void precondition_source(const double2* f, double2* od, double2* ou);
   void reconstruct(const double2* f, const double2* tr, double2* u);
   void dot(const double2* a, const double2* b, long long V, double2* out);
   int gmres(const double2* b, double2* x, const std::vector<double>& tol, int max_iter,

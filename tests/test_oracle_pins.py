@@ -281,6 +281,84 @@ def test_sweeps_invert_forward_blocks(homog25):
     assert np.abs(pt.sweep_up(pt.D_up(x)) - x).max() <= 1e-12 * np.abs(x).max()
 
 
+def test_folded_sweep_equals_preconditioned_operator(homog25):
+    """The device path applies P M x as x + P (U x_up, 0) with the local solves
+    of U folded into the sweep solves by linearity: one solve of layer 0,
+    downward solves with the sources J_top(z_{l-1} - x_{l-1}) - J_bot(x_l),
+    and upward solves that also take J_top(x_j) + J_bot(x_{j+1}) to restore
+    the top read-outs.  Written here with the oracle's own local solves,
+    sources and read-outs, it must equal P (M x) from the oracle's blocks."""
+    wl, pb, f, u, pt = homog25
+    rng = np.random.default_rng(9)
+    shape = pt.zero_pairs().shape
+    xd = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    xu = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    L = pt.L
+
+    def a_only(p):
+        return np.stack([p[0], np.zeros_like(p[1])])
+
+    def b_only(p):
+        return np.stack([np.zeros_like(p[0]), p[1]])
+
+    zd, zu, keep = pt.zero_pairs(), pt.zero_pairs(), pt.zero_pairs()
+    src = pt.zeros_local(0)
+    pt.add_J_bot(0, src, -xu[0])
+    zd[0] = pt.R_bot(0, pt.G(0, src)) + a_only(xu[0])
+    for l in range(1, L - 1):
+        src = pt.zeros_local(l)
+        pt.add_J_top(l, src, zd[l - 1] - xu[l - 1])
+        pt.add_J_bot(l, src, -xu[l])
+        w = pt.G(l, src)
+        zd[l] = pt.R_bot(l, w) + a_only(xu[l])
+        keep[l - 1] = pt.R_top(l, w)
+    src = pt.zeros_local(L - 1)
+    pt.add_J_top(L - 1, src, zd[L - 2])
+    keep[L - 2] = pt.R_top(L - 1, pt.G(L - 1, src))
+    zu[L - 2] = keep[L - 2] - b_only(zd[L - 2])
+    for j in range(L - 3, -1, -1):
+        src = pt.zeros_local(j + 1)
+        pt.add_J_bot(j + 1, src, zu[j + 1] + zd[j + 1] + xu[j + 1])
+        pt.add_J_top(j + 1, src, xu[j])
+        zu[j] = pt.R_top(j + 1, pt.G(j + 1, src)) + keep[j] - b_only(zd[j])
+    ref_d, ref_u = pt.precondition(*pt.apply_M(xd, xu))
+    scale = max(np.abs(ref_d).max(), np.abs(ref_u).max())
+    assert np.abs(xd + zd - ref_d).max() <= 1e-11 * scale
+    assert np.abs(xu + zu - ref_u).max() <= 1e-11 * scale
+
+
+def test_folded_source_sweep_equals_preconditioned_rhs(homog25):
+    """The device path forms P (f_down, f_up) in one sweep pair: the layer
+    sources f^l join the downward solves, whose top read-outs then already
+    hold keep - f_up.  With the oracle's solves, sources and read-outs it must
+    equal the oracle's P applied to its polarized right-hand side."""
+    wl, pb, f, u, pt = homog25
+    L = pt.L
+
+    def b_only(p):
+        return np.stack([np.zeros_like(p[0]), p[1]])
+
+    zd, zu, keep = pt.zero_pairs(), pt.zero_pairs(), pt.zero_pairs()
+    for l in range(L):
+        src = pt.restrict_source(l, f)
+        if l >= 1:
+            pt.add_J_top(l, src, zd[l - 1])
+        w = pt.G(l, src)
+        if l <= L - 2:
+            zd[l] = pt.R_bot(l, w)
+        if l >= 1:
+            keep[l - 1] = pt.R_top(l, w)
+    zu[L - 2] = keep[L - 2] - b_only(zd[L - 2])
+    for j in range(L - 3, -1, -1):
+        src = pt.zeros_local(j + 1)
+        pt.add_J_bot(j + 1, src, zu[j + 1] + zd[j + 1])
+        zu[j] = pt.R_top(j + 1, pt.G(j + 1, src)) + keep[j] - b_only(zd[j])
+    ref_d, ref_u = pt.precondition(*pt.polarized_rhs(f))
+    scale = max(np.abs(ref_d).max(), np.abs(ref_u).max())
+    assert np.abs(zd - ref_d).max() <= 1e-11 * scale
+    assert np.abs(zu - ref_u).max() <= 1e-11 * scale
+
+
 def test_polarized_method_matches_direct_homogeneous(homog25):
     wl, pb, f, u, pt = homog25
     up, iters, hist = pt.solve(f, tol=1e-10)
