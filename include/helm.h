@@ -261,11 +261,15 @@ int helm_apply_operator_dev(helm_handle* h, int k, const double* f_dev,
  * [j][plane 0/1][y][x][column], complex double, device memory.
  *   op 0: the preconditioner P applied to (x_down, x_up)  (Algs. 4-6),
  *   op 1: P M x = x + P (U x_up, 0)                        (Alg. 7 + P),
+ *         with the local solves of U folded into the sweeps,
  *   op 2: U x_up                                            (Alg. 10),
  *   op 3: the polarized right-hand side (f_down, f_up) of a volume source
  *         (the first steps of Alg. 2); `in_dev` is then k volumes
- *         (RHS-major).
- * For ops 0-1 `in_dev`/`out_dev` hold [x_down | x_up], each a pair vector. */
+ *         (RHS-major),
+ *   op 4: P (f_down, f_up) of a volume source in one folded sweep pair (the
+ *         right-hand side GMRES works on); `in_dev` is k volumes.
+ * For ops 0-1 `in_dev`/`out_dev` hold [x_down | x_up], each a pair vector;
+ * for ops 3-4 `out_dev` holds [down | up]. */
 int helm_polarized_op_dev(helm_handle* h, int op, int k, const double* in_dev,
                           double* out_dev);
 

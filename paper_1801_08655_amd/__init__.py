@@ -175,7 +175,7 @@ class Solver:
 
     def polarized_op(self, op: int, x, k: int):
         """Interface operators (see include/helm.h): 0 = P, 1 = P M, 2 = U,
-        3 = polarized right-hand side of a volume source."""
+        3 = polarized right-hand side of a volume source, 4 = P of it."""
         import torch
         nx, ny, _ = self.n
         vp = (self.n_layers - 1) * 2 * nx * ny * k

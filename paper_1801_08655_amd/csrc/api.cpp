@@ -410,7 +410,7 @@ int helm_polarized_op_dev(helm_handle* h, int op, int k, const double* in_dev,
     HELM_REQUIRE(h && in_dev && out_dev && k >= 1, HELM_EINVAL, "bad argument");
     Handle& H = h->impl;
     HELM_REQUIRE(H.G.L >= 2, HELM_EINVAL, "interface operators need at least two layers");
-    HELM_REQUIRE(op >= 0 && op <= 3, HELM_EINVAL, "unknown operator");
+    HELM_REQUIRE(op >= 0 && op <= 4, HELM_EINVAL, "unknown operator");
     HELM_HIP(hipSetDevice(H.device));
     Method& M = method_for(h, k);
     const double2* in = reinterpret_cast<const double2*>(in_dev);
@@ -420,6 +420,7 @@ int helm_polarized_op_dev(helm_handle* h, int op, int k, const double* in_dev,
       case 1: M.apply_A(in, out); break;
       case 2: M.apply_U(in, out); break;
       case 3: M.polarized_rhs(in, out, out + M.Vp); break;
+      case 4: M.precondition_source(in, out, out + M.Vp); break;
     }
     HELM_HIP(hipGetLastError());
     HELM_HIP(hipStreamSynchronize(H.st));

@@ -106,6 +106,29 @@ def test_interface_operators_match_oracle(homog):
     assert relative_error(ga, ref)[0] <= 1e-10
 
 
+def test_polarized_rhs_and_its_preconditioned_form_match_oracle(homog):
+    """op 3: (f_down, f_up) of a volume source; op 4: P (f_down, f_up) from one
+    folded sweep pair (the layer sources join the downward solves), against the
+    oracle's polarized right-hand side and its P."""
+    wl, pb, _ = homog
+    s = _solver(wl, "fp64")
+    pt_cpu = PolarizedTraces(pb, wl.n_layers, wl.pml_local)
+    k = 2
+    nx, ny, nz = wl.n
+    f = [_rand((nz, ny, nx), 31 + c) for c in range(k)]
+    gf = torch.from_numpy(np.stack(f).ravel()).cuda()
+    rhs = [pt_cpu.polarized_rhs(x) for x in f]
+    g3 = s.polarized_op(3, gf, k).cpu().numpy()
+    ref = np.concatenate([_pairs_gpu_layout([r[0] for r in rhs]),
+                          _pairs_gpu_layout([r[1] for r in rhs])])
+    assert relative_error(g3, ref)[0] <= 1e-11
+    g4 = s.polarized_op(4, gf, k).cpu().numpy()
+    pre = [pt_cpu.precondition(*r) for r in rhs]
+    ref = np.concatenate([_pairs_gpu_layout([r[0] for r in pre]),
+                          _pairs_gpu_layout([r[1] for r in pre])])
+    assert relative_error(g4, ref)[0] <= 1e-10
+
+
 @pytest.mark.parametrize("name", ["homogeneous-25", "smooth-24", "layered-28"])
 def test_fp64_solve_matches_direct(name):
     wl = workload(name)
