@@ -301,6 +301,7 @@ def batch_bench(args, torch, pt):
                    "rhs": [len(w.sources) for w in wls]},
         "summary": summ,
         "all_ok": all(i["status"] == 0 for i in infos),
+        "failed": {i: inf["status"] for i, inf in enumerate(infos) if inf["status"] != 0},
         "est_error_max": max(i["est_error_max"] for i in infos),
         "rel_residual_max": max(i["rel_residual_max"] for i in infos),
         "factor_ms": [i["factor_ms"] for i in infos],

@@ -142,6 +142,14 @@ int helm_plan(const helm_grid* g, int pml_width, int n_layers,
               const helm_options* opt, size_t* factor_bytes,
               size_t* bytes_per_rhs, size_t* max_front);
 
+/* Device memory one more column slot costs in a lane of the request server
+ * or of a batched problem (include/helm_serve.h, include/helm_batch.h): the
+ * bytes_per_rhs of helm_plan plus the Krylov and sweep vectors of the lane's
+ * narrower step widths.  A lane of K slots reserves factor_bytes +
+ * K * lane_bytes_per_rhs.  Same arguments and errors as helm_plan. */
+int helm_plan_lane(const helm_grid* g, int pml_width, int n_layers,
+                   const helm_options* opt, size_t* lane_bytes_per_rhs);
+
 /* Offline stage (Algorithm 1).  `m` is the squared slowness 1/c^2 on the
  * full grid (host pointer, nx*ny*nz doubles, copied).  `omega` > 0 is the
  * angular frequency, `pml_width` the global absorbing nodes per face,

@@ -8,10 +8,13 @@
  * this call only schedules the problems on one device:
  *
  *  - Problems are admitted in the given order while the planned device
- *    memory of the admitted ones (factors + a lane of min(n_rhs, slots)
- *    columns, from the same symbolic plan as helm_plan) fits the budget and
+ *    memory of the admitted ones (factor_bytes + min(n_rhs, slots) *
+ *    lane_bytes_per_rhs from helm_plan / helm_plan_lane) fits the budget and
  *    at most max_resident are resident.  A problem whose plan does not fit
- *    an empty device ends with HELM_ENOMEM and the others proceed.
+ *    an empty device ends with HELM_ENOMEM and the others proceed.  The
+ *    factorization also needs a transient frontal workspace; when that does
+ *    not fit beside the resident problems, the problem waits for one of them
+ *    to finish and is factored again (its factor_ms counts every attempt).
  *  - An admitted problem is factored on its own stream by the calling
  *    thread while the problems admitted before it keep solving, then served
  *    by a lane of the request server (include/helm_serve.h): its columns run

@@ -41,14 +41,18 @@ def options(**kw) -> _lib.helm_options:
 
 
 def plan(n, pml: int, n_layers: int, h: float = None, **kw):
-    """Exact factor bytes, device bytes per RHS column and largest front."""
+    """Exact factor bytes, device bytes per RHS column (helm_solve and a
+    server or batch lane slot) and largest front."""
     nx, ny, nz = n
     g = _lib.helm_grid(nx, ny, nz, h if h else 1.0 / (max(n) - 1))
     o = options(**kw)
-    fb, br, mf = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    fb, br, mf, lb = (ctypes.c_size_t() for _ in range(4))
     check(lib().helm_plan(ctypes.byref(g), pml, n_layers, ctypes.byref(o),
                           ctypes.byref(fb), ctypes.byref(br), ctypes.byref(mf)), "helm_plan")
-    return {"factor_bytes": fb.value, "bytes_per_rhs": br.value, "max_front": mf.value}
+    check(lib().helm_plan_lane(ctypes.byref(g), pml, n_layers, ctypes.byref(o),
+                               ctypes.byref(lb)), "helm_plan_lane")
+    return {"factor_bytes": fb.value, "bytes_per_rhs": br.value, "max_front": mf.value,
+            "lane_bytes_per_rhs": lb.value}
 
 
 def node_indices(nodes: Sequence, n) -> np.ndarray:

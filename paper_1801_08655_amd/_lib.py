@@ -18,7 +18,8 @@ HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EZEROPIVOT, HELM_ENOCONV, HELM_EHIP = ra
 HELM_FP64, HELM_MIXED = 0, 1
 
 EXPORTED = [
-    "helm_default_options", "helm_plan", "helm_factorize", "helm_factorize_dev",
+    "helm_default_options", "helm_plan", "helm_plan_lane", "helm_factorize",
+    "helm_factorize_dev",
     "helm_solve", "helm_solve_dev", "helm_solve_points", "helm_free",
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
@@ -224,6 +225,9 @@ def lib():
     L.helm_plan.argtypes = [ctypes.POINTER(helm_grid), I, I, ctypes.POINTER(helm_options),
                             ctypes.POINTER(S), ctypes.POINTER(S), ctypes.POINTER(S)]
     L.helm_plan.restype = I
+    L.helm_plan_lane.argtypes = [ctypes.POINTER(helm_grid), I, I, ctypes.POINTER(helm_options),
+                                 ctypes.POINTER(S)]
+    L.helm_plan_lane.restype = I
     for fn in (L.helm_factorize, L.helm_factorize_dev):
         fn.argtypes = [ctypes.POINTER(helm_grid), P, D, I, I,
                        ctypes.POINTER(helm_options), ctypes.POINTER(H)]

@@ -131,6 +131,19 @@ int helm_plan(const helm_grid* g, int pml_width, int n_layers, const helm_option
   });
 }
 
+int helm_plan_lane(const helm_grid* g, int pml_width, int n_layers, const helm_options* opt,
+                   size_t* lane_bytes_per_rhs) {
+  return guard([&] {
+    HELM_REQUIRE(g, HELM_EINVAL, "null grid");
+    helm_options o = resolve(opt);
+    Geometry G;
+    build_geometry(G, *g, 1.0, pml_width, n_layers, o.pml_local, 1.0, o.leaf_size);
+    const size_t elem = o.precision == HELM_FP64 ? 16 : 8;
+    if (lane_bytes_per_rhs) *lane_bytes_per_rhs = lane_bytes_per_slot(G, elem);
+    return HELM_OK;
+  });
+}
+
 int helm_factorize(const helm_grid* g, const double* m, double omega, int pml_width,
                    int n_layers, const helm_options* opt, helm_handle** out) {
   return guard([&] {

@@ -81,9 +81,12 @@ int helm_solve_batch(int n, const helm_problem* P, const helm_batch_options* bo,
             continue;
           }
           const int K = std::max(1, std::min(p.n_rhs, o.slots));
-          size_t fb = 0, br = 0, mf = 0;
-          int st = helm_plan(&p.grid, p.pml_width, p.n_layers, &o.opt, &fb, &br, &mf);
+          size_t fb = 0, br = 0;
+          int st = helm_plan(&p.grid, p.pml_width, p.n_layers, &o.opt, &fb, nullptr, nullptr);
+          if (st == HELM_OK)
+            st = helm_plan_lane(&p.grid, p.pml_width, p.n_layers, &o.opt, &br);
           if (st != HELM_OK) { I.status = st; ++next; continue; }
+          // what the server's lane will reserve for K slots
           const size_t need = fb + br * (size_t)K;
           if (planned + need > budget) {
             if (res.empty()) { I.status = HELM_ENOMEM; ++next; continue; }
@@ -94,10 +97,17 @@ int helm_solve_batch(int n, const helm_problem* P, const helm_batch_options* bo,
           I.planned_bytes = need;
           helm_handle* h = nullptr;
           const double tf = wall_ms();
-          st = helm_factorize(&p.grid, p.m, p.omega, p.pml_width, p.n_layers, &o.opt, &h);
-          I.factor_ms = wall_ms() - tf;
+          // the factorization keeps room for the solve workspace of max_rhs
+          // columns: the lane's K
+          helm_options po = o.opt;
+          po.max_rhs = K;
+          st = helm_factorize(&p.grid, p.m, p.omega, p.pml_width, p.n_layers, &po, &h);
+          I.factor_ms += wall_ms() - tf;
           I.t_factored_ms = wall_ms() - t0;
-          fsum += I.factor_ms * 1e-3;
+          fsum += (wall_ms() - tf) * 1e-3;
+          // the factorization's transient frontal workspace did not fit beside
+          // the resident problems: retry once one of them has finished
+          if (st == HELM_ENOMEM && !res.empty()) break;
           if (st != HELM_OK) { I.status = st; ++next; continue; }
           int model = -1;
           try {

@@ -255,6 +255,10 @@ size_t plan_pair_bytes_per_rhs(const Geometry& G) {
   return pv * 2 * (18 + 8);
 }
 
+size_t lane_bytes_per_slot(const Geometry& G, size_t elem) {
+  return plan_bytes_per_rhs(G, elem) + plan_pair_bytes_per_rhs(G);
+}
+
 size_t plan_bytes_per_rhs(const Geometry& G, size_t elem) {
   // local solve vectors of every layer (X, Wt, Ub even/odd)
   size_t per = 0;
@@ -274,6 +278,30 @@ void Handle::factorize() {
   if (prec == HELM_FP64) factorize_t<double>(); else factorize_t<float>();
   factor_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Frontal workspace of one layer per depth: the sum of (s+b)^2 over its fronts
+// and of the panel copies s nb.
+std::pair<std::vector<long long>, std::vector<long long>> layer_workspace(const LayerPlan& P,
+                                                                          int nb) {
+  std::vector<long long> sum(P.max_depth + 1, 0), pan(P.max_depth + 1, 0);
+  for (const auto& F : P.fronts) {
+    sum[F.depth] += (long long)(F.s + F.b) * (F.s + F.b);
+    pan[F.depth] += (long long)F.s * nb;
+  }
+  return {sum, pan};
+}
+
+// Bytes of the two depth-parity frontal buffers and the two panel copies for
+// per-depth element counts a (fronts) and p (panels).
+size_t workspace_bytes(const std::vector<long long>& a, const std::vector<long long>& p,
+                       size_t elem) {
+  long long m0 = 0, m1 = 0, mp = 0;
+  for (size_t d = 0; d < a.size(); ++d) {
+    if (d & 1) m1 = std::max(m1, a[d]); else m0 = std::max(m0, a[d]);
+    mp = std::max(mp, p[d]);
+  }
+  return (size_t)(m0 + m1 + 2 * mp) * elem;
 }
 
 template <typename T>
@@ -301,27 +329,14 @@ void Handle::factorize_t() {
   // leave room for the solve workspace of the default batch
   size_t reserve = plan_bytes_per_rhs(G, elem) * (size_t)std::max(1, opt.max_rhs);
   size_t ws_budget = avail > reserve ? (avail - reserve) : avail / 2;
-  auto layer_ws = [&](int l) {
-    const LayerPlan& P = G.layers[l];
-    std::vector<long long> sum(P.max_depth + 1, 0), pan(P.max_depth + 1, 0);
-    for (const auto& F : P.fronts) {
-      sum[F.depth] += (long long)(F.s + F.b) * (F.s + F.b);
-      pan[F.depth] += (long long)F.s * nb;
-    }
-    return std::make_pair(sum, pan);
-  };
+  auto layer_ws = [&](int l) { return layer_workspace(G.layers[l], nb); };
   std::vector<std::vector<int>> groups;
   {
     std::vector<int> cur;
     std::vector<long long> acc;
     std::vector<long long> accp;
     auto cost = [&](const std::vector<long long>& a, const std::vector<long long>& p) {
-      long long m0 = 0, m1 = 0, mp = 0;
-      for (size_t d = 0; d < a.size(); ++d) {
-        if (d & 1) m1 = std::max(m1, a[d]); else m0 = std::max(m0, a[d]);
-        mp = std::max(mp, p[d]);
-      }
-      return (size_t)(m0 + m1 + 2 * mp) * elem;
+      return workspace_bytes(a, p, elem);
     };
     for (int l = 0; l < L; ++l) {
       auto w = layer_ws(l);

@@ -174,7 +174,15 @@ struct Handle {
 };
 
 size_t plan_factor_elems(const Geometry& G);
+// frontal workspace per depth of one layer, and its bytes for a group
+std::pair<std::vector<long long>, std::vector<long long>> layer_workspace(const LayerPlan& P,
+                                                                          int nb);
+size_t workspace_bytes(const std::vector<long long>& a, const std::vector<long long>& p,
+                       size_t elem);
 size_t plan_bytes_per_rhs(const Geometry& G, size_t elem);
 size_t plan_pair_bytes_per_rhs(const Geometry& G);
+// per-slot reservation of a server or batch lane: the solve workspace of one
+// column plus the Krylov and sweep vectors of the lane's narrower widths
+size_t lane_bytes_per_slot(const Geometry& G, size_t elem);
 
 }  // namespace helm

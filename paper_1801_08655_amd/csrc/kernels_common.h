@@ -183,7 +183,10 @@ __device__ __forceinline__ C_t<T> view_at(const View<T>& v, int r, int k) {
 // apart (mod 64), so the 64 lanes touch 64 distinct banks.  The row-major
 // stride 2 GK + 2 puts the 16 rows of a read on even banks, offset by k.
 constexpr int PSTR = 2 * GK + 2;
-template <int W> constexpr int kmajor_stride() { return W == 64 ? 80 : 48; }
+template <int W> constexpr int kmajor_stride() {
+  static_assert(W == 16 || W == 32 || W == 64, "k-major rows are padded for 16, 32 or 64");
+  return W == 64 ? 80 : 48;
+}
 template <typename T, int BM, int BN = GT, bool PKM = false> struct GemmSmem {
   T P[PKM ? 2 * GK : BM][PKM ? kmajor_stride<BM>() : PSTR];
   T Q1[2 * GK][kmajor_stride<BN>()];

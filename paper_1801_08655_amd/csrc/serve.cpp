@@ -215,7 +215,7 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   HELM_HIP(hipSetDevice(H.device));
   std::lock_guard<std::mutex> lk(mu);
   for (auto& l : lanes) HELM_REQUIRE(l->gone || l->h != h, HELM_EINVAL, "handle already served");
-  const size_t per = plan_bytes_per_rhs(H.G, H.elem);
+  const size_t per = lane_bytes_per_slot(H.G, H.elem);
   size_t free_b = 0, total_b = 0;
   HELM_HIP(hipMemGetInfo(&free_b, &total_b));
   // memory admission: the largest slot count whose workspace fits
@@ -223,7 +223,7 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   auto fits = [&](int k) {
     // the lane's full-width workspace plus the Krylov and sweep vectors of
     // its narrower widths (together at most those of one more full width)
-    const size_t ws = (per + plan_pair_bytes_per_rhs(H.G)) * (size_t)k;
+    const size_t ws = per * (size_t)k;
     if (opt.hbm_budget_bytes) return reserved + H.bytes_factors + ws <= opt.hbm_budget_bytes;
     return ws <= (size_t)(0.9 * (double)free_b);
   };
@@ -233,7 +233,7 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   ln->model = (int)lanes.size();
   ln->h = h;
   ln->K = K;
-  ln->bytes = H.bytes_factors + (per + plan_pair_bytes_per_rhs(H.G)) * (size_t)K;
+  ln->bytes = H.bytes_factors + per * (size_t)K;
   const long long N = (long long)H.G.nx * H.G.ny * H.G.nz;
   const size_t vol = (size_t)N * K * sizeof(double2);
   ln->F.alloc(vol);

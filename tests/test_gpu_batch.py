@@ -69,7 +69,7 @@ def test_batch_memory_budget_refuses_only_what_cannot_fit(probs):
     for p in ps:
         n = p.m.shape[0]
         pl = pt.plan((n, n, n), p.pml, p.n_layers, pml_local=3, precision="fp64")
-        needs.append(pl["factor_bytes"] + pl["bytes_per_rhs"] * min(len(p.sources), 8))
+        needs.append(pl["factor_bytes"] + pl["lane_bytes_per_rhs"] * min(len(p.sources), 8))
     budget = int(sorted(needs)[-2] * 1.05)       # the largest problem cannot fit
     big = int(np.argmax(needs))
     res, summ = solve_batch(ps, slots=8, hbm_budget_bytes=budget, precision="fp64",
