@@ -342,9 +342,12 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    flags = pt._lib.HELM_FLAG_PROFILE if args.profile else 0
-    if not args.no_autotune:
-        flags |= pt._lib.HELM_FLAG_AUTOTUNE
+    # the factorizations and the one-column probe time every kernel class;
+    # the timed steps time only the forward substitution GEMM launches (the
+    # roofline's kernel), so that the other kernels run without events
+    tune = 0 if args.no_autotune else pt._lib.HELM_FLAG_AUTOTUNE
+    flags = (pt._lib.HELM_FLAG_PROFILE if args.profile else 0) | tune
+    step_flags = (pt._lib.HELM_FLAG_PROFILE_FWD if args.profile else 0) | tune
     common = dict(pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64, flags=flags)
     extra = {}
 
@@ -359,6 +362,8 @@ def main():
         torch.cuda.synchronize()
         f64_factor = time.perf_counter() - t0
         log(f"[fp64] factorized in {f64_factor:.2f}s; solving R={R}")
+        extra["fp64_factor_kernels"] = s64.kernel_stats(reset=True)
+        s64.set_options(flags=step_flags)
         u_ref, info64, tot64, lat64 = timed_solves(s64, srcs, args.fp64_steps,
                                                    args.fp64_warmup, torch)
         fp64 = {"value": R * args.fp64_steps / tot64, "factor_s": f64_factor,
@@ -381,8 +386,10 @@ def main():
     factor_s = time.perf_counter() - t0
     log(f"[mixed] factorized in {factor_s:.2f}s; warmup {args.warmup}, steps {args.steps}")
     fstats = s.kernel_stats(reset=True)
+    s.set_options(flags=step_flags)
     u, info, total, lat = timed_solves(s, srcs, args.steps, args.warmup, torch)
     kstats = s.kernel_stats()
+    s.set_options(flags=flags)
     value = R * args.steps / total
     # the same step with the 64 solution volumes handed back to host memory
     # (pinned): the PCIe-inclusive rate, reported beside the HBM-resident one

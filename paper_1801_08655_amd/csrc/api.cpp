@@ -338,7 +338,7 @@ int helm_set_solve_options(helm_handle* h, const helm_options* opt) {
     H.opt.err_target = o.err_target;
     H.opt.max_rhs = o.max_rhs;
     H.opt.flags = o.flags;
-    H.profile = (o.flags & HELM_FLAG_PROFILE) != 0;
+    H.set_profile(o.flags);
     return HELM_OK;
   });
 }

@@ -107,11 +107,23 @@ void Handle::init_device(const helm_options& o) {
   }
   prec = o.precision == HELM_FP64 ? HELM_FP64 : HELM_MIXED;
   elem = prec == HELM_FP64 ? 16 : 8;
-  profile = (o.flags & HELM_FLAG_PROFILE) != 0;
+  set_profile(o.flags);
 }
 
-hipEvent_t Handle::prof_begin() {
-  if (!profile) return nullptr;
+void Handle::set_profile(int flags) {
+  profile_mask = 0;
+  if (flags & HELM_FLAG_PROFILE) profile_mask = (1u << K_NCLASS) - 1;
+  if (flags & HELM_FLAG_PROFILE_FWD) profile_mask |= 1u << K_FWD_GEMM;
+}
+
+// An event recorded on the handle's stream, for the timing of class cls
+// (null when that class is not timed).
+hipEvent_t Handle::prof_begin(int cls) {
+  if (!((profile_mask >> cls) & 1u)) return nullptr;
+  return record_event();
+}
+
+hipEvent_t Handle::record_event() {
   hipEvent_t e;
   if (!ev_free.empty()) {
     e = ev_free.back();
@@ -127,7 +139,7 @@ hipEvent_t Handle::prof_begin() {
 
 void Handle::prof_end(int cls, hipEvent_t a, double flops, double bytes) {
   if (!a) return;
-  hipEvent_t b = prof_begin();
+  hipEvent_t b = record_event();
   pending.push_back(PendingEvent{cls, a, b, flops, bytes});
 }
 
@@ -433,11 +445,11 @@ void Handle::factorize_t() {
         double n = fronts_h[v[a]].s + fronts_h[v[a]].b;
         front_elems += n * n;
       }
-      hipEvent_t e0 = prof_begin();
+      hipEvent_t e0 = prof_begin(K_EXTEND_ADD);
       kern::launch_extend_add<T>(fr, ids, fd.n, fd.pFull.as<int2>(), fd.pFull_h[fd.n], ld,
                                  ws0.p, ws1.p, st);
       prof_end(K_EXTEND_ADD, e0, 0, 2 * front_elems * elem);
-      e0 = prof_begin();
+      e0 = prof_begin(K_ORIG);
       kern::launch_orig_entries<T>(fr, ids, fd.n, fd.pRow.as<int2>(), pRow[fd.n], ld,
                                    ws0.p, ws1.p, grid, st);
       prof_end(K_ORIG, e0, 0, 0);
@@ -446,36 +458,36 @@ void Handle::factorize_t() {
         int n_act = 0;
         while (n_act < fd.n && fd.s_sorted[n_act] > k) ++n_act;
         double sw_flops = 0, sw_bytes = 0;
-        if (profile)
+        if (profile())
           for (int a = 0; a < n_act; ++a) {
             double n = fronts_h[v[a]].s + fronts_h[v[a]].b;
             double nbf = std::min(nb, fronts_h[v[a]].s - k);
             sw_flops += 8.0 * n * n * nbf;
             sw_bytes += (2.0 * n * n + 2.0 * n * nbf) * elem;
           }
-        hipEvent_t e1 = prof_begin();
+        hipEvent_t e1 = prof_begin(K_PANEL);
         kern::launch_panel<T>(fr, ids, n_act, k, nb, ws0.p, ws1.p, panel.p,
                               fd.panel_off.as<long long>(), Dbuf.p, ipiv.as<int>(),
                               perm.as<int>(), fd.perm_off.as<long long>(),
                               status.as<int>(), st);
         prof_end(K_PANEL, e1, 0, 0);
-        e1 = prof_begin();
+        e1 = prof_begin(K_SWAP_JO);
         kern::launch_swap_JO<T>(fr, ids, n_act, fd.pCol.as<int2>(), fd.pCol_h[n_act], k,
                                 nb, ws0.p, ws1.p, Dbuf.p, ipiv.as<int>(),
                                 fd.panel_off.as<long long>(), fd.perm_off.as<long long>(),
                                 st);
         prof_end(K_SWAP_JO, e1, 0, 0);
-        e1 = prof_begin();
+        e1 = prof_begin(K_SWEEP_GEMM);
         kern::launch_sweep_gemm<T>(fr, ids, n_act, fd.pFull.as<int2>(), fd.pFull_h[n_act],
                                    k, nb, ws0.p, ws1.p, st);
         prof_end(K_SWEEP_GEMM, e1, sw_flops, sw_bytes);
-        e1 = prof_begin();
+        e1 = prof_begin(K_UPDATE_OJ);
         kern::launch_update_OJ<T>(fr, ids, n_act, fd.pCol.as<int2>(), fd.pCol_h[n_act], k,
                                   nb, ws0.p, ws1.p, Dbuf.p, fd.panel_off.as<long long>(),
                                   st);
         prof_end(K_UPDATE_OJ, e1, 0, 0);
       }
-      hipEvent_t e2 = prof_begin();
+      hipEvent_t e2 = prof_begin(K_STORE);
       kern::launch_store_factor<T>(fr, ids, fd.n, fd.pStore.as<int2>(), pStore[fd.n], ld,
                                    ws0.p, ws1.p, perm.as<int>(),
                                    fd.perm_off.as<long long>(), st);
@@ -656,7 +668,7 @@ void Handle::solve_layers(const LayerSet& set, int k) {
   // (layer set, width) into a HIP graph and replayed; the sequence holds no
   // memset or host work.  Event timing needs the launches one by one.
   (void)tile_plan(set, k);   // measured choices, if asked for, are taken here
-  const bool use_graph = !profile && !(opt.flags & HELM_FLAG_NO_GRAPHS);
+  const bool use_graph = !profile() && !(opt.flags & HELM_FLAG_NO_GRAPHS);
   if (use_graph) {
     GraphKey key{&set, k};
     auto it = graphs.find(key);
@@ -813,7 +825,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     if (D.n == 0) continue;
     hipEvent_t a = nullptr;
     if (D.nS > 0) {
-      a = prof_begin();
+      a = prof_begin(K_FWD_GATHER);
       kern::launch_fwd_gather<T>(fr, D.idsS.as<int>(), D.nS, D.pSB.as<int2>(), D.tSB, ld, k,
                                  st);
       prof_end(K_FWD_GATHER, a, 0, 3.0 * D.fs_s * kk * e);
@@ -821,14 +833,14 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     if (D.nL > 0) {
       const int* ids = D.idsL.as<int>();
       const SolveTask* tk = D.tasksL.as<SolveTask>();
-      a = prof_begin();
+      a = prof_begin(K_FWD_GEMM);
       launch_fwd<T>(D, fr, ld, k, scr, tp[d].fwd_bn);
       // factor block read once; pivots read, Z written, boundary updates
       // written and the children's updates of the boundary rows read
       prof_end(K_FWD_GEMM, a, 8.0 * D.fl_sbs * kk,
                D.fl_sbs * e + (2.0 * D.fl_s + D.fl_b + D.fs_b) * kk * e);
       if (D.tRF > 0) {
-        a = prof_begin();
+        a = prof_begin(K_FWD_REDUCE);
         kern::launch_fwd_reduce<T>(fr, ids, tk, D.nL, D.rF.as<int2>(), D.tRF, ld, k, scr, st);
         prof_end(K_FWD_REDUCE, a, 0, 0);
       }
@@ -839,13 +851,13 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     if (D.n == 0) continue;
     const int* ids = D.ids.as<int>();
     const SolveTask* tk = D.tasks.as<SolveTask>();
-    hipEvent_t a = prof_begin();
+    hipEvent_t a = prof_begin(K_BWD_GEMM);
     launch_bwd<T>(D, fr, ld, k, scr, tp[d].bwd_bn);
     // factor block read once; X(B) rows read, Z(S) read, X(S) written
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
     if (D.tRB > 0) {
-      a = prof_begin();
+      a = prof_begin(K_BWD_REDUCE);
       kern::launch_bwd_reduce<T>(fr, ids, tk, D.n, D.rB.as<int2>(), D.tRB, ld, k, scr, st);
       prof_end(K_BWD_REDUCE, a, 0, 0);
     }

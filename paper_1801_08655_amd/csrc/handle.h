@@ -142,12 +142,16 @@ struct Handle {
   template <typename T> void launch_bwd(const DepthList& D, const FrontDev* fr,
                                         const LayerDev* ld, int k, void* scr, int bn);
 
-  // kernel timing (HELM_FLAG_PROFILE)
-  bool profile = false;
+  // kernel timing (HELM_FLAG_PROFILE: every class; HELM_FLAG_PROFILE_FWD:
+  // the forward substitution GEMM only), one bit per KClass
+  unsigned profile_mask = 0;
+  void set_profile(int flags);
+  bool profile() const { return profile_mask != 0; }
   KStat kstats[K_NCLASS];
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> ev_free;
-  hipEvent_t prof_begin();
+  hipEvent_t record_event();
+  hipEvent_t prof_begin(int cls);
   void prof_end(int cls, hipEvent_t a, double flops, double bytes);
   void collect_profile();
 
