@@ -106,6 +106,29 @@ def test_interface_operators_match_oracle(homog):
     assert relative_error(ga, ref)[0] <= 1e-10
 
 
+def test_profile_flags_time_only_what_they_name(homog):
+    """HELM_FLAG_PROFILE times every substitution kernel class,
+    HELM_FLAG_PROFILE_FWD only the forward GEMM; timing never changes the
+    arithmetic (same solution, bit for bit, as an untimed solve)."""
+    import paper_1801_08655_amd as pt
+    wl, pb, _ = homog
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12)]
+    base = _solver(wl, "mixed").solve_points(srcs).cpu().numpy()
+    for flag, timed in ((pt._lib.HELM_FLAG_PROFILE, None),
+                        (pt._lib.HELM_FLAG_PROFILE_FWD, {"solve_fwd_gemm"})):
+        s = _solver(wl, "mixed", flags=flag)
+        s.kernel_stats(reset=True)
+        u = s.solve_points(srcs).cpu().numpy()
+        assert np.array_equal(u, base)
+        st = s.kernel_stats()
+        launched = {name for name, v in st.items() if v["launches"] > 0}
+        if timed is None:
+            assert {"solve_fwd_gemm", "solve_bwd_gemm"} <= launched
+        else:
+            assert launched == timed
+        assert st["solve_fwd_gemm"]["total_ms"] > 0 and st["solve_fwd_gemm"]["flops"] > 0
+
+
 def test_polarized_rhs_and_its_preconditioned_form_match_oracle(homog):
     """op 3: (f_down, f_up) of a volume source; op 4: P (f_down, f_up) from one
     folded sweep pair (the layer sources join the downward solves), against the
