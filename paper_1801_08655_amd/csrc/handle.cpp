@@ -466,7 +466,7 @@ void Handle::factorize_t() {
             sw_bytes += (2.0 * n * n + 2.0 * n * nbf) * elem;
           }
         hipEvent_t e1 = prof_begin(K_PANEL);
-        kern::launch_panel<T>(fr, ids, n_act, k, nb, ws0.p, ws1.p, panel.p,
+        kern::launch_panel<T>(fr, ids, n_act, smax - k, k, nb, ws0.p, ws1.p, panel.p,
                               fd.panel_off.as<long long>(), Dbuf.p, ipiv.as<int>(),
                               perm.as<int>(), fd.perm_off.as<long long>(),
                               status.as<int>(), st);

@@ -22,8 +22,8 @@ void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
                          const int2* tmap, int total, const LayerDev* layers,
                          void* ws0, void* ws1, const GridDev& g, hipStream_t st);
 template <typename T>
-void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
-                  int nb, void* ws0, void* ws1, void* panel,
+void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_rows,
+                  int k, int nb, void* ws0, void* ws1, void* panel,
                   const long long* panel_off, void* D, int* ipiv, int* perm,
                   const long long* perm_off, int* status, hipStream_t st);
 template <typename T>

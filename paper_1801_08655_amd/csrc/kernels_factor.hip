@@ -166,19 +166,25 @@ k_orig_entries(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // --------------------------------------------------------------------------
 // panel: LU with partial pivoting of rows [k, s) x columns [k, k+nbf) on a
 // copy, to choose the nbf pivot rows; then D = (pivoted diagonal block)^-1.
-// One 1024-thread workgroup per front.
+// One workgroup of NT threads per front.  The copy lives in LDS (PR rows at
+// most) when the launch's tallest panel fits, as every leaf front's does,
+// else (PR = 0) in the global panel buffer; only D, the pivots and the
+// permutation leave the kernel.
 // --------------------------------------------------------------------------
-constexpr int PANEL_THREADS = 1024;
 constexpr int NBMAX = 64;
 constexpr int PB = 8;   // column block of the panel LU
+template <typename T> constexpr int panel_lds_rows() { return sizeof(T) == 4 ? 192 : 64; }
 
-template <typename T>
-__global__ void __launch_bounds__(PANEL_THREADS)
+template <typename T, int NT, int PR>
+__global__ void __launch_bounds__(NT)
 k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
         int k, int nb, void* ws0, void* ws1, void* panel_base,
         const long long* __restrict__ panel_off, void* D_base, int* ipiv_base,
         int* perm_base, const long long* __restrict__ perm_off, int* status) {
   using C = C_t<T>;
+  constexpr int NW = NT / 64;
+  constexpr bool LDSP = PR > 0;
+  __shared__ C Ps[LDSP ? PR * NBMAX : 1];
   const int a = blockIdx.x;
   const FrontDev f = fronts[ids[a]];
   const int n = f.s + f.b;
@@ -186,19 +192,19 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   if (R <= 0) return;
   const int nbf = R < nb ? R : nb;
   const int t = threadIdx.x;
-  C* F = front_ptr<T>(ws0, ws1, f);
-  C* P = reinterpret_cast<C*>(panel_base) + panel_off[a];
+  const C* F = front_ptr<T>(ws0, ws1, f);
+  C* P = LDSP ? Ps : reinterpret_cast<C*>(panel_base) + panel_off[a];
   C* D = reinterpret_cast<C*>(D_base) + panel_off[a];
   int* ipiv = ipiv_base + perm_off[a];
   int* perm = perm_base + perm_off[a];
   if (k == 0)
-    for (int i = t; i < f.s; i += PANEL_THREADS) perm[i] = i;
-  for (long long e = t; e < (long long)R * nbf; e += PANEL_THREADS) {
+    for (int i = t; i < f.s; i += NT) perm[i] = i;
+  for (long long e = t; e < (long long)R * nbf; e += NT) {
     int r = e % R, c = e / R;
-    P[r + (long long)c * R] = F[(long long)(k + r) + (long long)(k + c) * n];
+    P[r + (long long)c * R] = ld(F + (long long)(k + r) + (long long)(k + c) * n);
   }
-  __shared__ double red_v[PANEL_THREADS / 64];
-  __shared__ int red_i[PANEL_THREADS / 64];
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
   __shared__ int piv_row;
   __syncthreads();
   // Blocked right-looking LU of the panel: columns in blocks of PB; inside
@@ -215,7 +221,7 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       // reproducible)
       double best = -1.0;
       int bi = R;
-      for (int r = c + t; r < R; r += PANEL_THREADS) {
+      for (int r = c + t; r < R; r += NT) {
         double v = cabs2(P[r + (long long)c * R]);
         if (v > best) { best = v; bi = r; }
       }
@@ -224,12 +230,14 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
         int oi = __shfl_down(bi, off);
         if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
       }
-      if ((t & 63) == 0) { red_v[t >> 6] = best; red_i[t >> 6] = bi; }
-      __syncthreads();
+      if (NW > 1) {
+        if ((t & 63) == 0) { red_v[t >> 6] = best; red_i[t >> 6] = bi; }
+        __syncthreads();
+      }
       if (t == 0) {
-        double bv = red_v[0];
-        int bidx = red_i[0];
-        for (int w = 1; w < PANEL_THREADS / 64; ++w)
+        double bv = NW > 1 ? red_v[0] : best;
+        int bidx = NW > 1 ? red_i[0] : bi;
+        for (int w = 1; w < NW; ++w)
           if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bidx)) {
             bv = red_v[w];
             bidx = red_i[w];
@@ -249,7 +257,7 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       __syncthreads();
       const int p = piv_row;
       if (p != c)
-        for (int cc = t; cc < nbf; cc += PANEL_THREADS) {
+        for (int cc = t; cc < nbf; cc += NT) {
           C x = P[c + (long long)cc * R];
           P[c + (long long)cc * R] = P[p + (long long)cc * R];
           P[p + (long long)cc * R] = x;
@@ -259,12 +267,12 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       if (cabs2(piv) == 0.0) piv = cmake<C>(1.0, 0.0);
       const C one = cmake<C>(1.0, 0.0);
       const C ipv = cdiv(one, piv);
-      for (int r = c + 1 + t; r < R; r += PANEL_THREADS)
+      for (int r = c + 1 + t; r < R; r += NT)
         P[r + (long long)c * R] = cmul(P[r + (long long)c * R], ipv);
       __syncthreads();
       // rank-1 update of the block's remaining columns
       const int rows = R - c - 1, cols = c1 - c - 1;
-      for (long long e = t; e < (long long)rows * cols; e += PANEL_THREADS) {
+      for (long long e = t; e < (long long)rows * cols; e += NT) {
         int r = c + 1 + (int)(e % rows), cc = c + 1 + (int)(e / rows);
         C& x = P[r + (long long)cc * R];
         cfms(x, P[r + (long long)c * R], P[c + (long long)cc * R]);
@@ -274,7 +282,7 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     if (c1 >= nbf) break;
     const int W = nbf - c1, bw = c1 - c0;
     // block rows of the trailing columns: U12 = L11^-1 A12 (unit lower)
-    for (int cc = t; cc < W; cc += PANEL_THREADS) {
+    for (int cc = t; cc < W; cc += NT) {
       const long long col = (long long)(c1 + cc) * R;
       for (int i = 0; i < bw; ++i) {
         C x = P[c0 + i + col];
@@ -285,7 +293,7 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     }
     __syncthreads();
     // rank-bw update of the trailing columns below the block
-    for (int r = c1 + t; r < R; r += PANEL_THREADS) {
+    for (int r = c1 + t; r < R; r += NT) {
       C l[PB];
 #pragma unroll
       for (int j = 0; j < PB; ++j)
@@ -301,33 +309,57 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     }
     __syncthreads();
   }
-  // D = U^-1 L^-1 of the leading nbf x nbf block, one column per thread
-  __shared__ C LU[NBMAX][NBMAX + 1];
-  for (int e = t; e < nbf * nbf; e += PANEL_THREADS) {
+  // D = U^-1 L^-1 of the leading nbf x nbf block, in LDS: X = L^-1 by
+  // eliminating below each unit pivot, then D = U^-1 X from the last row up.
+  // Every step updates all entries it touches in parallel.
+  // (the factors are read in place when the panel is in LDS)
+  __shared__ C LUs[LDSP ? 1 : NBMAX][LDSP ? 1 : NBMAX + 1];
+  __shared__ C X[NBMAX][NBMAX + 1];
+  __shared__ C uinv[NBMAX];
+  auto LU = [&](int r, int c) -> C { return LDSP ? P[r + c * R] : LUs[r][c]; };
+  for (int e = t; e < nbf * nbf; e += NT) {
     int r = e % nbf, c = e / nbf;
-    LU[r][c] = P[r + (long long)c * R];
+    if (!LDSP) LUs[r][c] = P[r + (long long)c * R];
+    X[r][c] = cmake<C>(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   if (t < nbf) {
-    const int j = t;
-    // forward: L y = e_j (unit lower), y stored in D[:, j]
-    for (int i = 0; i < nbf; ++i) {
-      C y = cmake<C>(i == j ? 1.0 : 0.0, 0.0);
-      for (int q = 0; q < i; ++q) cfms(y, LU[i][q], D[q + j * nb]);
-      D[i + j * nb] = y;
+    C u = LU(t, t);
+    if (cabs2(u) == 0.0) u = cmake<C>(1.0, 0.0);
+    uinv[t] = cdiv(cmake<C>(1.0, 0.0), u);
+  }
+  __syncthreads();
+  // X[i][j] -= L[i][q] X[q][j] for i > q, j <= q
+  for (int q = 0; q + 1 < nbf; ++q) {
+    const int rows = nbf - 1 - q, cols = q + 1;
+    for (int e = t; e < rows * cols; e += NT) {
+      const int i = q + 1 + e % rows, j = e / rows;
+      cfms(X[i][j], LU(i, q), X[q][j]);
     }
-    // backward: U x = y
-    for (int i = nbf - 1; i >= 0; --i) {
-      C x = D[i + j * nb];
-      for (int q = i + 1; q < nbf; ++q) cfms(x, LU[i][q], D[q + j * nb]);
-      D[i + j * nb] = cdiv(x, LU[i][i]);
+    __syncthreads();
+  }
+  // X[i][j] -= U[i][q] / U[q][q] X[q][j] for i < q; rows scaled at the end
+  for (int q = nbf - 1; q > 0; --q) {
+    for (int e = t; e < q * nbf; e += NT) {
+      const int i = e % q, j = e / q;
+      cfms(X[i][j], cmul(LU(i, q), uinv[q]), X[q][j]);
     }
+    __syncthreads();
+  }
+  for (int e = t; e < nbf * nbf; e += NT) {
+    int r = e % nbf, c = e / nbf;
+    st(D + r + c * nb, cmul(X[r][c], uinv[r]));
   }
 }
 
 // --------------------------------------------------------------------------
 // apply the nbf row swaps to every column, then rows J <- D * rows J for the
 // columns outside J.  One workgroup per 64-column tile.
+// The swaps are composed first (one wave, in registers): row k + jj of J
+// ends up holding old row srcJ[jj], and each row outside J that a swap
+// touches (at most nbf of them) holds old row srcO[i].  Every new value is
+// then one independent load, so the column tile is read once, in parallel,
+// instead of through nbf dependent swaps per column.
 // --------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -346,37 +378,92 @@ k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int* ipiv = ipiv_base + perm_off[a];
   const C* D = reinterpret_cast<const C*>(D_base) + panel_off[a];
   const int t = threadIdx.x;
-  if (t < GT && c0 + t < n) {
-    C* col = F + (long long)(c0 + t) * n;
+  __shared__ int srcJ[NBMAX], rowO[NBMAX], srcO[NBMAX];
+  __shared__ int nO;
+  __shared__ C V[NBMAX][GT + 1];
+  __shared__ C DsT[NBMAX][NBMAX + 1];  // DsT[q][r] = D(r, q)
+  if (t < 64) {
+    // lane i holds srcJ[i] and outside entry i (row ro, source so)
+    int vJ = k + t, ro = -1, so = 0, cnt = 0;
+    const int piv = ld(ipiv + (t < nbf ? t : 0));
     for (int jj = 0; jj < nbf; ++jj) {
-      int r2 = k + ipiv[jj];
-      if (r2 != k + jj) {
-        C x = col[k + jj];
-        col[k + jj] = col[r2];
-        col[r2] = x;
+      const int r2 = k + __builtin_amdgcn_readlane(piv, jj);
+      const int cur = __builtin_amdgcn_readlane(vJ, jj);
+      if (r2 < k + nbf) {
+        const int other = __builtin_amdgcn_readlane(vJ, r2 - k);
+        if (t == jj) vJ = other;
+        if (t == r2 - k) vJ = cur;
+      } else {
+        const unsigned long long hit = __ballot(ro == r2);
+        if (hit) {
+          const int i = __ffsll((long long)hit) - 1;
+          const int other = __builtin_amdgcn_readlane(so, i);
+          if (t == jj) vJ = other;
+          if (t == i) so = cur;
+        } else {
+          if (t == jj) vJ = r2;
+          if (t == cnt) { ro = r2; so = cur; }
+          ++cnt;
+        }
       }
     }
+    if (t < nbf) srcJ[t] = vJ;
+    if (t < cnt) { rowO[t] = ro; srcO[t] = so; }
+    if (t == 0) nO = cnt;
   }
   __syncthreads();
-  __shared__ C V[NBMAX][GT + 1];
-  __shared__ C Ds[NBMAX][NBMAX + 1];
+  const int no = nO;
+  // every read of the tile before any write
+  constexpr int WPT = NBMAX * GT / 256;
+  C w[WPT];
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    const int e = t + 256 * i, r = e / GT, gc = c0 + e % GT;
+    const bool ok = r < no && gc < n;
+    w[i] = ld_or_zero(ok, F + (ok ? (long long)srcO[r] + (long long)gc * n : 0));
+  }
   for (int e = t; e < nbf * GT; e += 256) {
-    int r = e % nbf, c = e / nbf;
-    V[r][c] = (c0 + c < n) ? F[(long long)(k + r) + (long long)(c0 + c) * n] : czero<C>();
+    const int r = e % nbf, c = e / nbf, gc = c0 + c;
+    V[r][c] = ld_or_zero(gc < n, F + (gc < n ? (long long)srcJ[r] + (long long)gc * n : 0));
   }
   for (int e = t; e < nbf * nbf; e += 256) {
-    int r = e % nbf, c = e / nbf;
-    Ds[r][c] = D[r + c * nb];
+    const int r = e % nbf, q = e / nbf;
+    DsT[q][r] = ld(D + r + q * nb);
   }
   __syncthreads();
-  for (int e = t; e < nbf * GT; e += 256) {
-    int r = e % nbf, c = e / nbf;
-    int gc = c0 + c;
-    if (gc >= n || (gc >= k && gc < k + nbf)) continue;
-    C acc = czero<C>();
-    for (int q = 0; q < nbf; ++q) cfma(acc, Ds[r][q], V[q][c]);
-    F[(long long)(k + r) + (long long)gc * n] = acc;
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    const int e = t + 256 * i, r = e / GT, gc = c0 + e % GT;
+    if (r < no && gc < n) st(F + (long long)rowO[r] + (long long)gc * n, w[i]);
   }
+  // rows J of the tile: thread (rg, cg) owns rows rg + 16 i and columns
+  // cg + 16 j (i, j < 4), so each LDS value read feeds four products
+  const int rg = t & 15, cg = t >> 4;
+  C acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = czero<C>();
+  for (int q = 0; q < nbf; ++q) {
+    C dv[4], vv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dv[i] = DsT[q][rg + 16 * i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vv[j] = V[q][cg + 16 * j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cfma(acc[i][j], dv[i], vv[j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rg + 16 * i, c = cg + 16 * j, gc = c0 + c;
+      if (r >= nbf || gc >= n) continue;
+      const bool inJ = gc >= k && gc < k + nbf;
+      st(F + (long long)(k + r) + (long long)gc * n, inJ ? V[r][c] : acc[i][j]);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -408,13 +495,29 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> qv{F + (long long)k * n, 1, (long long)n, n, nbf};
   WaveAcc<T, 64> acc;
   gemm_tile<T, 64, false, true>(sm, acc, pv, qv, j0, i0, 0, nbf);
-  for_each_acc<T, 64, 64>(acc, [&](int r, int c, C z) {
-    const int gi = i0 + c, gj = j0 + r;
-    if (gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf)) {
-      C& e = F[(long long)gi + (long long)gj * n];
-      e = csub(e, z);
+  // F(i, j) -= acc: every entry of the lane is loaded before the first store
+  // (one latency for the group instead of a load-store chain per entry)
+  using O = LaneOut<T, 64, 64>;
+  const O o;
+  auto outside = [&](int gi, int gj) {
+    return gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf);
+  };
+  C cv[O::NR][O::NC];
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+    for (int j = 0; j < O::NC; ++j) {
+      const int gi = i0 + o.c[j], gj = j0 + o.r[i];
+      cv[i][j] = ld_or_zero(outside(gi, gj), F + (long long)gi + (long long)gj * n);
     }
-  });
+#pragma unroll
+  for (int i = 0; i < O::NR; ++i)
+#pragma unroll
+    for (int j = 0; j < O::NC; ++j) {
+      const int gi = i0 + o.c[j], gj = j0 + o.r[i];
+      if (outside(gi, gj))
+        st(F + (long long)gi + (long long)gj * n, csub(cv[i][j], acc_at(acc, i, j)));
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -448,20 +551,33 @@ k_update_OJ(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     Ds[r][c] = D[r + c * nb];
   }
   __syncthreads();
-  for (int e = t; e < GT * nbf; e += 256) {
-    int r = e % GT, c = e / GT;
-    int gr = r0 + r;
-    if (gr >= n) continue;
-    C out;
-    if (gr >= k && gr < k + nbf) {
-      out = Ds[gr - k][c];
-    } else {
-      C acc = czero<C>();
-      for (int q = 0; q < nbf; ++q) cfma(acc, V[r][q], Ds[q][c]);
-      out = cneg(acc);
-    }
-    F[(long long)gr + (long long)(k + c) * n] = out;
+  // thread (rg, cg) owns rows rg + 16 i and columns cg + 16 j (i, j < 4)
+  const int rg = t & 15, cg = t >> 4;
+  C acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = czero<C>();
+  for (int q = 0; q < nbf; ++q) {
+    C vv[4], dv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) vv[i] = V[rg + 16 * i][q];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dv[j] = Ds[q][cg + 16 * j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cfma(acc[i][j], vv[i], dv[j]);
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rg + 16 * i, c = cg + 16 * j, gr = r0 + r;
+      if (gr >= n || c >= nbf) continue;
+      const bool inJ = gr >= k && gr < k + nbf;
+      st(F + (long long)gr + (long long)(k + c) * n, inJ ? Ds[gr - k][c] : cneg(acc[i][j]));
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -517,14 +633,21 @@ void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
                      n_ids, tmap, layers, ws0, ws1, g);
 }
 template <typename T>
-void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int k,
-                  int nb, void* ws0, void* ws1, void* panel,
+void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_rows,
+                  int k, int nb, void* ws0, void* ws1, void* panel,
                   const long long* panel_off, void* D, int* ipiv, int* perm,
                   const long long* perm_off, int* status, hipStream_t st) {
   if (n_active <= 0) return;
-  hipLaunchKernelGGL(k_panel<T>, dim3(n_active), dim3(PANEL_THREADS), 0, st, fronts,
-                     ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm,
-                     perm_off, status);
+  // threads and panel home from the tallest panel of the launch
+#define HELM_PANEL(NT, PR)                                                          \
+  hipLaunchKernelGGL((k_panel<T, NT, PR>), dim3(n_active), dim3(NT), 0, st,        \
+                     fronts, ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm, \
+                     perm_off, status)
+  if (max_rows <= 64) HELM_PANEL(64, 64);
+  else if (max_rows <= panel_lds_rows<T>()) HELM_PANEL(256, panel_lds_rows<T>());
+  else if (max_rows <= 1024) HELM_PANEL(256, 0);
+  else HELM_PANEL(1024, 0);
+#undef HELM_PANEL
 }
 template <typename T>
 void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
@@ -570,7 +693,7 @@ void launch_store_factor(const FrontDev* fronts, const int* ids, int n_ids,
   template void launch_orig_entries<T>(const FrontDev*, const int*, int,          \
                                        const int2*, int, const LayerDev*, void*,    \
                                        void*, const GridDev&, hipStream_t);        \
-  template void launch_panel<T>(const FrontDev*, const int*, int, int, int, void*, \
+  template void launch_panel<T>(const FrontDev*, const int*, int, int, int, int, void*, \
                                 void*, void*, const long long*, void*, int*, int*, \
                                 const long long*, int*, hipStream_t);              \
   template void launch_swap_JO<T>(const FrontDev*, const int*, int, const int2*,    \

@@ -109,32 +109,6 @@ template <typename T, int BM, int BN> constexpr int gemm_waves() {
   return (sizeof(T) == 4 && !(BM == 64 && BN == 64)) ? 4 : 1;
 }
 
-// Output rows and columns (tile offsets) of this lane's accumulators, in the
-// order of WaveAcc: row i = 4 bm + v, column j = bn.
-template <typename T, int BM, int BN> struct LaneOut {
-  using G = WaveGrid<BM, BN>;
-  static constexpr int NR = G::MB * 4, NC = G::NB;
-  int r[NR], c[NC];
-  __device__ __forceinline__ LaneOut() {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave / G::WC, wc = wave % G::WC;
-#pragma unroll
-    for (int bm = 0; bm < G::MB; ++bm)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) r[bm * 4 + v] = wr * G::RW + bm * 16 + Mfma<T>::row(lane, v);
-#pragma unroll
-    for (int bn = 0; bn < G::NB; ++bn) c[bn] = wc * G::CW + bn * 16 + (lane & 15);
-  }
-};
-
-template <typename T, int BM, int BN>
-__device__ __forceinline__ C_t<T> acc_at(const WaveAcc<T, BM, BN>& acc, int i, int j) {
-  C_t<T> z;
-  z.x = acc.re[i / 4][j][i % 4];
-  z.y = acc.im[i / 4][j][i % 4];
-  return z;
-}
-
 // Forward GEMM epilogue of an unsplit front: pivot rows to Z, boundary rows
 // to the update buffer with the children's updates added.  The child rows of
 // all of this lane's outputs are loaded first, then the child values, then

@@ -12,7 +12,9 @@
 // hold at most `leaf` unknowns.
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <numeric>
+#include <thread>
 
 #include "helm_internal.h"
 
@@ -275,7 +277,37 @@ void build_geometry(Geometry& G, const helm_grid& g, double omega, int pml,
     G.lbzh[l].resize(P.t + 1);
     for (int q = 0; q < P.t; ++q) G.lbz[l][q] = beta_of(sig(P.lo + q), omega);
     for (int q = 0; q <= P.t; ++q) G.lbzh[l][q] = beta_of(sig(P.lo + q - 0.5), omega);
-    build_layer_plan(P, g.nx, g.ny, leaf);
+  }
+
+  // The dissection depends only on the layer's extent (nx, ny, t): build one
+  // plan per distinct thickness, on threads of their own, and copy it into
+  // the other layers of that thickness.
+  std::vector<int> first(n_layers, -1), owners;
+  for (int l = 0; l < n_layers; ++l) {
+    for (int o : owners)
+      if (G.layers[o].t == G.layers[l].t) { first[l] = o; break; }
+    if (first[l] < 0) { first[l] = l; owners.push_back(l); }
+  }
+  std::vector<std::exception_ptr> err(owners.size());
+  std::vector<std::thread> pool;
+  for (size_t i = 0; i < owners.size(); ++i)
+    pool.emplace_back([&, i] {
+      try {
+        build_layer_plan(G.layers[owners[i]], g.nx, g.ny, leaf);
+      } catch (...) {
+        err[i] = std::current_exception();
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  for (int l = 0; l < n_layers; ++l) {
+    if (first[l] == l) continue;
+    LayerPlan& P = G.layers[l];
+    const LayerPlan keep = P;
+    P = G.layers[first[l]];
+    P.index = keep.index; P.s = keep.s; P.e = keep.e;
+    P.lo = keep.lo; P.hi = keep.hi;
   }
 }
 
