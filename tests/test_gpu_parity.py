@@ -326,3 +326,24 @@ def test_per_rhs_info():
         else:
             assert info["rhs_est_error"] == [0.0, 0.0, 0.0]
         s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_tall_panels_single_layer_residual(precision, tol):
+    """L = 1 on 40^3: the top separator has 1600 rows, so as the elimination
+    advances its panels take every panel kernel shape (more than 1024 rows,
+    up to 1024, up to 192 and up to 64, global and LDS homes).  The local
+    solve is checked by its residual under the oracle's own assembly."""
+    from helm_inputs import smooth_random_model, omega_for_ppw
+    import paper_1801_08655_amd as pt
+    n, p = 40, 5
+    h = 1.0 / (n - 1)
+    m = smooth_random_model((n, n, n), 0.25, 2.0, 0.75, 1.25, 8)
+    om = omega_for_ppw(0.75, h, 10.0)
+    pb = Problem(m, h, om, p, 25.0)
+    s = pt.Solver(m, h, om, p, 1, precision=precision, pml_C=25.0)
+    r = _rand((2, n, n, n), 41)
+    w = s.layer_solve(0, torch.from_numpy(r).cuda()).cpu().numpy()
+    R = r.reshape(2, -1).T
+    res = R - pb.operator() @ w.reshape(2, -1).T
+    assert (np.linalg.norm(res, axis=0) / np.linalg.norm(R, axis=0)).max() <= tol
