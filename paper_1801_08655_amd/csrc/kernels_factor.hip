@@ -473,7 +473,7 @@ k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // contiguous (row) dimension of the column-major front.
 // --------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
 k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              int n_active, const int2* __restrict__ tmap, int k, int nb,
              void* ws0, void* ws1) {
