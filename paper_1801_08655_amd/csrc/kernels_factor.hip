@@ -69,19 +69,28 @@ k_extend_add(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       sc[slot] = c.s;
     }
   }
-  const int i = t % GT;
-  for (int jj = t / GT; jj < GT; jj += 256 / GT) {
-    const int gi = i0 + i, gj = j0 + jj;
-    if (gi >= n || gj >= n) continue;
-    C v = czero<C>();
+  // the lane's 16 entries are all gathered before the first store
+  constexpr int NJ = GT / (256 / GT);
+  const int i = t % GT, gi = i0 + i;
+  C v[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int jj = t / GT + u * (256 / GT), gj = j0 + jj;
+    C acc = czero<C>();
 #pragma unroll
     for (int slot = 0; slot < 2; ++slot) {
-      int ri = inv_r[slot][i], cj = inv_c[slot][jj];
-      if (S[slot] && ri >= 0 && cj >= 0)
-        v = cadd(v, S[slot][(long long)(sc[slot] + ri) +
-                            (long long)(sc[slot] + cj) * ldc[slot]]);
+      const int ri = inv_r[slot][i], cj = inv_c[slot][jj];
+      const bool hit = gi < n && gj < n && S[slot] && ri >= 0 && cj >= 0;
+      acc = cadd(acc, ld_or_zero(hit, S[slot] + (hit ? (long long)(sc[slot] + ri) +
+                                                         (long long)(sc[slot] + cj) * ldc[slot]
+                                                     : 0)));
     }
-    F[(long long)gi + (long long)gj * n] = v;
+    v[u] = acc;
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int gj = j0 + t / GT + u * (256 / GT);
+    if (gi < n && gj < n) st(F + (long long)gi + (long long)gj * n, v[u]);
   }
 }
 
