@@ -20,40 +20,74 @@ namespace kern {
 
 namespace {
 
+// Volume <-> layer copies of the bulk planes [s, e], as tiles of 64 nodes x
+// 64 columns staged in LDS: f and u hold each column contiguously over the
+// nodes, X holds each node's k values contiguously, so both sides are read
+// or written along their contiguous direction.  Grid: (node tiles, column
+// tiles); wave w of the block handles tile rows w, w + 4, ...
+constexpr int VT = 64;
+
 template <typename T>
-__global__ void k_scatter_source(LayerDev L, const double2* __restrict__ f,
-                                 int nx, int ny, long long N, int k) {
+__global__ void __launch_bounds__(256)
+k_scatter_source(LayerDev L, const double2* __restrict__ f, int nx, int ny, long long N, int k) {
   using C = C_t<T>;
+  __shared__ C tile[VT][VT + 1];   // [node][column]
   const long long plane = (long long)nx * ny;
   const long long nb = plane * (L.e - L.s + 1);
-  const long long total = nb * k;
+  const long long n0 = (long long)blockIdx.x * VT;
+  const int c0 = blockIdx.y * VT, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   C* X = reinterpret_cast<C*>(L.X);
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long sp = e % nb;
-    const int c = (int)(e / nb);
-    const long long g = sp + plane * L.s;          // global index
-    const long long loc = sp + plane * (L.s - L.lo);
-    X[(long long)L.nat2nd[loc] * k + c] = from_d2<C>(f[(long long)c * N + g]);
+  {
+    const long long sp = n0 + lane;
+#pragma unroll
+    for (int j = 0; j < VT / 4; ++j) {
+      const int c = w + 4 * j;
+      const bool ok = sp < nb && c0 + c < k;
+      tile[lane][c] = from_d2<C>(ld_or_zero(ok, f + (ok ? (long long)(c0 + c) * N + sp + plane * L.s : 0)));
+    }
   }
+  __syncthreads();
+  long long dst[VT / 4];
+#pragma unroll
+  for (int j = 0; j < VT / 4; ++j) {
+    const long long sp = n0 + w + 4 * j;
+    dst[j] = sp < nb ? (long long)ld(L.nat2nd + sp + plane * (L.s - L.lo)) * k : -1;
+  }
+  if (c0 + lane < k)
+#pragma unroll
+    for (int j = 0; j < VT / 4; ++j)
+      if (dst[j] >= 0) st(X + dst[j] + c0 + lane, tile[w + 4 * j][lane]);
 }
 
 template <typename T>
-__global__ void k_gather_volume(LayerDev L, double2* __restrict__ u, int nx,
-                                int ny, long long N, int k) {
+__global__ void __launch_bounds__(256)
+k_gather_volume(LayerDev L, double2* __restrict__ u, int nx, int ny, long long N, int k) {
   using C = C_t<T>;
+  __shared__ C tile[VT][VT + 1];   // [node][column]
   const long long plane = (long long)nx * ny;
   const long long nb = plane * (L.e - L.s + 1);
-  const long long total = nb * k;
+  const long long n0 = (long long)blockIdx.x * VT;
+  const int c0 = blockIdx.y * VT, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const C* X = reinterpret_cast<const C*>(L.X);
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long sp = e % nb;
-    const int c = (int)(e / nb);
-    const long long g = sp + plane * L.s;
-    const long long loc = sp + plane * (L.s - L.lo);
-    u[(long long)c * N + g] = to_d2(X[(long long)L.nat2nd[loc] * k + c]);
+  long long src[VT / 4];
+#pragma unroll
+  for (int j = 0; j < VT / 4; ++j) {
+    const long long sp = n0 + w + 4 * j;
+    src[j] = sp < nb ? (long long)ld(L.nat2nd + sp + plane * (L.s - L.lo)) * k : -1;
   }
+#pragma unroll
+  for (int j = 0; j < VT / 4; ++j) {
+    const bool ok = src[j] >= 0 && c0 + lane < k;
+    tile[w + 4 * j][lane] = ld_or_zero(ok, X + (ok ? src[j] + c0 + lane : 0));
+  }
+  __syncthreads();
+  const long long sp = n0 + lane;
+  if (sp < nb)
+#pragma unroll
+    for (int j = 0; j < VT / 4; ++j) {
+      const int c = w + 4 * j;
+      if (c0 + c < k) u[(long long)(c0 + c) * N + sp + plane * L.s] = to_d2(tile[lane][c]);
+    }
 }
 
 // whole extended layer, natural order <-> ND order (inspection entry point)
@@ -342,16 +376,18 @@ inline int grid_for(long long n, int block = 256) {
 template <typename T>
 void launch_scatter_source(const LayerDev& L, const double2* f, int nx, int ny,
                            long long N, int k, hipStream_t st) {
-  long long n = (long long)nx * ny * (L.e - L.s + 1) * k;
-  hipLaunchKernelGGL(k_scatter_source<T>, dim3(grid_for(n)), dim3(256), 0, st, L, f,
-                     nx, ny, N, k);
+  const long long nb = (long long)nx * ny * (L.e - L.s + 1);
+  if (nb <= 0 || k <= 0) return;
+  const dim3 grid((unsigned)((nb + VT - 1) / VT), (unsigned)((k + VT - 1) / VT));
+  hipLaunchKernelGGL(k_scatter_source<T>, grid, dim3(256), 0, st, L, f, nx, ny, N, k);
 }
 template <typename T>
 void launch_gather_volume(const LayerDev& L, double2* u, int nx, int ny,
                           long long N, int k, hipStream_t st) {
-  long long n = (long long)nx * ny * (L.e - L.s + 1) * k;
-  hipLaunchKernelGGL(k_gather_volume<T>, dim3(grid_for(n)), dim3(256), 0, st, L, u,
-                     nx, ny, N, k);
+  const long long nb = (long long)nx * ny * (L.e - L.s + 1);
+  if (nb <= 0 || k <= 0) return;
+  const dim3 grid((unsigned)((nb + VT - 1) / VT), (unsigned)((k + VT - 1) / VT));
+  hipLaunchKernelGGL(k_gather_volume<T>, grid, dim3(256), 0, st, L, u, nx, ny, N, k);
 }
 template <typename T>
 void launch_local_to_X(const LayerDev& L, const double2* r, int k, hipStream_t st) {
