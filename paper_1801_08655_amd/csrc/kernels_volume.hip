@@ -26,6 +26,7 @@ namespace {
 // or written along their contiguous direction.  Grid: (node tiles, column
 // tiles); wave w of the block handles tile rows w, w + 4, ...
 constexpr int VT = 64;
+constexpr int RESID_COLS = 8;   // columns per block row of k_residual
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -271,37 +272,39 @@ __global__ void k_add(double2* __restrict__ y, const double2* __restrict__ x,
 
 // FP64 residual r = f - H u on the global grid (volumes RHS-major); f may be
 // null (then r = H u).  Same operator as the local assembly.
-__global__ void k_residual(GridDev g, const double2* __restrict__ f,
-                           const double2* __restrict__ u, double2* __restrict__ r,
-                           int k) {
+__global__ void __launch_bounds__(256)
+k_residual(GridDev g, const double2* __restrict__ f, const double2* __restrict__ u,
+           double2* __restrict__ r, int k) {
+  // one node per thread and RESID_COLS columns per block row: the node's
+  // stencil coefficients are formed once for all of its columns
   const long long N = (long long)g.nx * g.ny * g.nz;
-  const long long total = N * k;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N) return;
   const double ih2 = 1.0 / (g.h * g.h);
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long idx = e % N;
-    const int x = (int)(idx % g.nx);
-    const int y = (int)((idx / g.nx) % g.ny);
-    const int z = (int)(idx / ((long long)g.nx * g.ny));
-    const double2* uc = u + (e - idx);
-    const double2 bx = g.bx[x], by = g.by[y], bz = g.bz[z];
-    auto mul = [](double2 a, double2 b) {
-      return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-    };
-    const double2 bxy = mul(bx, by), bxz = mul(bx, bz), byz = mul(by, bz);
-    double2 cp[6];
-    cp[0] = cdiv(g.bxh[x], byz);
-    cp[1] = cdiv(g.bxh[x + 1], byz);
-    cp[2] = cdiv(g.byh[y], bxz);
-    cp[3] = cdiv(g.byh[y + 1], bxz);
-    cp[4] = cdiv(g.bzh[z], bxy);
-    cp[5] = cdiv(g.bzh[z + 1], bxy);
+  const int x = (int)(idx % g.nx);
+  const int y = (int)((idx / g.nx) % g.ny);
+  const int z = (int)(idx / ((long long)g.nx * g.ny));
+  const double2 bx = g.bx[x], by = g.by[y], bz = g.bz[z];
+  auto mul = [](double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  };
+  const double2 bxy = mul(bx, by), bxz = mul(bx, bz), byz = mul(by, bz);
+  double2 cp[6];
+  cp[0] = cdiv(g.bxh[x], byz);
+  cp[1] = cdiv(g.bxh[x + 1], byz);
+  cp[2] = cdiv(g.byh[y], bxz);
+  cp[3] = cdiv(g.byh[y + 1], bxz);
+  cp[4] = cdiv(g.bzh[z], bxy);
+  cp[5] = cdiv(g.bzh[z + 1], bxy);
+  const double2 dg = cdiv(make_double2(g.omega * g.omega * g.m[idx], 0.0), mul(bxy, bz));
+  const long long st[6] = {-1, 1, -(long long)g.nx, (long long)g.nx,
+                           -(long long)g.nx * g.ny, (long long)g.nx * g.ny};
+  const bool ok[6] = {x > 0, x < g.nx - 1, y > 0, y < g.ny - 1, z > 0, z < g.nz - 1};
+  const int cend = min(k, (int)(blockIdx.y + 1) * RESID_COLS);
+  for (int c = blockIdx.y * RESID_COLS; c < cend; ++c) {
+    const double2* uc = u + (long long)c * N;
     const double2 u0 = uc[idx];
-    double2 dg = cdiv(make_double2(g.omega * g.omega * g.m[idx], 0.0), mul(bxy, bz));
     double2 acc = mul(dg, u0);
-    const long long st[6] = {-1, 1, -(long long)g.nx, (long long)g.nx,
-                             -(long long)g.nx * g.ny, (long long)g.nx * g.ny};
-    const bool ok[6] = {x > 0, x < g.nx - 1, y > 0, y < g.ny - 1, z > 0, z < g.nz - 1};
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       double2 nb = ok[q] ? uc[idx + st[q]] : make_double2(0.0, 0.0);
@@ -310,12 +313,14 @@ __global__ void k_residual(GridDev g, const double2* __restrict__ f,
       acc.x += t.x;
       acc.y += t.y;
     }
+    const long long e = (long long)c * N + idx;
     double2 out;
     if (f) out = make_double2(f[e].x - acc.x, f[e].y - acc.y);
     else out = acc;
     r[e] = out;
   }
 }
+
 
 // point sources: f[c * N + node[c]] = amp[c] / h^3 (f zeroed before)
 __global__ void k_point_sources(double2* __restrict__ f, const long long* __restrict__ node,
@@ -437,8 +442,10 @@ void launch_add(double2* y, const double2* x, const double2* z, long long n,
 }
 void launch_residual(const GridDev& g, const double2* f, const double2* u,
                      double2* r, int k, hipStream_t st) {
-  long long n = (long long)g.nx * g.ny * g.nz * k;
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(256), 0, st, g, f, u, r, k);
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  if (N <= 0 || k <= 0) return;
+  const dim3 grid((unsigned)((N + 255) / 256), (unsigned)((k + RESID_COLS - 1) / RESID_COLS));
+  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, st, g, f, u, r, k);
 }
 void launch_point_sources(double2* f, const long long* node, const double2* amp,
                           double inv_h3, long long N, int k, hipStream_t st) {
