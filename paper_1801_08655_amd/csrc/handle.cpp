@@ -123,7 +123,7 @@ hipEvent_t Handle::prof_begin(int cls) {
   return record_event();
 }
 
-hipEvent_t Handle::record_event() {
+hipEvent_t Handle::take_event() {
   hipEvent_t e;
   if (!ev_free.empty()) {
     e = ev_free.back();
@@ -133,6 +133,11 @@ hipEvent_t Handle::record_event() {
     // between the kernels being timed
     HELM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
+  return e;
+}
+
+hipEvent_t Handle::record_event() {
+  hipEvent_t e = take_event();
   HELM_HIP(hipEventRecord(e, st));
   return e;
 }
@@ -701,13 +706,13 @@ static int width_bn(int k) { return k <= 2 ? 1 : mfma_bn(k); }
 // vector path).
 template <typename T>
 void Handle::launch_fwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
-                        void* scr, int bn) {
+                        void* scr, int bn, hipEvent_t t0, hipEvent_t t1) {
   if (bn == 1)
     kern::launch_fwd_gemv<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
-                             D.pF.as<int2>(), D.tF, ld, k, scr, st);
+                             D.pF.as<int2>(), D.tF, ld, k, scr, st, t0, t1);
   else
     kern::launch_fwd_gemm<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
-                             D.pF.as<int2>(), D.tF, ld, k, scr, bn, st);
+                             D.pF.as<int2>(), D.tF, ld, k, scr, bn, st, t0, t1);
 }
 template <typename T>
 void Handle::launch_bwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
@@ -833,12 +838,19 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     if (D.nL > 0) {
       const int* ids = D.idsL.as<int>();
       const SolveTask* tk = D.tasksL.as<SolveTask>();
-      a = prof_begin(K_FWD_GEMM);
-      launch_fwd<T>(D, fr, ld, k, scr, tp[d].fwd_bn);
+      // timed by the launch itself: its start and stop, no event commands
+      // between it and its neighbours
+      hipEvent_t t0 = nullptr, t1 = nullptr;
+      if (timed(K_FWD_GEMM)) {
+        t0 = take_event();
+        t1 = take_event();
+      }
+      launch_fwd<T>(D, fr, ld, k, scr, tp[d].fwd_bn, t0, t1);
       // factor block read once; pivots read, Z written, boundary updates
       // written and the children's updates of the boundary rows read
-      prof_end(K_FWD_GEMM, a, 8.0 * D.fl_sbs * kk,
-               D.fl_sbs * e + (2.0 * D.fl_s + D.fl_b + D.fs_b) * kk * e);
+      if (t0)
+        pending.push_back(PendingEvent{K_FWD_GEMM, t0, t1, 8.0 * D.fl_sbs * kk,
+                                       D.fl_sbs * e + (2.0 * D.fl_s + D.fl_b + D.fs_b) * kk * e});
       if (D.tRF > 0) {
         a = prof_begin(K_FWD_REDUCE);
         kern::launch_fwd_reduce<T>(fr, ids, tk, D.nL, D.rF.as<int2>(), D.tRF, ld, k, scr, st);

@@ -138,7 +138,8 @@ struct Handle {
   template <typename T> void autotune_t(const LayerSet& set, int k,
                                         std::vector<TileChoice>& plan);
   template <typename T> void launch_fwd(const DepthList& D, const FrontDev* fr,
-                                        const LayerDev* ld, int k, void* scr, int bn);
+                                        const LayerDev* ld, int k, void* scr, int bn,
+                                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
   template <typename T> void launch_bwd(const DepthList& D, const FrontDev* fr,
                                         const LayerDev* ld, int k, void* scr, int bn);
 
@@ -150,7 +151,9 @@ struct Handle {
   KStat kstats[K_NCLASS];
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> ev_free;
+  hipEvent_t take_event();     // from the pool, not recorded
   hipEvent_t record_event();
+  bool timed(int cls) const { return (profile_mask >> cls) & 1u; }
   hipEvent_t prof_begin(int cls);
   void prof_end(int cls, hipEvent_t a, double flops, double bytes);
   void collect_profile();

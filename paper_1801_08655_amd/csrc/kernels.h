@@ -52,15 +52,19 @@ template <typename T>
 void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tmap,
                        int total, const LayerDev* layers, int k, hipStream_t st);
 template <typename T>
+// t0 / t1 non-null: the launch records its own start and stop in them
+// (timing of the kernel alone, without event commands around it)
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bn, hipStream_t st);
+                     void* scratch, int bn, hipStream_t st, hipEvent_t t0 = nullptr,
+                     hipEvent_t t1 = nullptr);
 // vector path of the substitutions for k <= 4 columns (same tiles and
 // scratch layout as launch_fwd_gemm / launch_bwd_gemm with 64-row tiles)
 template <typename T>
 void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, hipStream_t st);
+                     void* scratch, hipStream_t st, hipEvent_t t0 = nullptr,
+                     hipEvent_t t1 = nullptr);
 template <typename T>
 void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,

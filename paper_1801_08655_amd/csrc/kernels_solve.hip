@@ -9,6 +9,8 @@
 // Both passes are dense complex GEMMs with the RHS columns as N.  X (the
 // solve vector) and Z are stored in nested-dissection order with the columns
 // fastest; update_B lives in a per-depth-parity buffer.
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 #include "kernels_common.h"
 
@@ -521,11 +523,15 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 template <typename T>
 void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, hipStream_t st) {
+                     void* scratch, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (total_tiles <= 0) return;
-#define HELM_FWDV(KC_)                                                                     \
-  hipLaunchKernelGGL((k_fwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,   \
-                     tasks, n, tmap, layers, k, scratch)
+#define HELM_FWDV(KC_)                                                                      \
+  if (t0)                                                                                   \
+    hipExtLaunchKernelGGL((k_fwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, t0, t1, \
+                          0, fr, ids, tasks, n, tmap, layers, k, scratch);                  \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_fwd_gemv<T, KC_>), dim3(total_tiles), dim3(256), 0, st, fr, ids,  \
+                       tasks, n, tmap, layers, k, scratch)
   switch (k) {
     case 1: HELM_FWDV(1); break;
     case 2: HELM_FWDV(2); break;
@@ -570,19 +576,25 @@ void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tm
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bn, hipStream_t st) {
+                     void* scratch, int bn, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (total_tiles <= 0) return;
   const int ntn = (k + bn - 1) / bn;
   const dim3 grid(total_tiles * ntn);
-  if (bn == 16)
-    hipLaunchKernelGGL((k_fwd_gemm<T, 16>), grid, dim3(256), 0, st, fr, ids, tasks, n,
-                       tmap, layers, k, scratch);
-  else if (bn == 32)
-    hipLaunchKernelGGL((k_fwd_gemm<T, 32>), grid, dim3(256), 0, st, fr, ids, tasks, n,
-                       tmap, layers, k, scratch);
-  else
-    hipLaunchKernelGGL((k_fwd_gemm<T, 64>), grid, dim3(256), 0, st, fr, ids, tasks, n,
-                       tmap, layers, k, scratch);
+#define HELM_FWD(BN_)                                                                       \
+  if (t0)                                                                                   \
+    hipExtLaunchKernelGGL((k_fwd_gemm<T, BN_>), grid, dim3(256), 0, st, t0, t1, 0, fr, ids, \
+                          tasks, n, tmap, layers, k, scratch);                              \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_fwd_gemm<T, BN_>), grid, dim3(256), 0, st, fr, ids, tasks, n,     \
+                       tmap, layers, k, scratch)
+  if (bn == 16) {
+    HELM_FWD(16);
+  } else if (bn == 32) {
+    HELM_FWD(32);
+  } else {
+    HELM_FWD(64);
+  }
+#undef HELM_FWD
 }
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
@@ -633,7 +645,7 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                                      int, const LayerDev*, int, hipStream_t);        \
   template void launch_fwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
-                                   void*, int, hipStream_t);                         \
+                                   void*, int, hipStream_t, hipEvent_t, hipEvent_t); \
   template void launch_fwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int2*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);                      \
@@ -649,7 +661,7 @@ HELM_INST_SOLVE(double)
 #define HELM_INST_GEMV(T)                                                            \
   template void launch_fwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
-                                   void*, hipStream_t);                              \
+                                   void*, hipStream_t, hipEvent_t, hipEvent_t);      \
   template void launch_bwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
                                    void*, int, hipStream_t);
