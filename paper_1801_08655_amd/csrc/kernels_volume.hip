@@ -20,7 +20,40 @@ namespace kern {
 
 namespace {
 
-// Volume <-> layer copies of the bulk planes [s, e], as tiles of 64 nodes x
+// Volume <-> layer copies of the bulk planes [s, e] for a few columns: one
+// element per thread, consecutive threads on consecutive nodes.
+template <typename T>
+__global__ void k_scatter_flat(LayerDev L, const double2* __restrict__ f, int nx, int ny,
+                               long long N, int k) {
+  using C = C_t<T>;
+  const long long plane = (long long)nx * ny;
+  const long long nb = plane * (L.e - L.s + 1);
+  C* X = reinterpret_cast<C*>(L.X);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nb * k;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long sp = e % nb;
+    const int c = (int)(e / nb);
+    X[(long long)L.nat2nd[sp + plane * (L.s - L.lo)] * k + c] =
+        from_d2<C>(f[(long long)c * N + sp + plane * L.s]);
+  }
+}
+template <typename T>
+__global__ void k_gather_flat(LayerDev L, double2* __restrict__ u, int nx, int ny,
+                              long long N, int k) {
+  using C = C_t<T>;
+  const long long plane = (long long)nx * ny;
+  const long long nb = plane * (L.e - L.s + 1);
+  const C* X = reinterpret_cast<const C*>(L.X);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nb * k;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long sp = e % nb;
+    const int c = (int)(e / nb);
+    u[(long long)c * N + sp + plane * L.s] =
+        to_d2(X[(long long)L.nat2nd[sp + plane * (L.s - L.lo)] * k + c]);
+  }
+}
+
+// The same copies for many columns, as tiles of 64 nodes x
 // 64 columns staged in LDS: f and u hold each column contiguously over the
 // nodes, X holds each node's k values contiguously, so both sides are read
 // or written along their contiguous direction.  Grid: (node tiles, column
@@ -383,6 +416,10 @@ void launch_scatter_source(const LayerDev& L, const double2* f, int nx, int ny,
                            long long N, int k, hipStream_t st) {
   const long long nb = (long long)nx * ny * (L.e - L.s + 1);
   if (nb <= 0 || k <= 0) return;
+  if (k <= 8) {   // a 64-column tile would leave most lanes idle
+    hipLaunchKernelGGL(k_scatter_flat<T>, dim3(grid_for(nb * k)), dim3(256), 0, st, L, f, nx, ny, N, k);
+    return;
+  }
   const dim3 grid((unsigned)((nb + VT - 1) / VT), (unsigned)((k + VT - 1) / VT));
   hipLaunchKernelGGL(k_scatter_source<T>, grid, dim3(256), 0, st, L, f, nx, ny, N, k);
 }
@@ -391,6 +428,10 @@ void launch_gather_volume(const LayerDev& L, double2* u, int nx, int ny,
                           long long N, int k, hipStream_t st) {
   const long long nb = (long long)nx * ny * (L.e - L.s + 1);
   if (nb <= 0 || k <= 0) return;
+  if (k <= 8) {   // a 64-column tile would leave most lanes idle
+    hipLaunchKernelGGL(k_gather_flat<T>, dim3(grid_for(nb * k)), dim3(256), 0, st, L, u, nx, ny, N, k);
+    return;
+  }
   const dim3 grid((unsigned)((nb + VT - 1) / VT), (unsigned)((k + VT - 1) / VT));
   hipLaunchKernelGGL(k_gather_volume<T>, grid, dim3(256), 0, st, L, u, nx, ny, N, k);
 }
