@@ -314,8 +314,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU; multi-GPU layer "
-              "sharding is a design in DESIGN.md, not a measured path", file=sys.stderr)
+        print("bench.py: the solver runs on exactly one GPU; sharding the layers over "
+              "several GPUs is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1801_08655_amd as pt

@@ -14,7 +14,7 @@ What is assembled, and where it comes from:
   internal interface, and the local systems H^l v = f^l
   (Eqs. ``local_Helmholtz`` and ``discrete_local_Helmholtz``).
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
 
 R1  h = 1/(n-1) for an n-node axis, nodes at i h; n counts the PML nodes.
 R2  A face with p PML nodes has its profile origin at the half-node between

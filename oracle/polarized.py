@@ -17,7 +17,7 @@ interface j = 0..L-2 separates layers j and j+1 and carries the pair
 u_j = (a_j, b_j) = (u(e_j), u(e_j + 1)), the paper's trace vector of Eq.
 ``traces_definition`` grouped by interface.  G^l = (H^l)^-1.
 
-Readings of the paper taken here (also listed in the design doc):
+Readings of the paper taken here:
 
 R8  Interface sources (the plane deltas of Section "Formulation" scaled to
     this discretisation): with B = 1/(h^2 beta_x beta_y) the z-coupling of H
