@@ -347,3 +347,17 @@ def test_tall_panels_single_layer_residual(precision, tol):
     R = r.reshape(2, -1).T
     res = R - pb.operator() @ w.reshape(2, -1).T
     assert (np.linalg.norm(res, axis=0) / np.linalg.norm(R, axis=0)).max() <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-6)])
+def test_twelve_column_solve_matches_direct(precision, tol):
+    """12 sources: the volume <-> layer copies run as 64-column LDS tiles with
+    52 masked columns (narrower batches take the element loop); every column
+    against the oracle's direct solve."""
+    wl = workload("homogeneous-25")
+    pb = _problem(wl)
+    srcs = [(6 + (3 * i) % 13, 6 + (7 * i) % 13, 6 + (5 * i) % 13) for i in range(12)]
+    ref = SparseLU(pb.operator()).solve(point_source_rhs(pb.shape, srcs, wl.h))
+    s = _solver(wl, precision)
+    u = s.solve_points(srcs).cpu().numpy().reshape(len(srcs), -1).T
+    assert relative_error(u, ref).max() <= tol
