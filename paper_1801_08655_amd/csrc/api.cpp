@@ -192,7 +192,9 @@ int helm_solve_dev(helm_handle* h, int n_rhs, const double* f_dev, double* u_dev
       if (s != HELM_OK) status = s;
     }
     HELM_HIP(hipStreamSynchronize(H.st));
-    H.collect_profile();
+    // timings are read back when asked for (helm_kernel_stats), or here once
+    // many are pending, so that a solve does not spend host time on them
+    if (H.pending.size() > (1u << 16)) H.collect_profile();
     if (info) {
       info->layer_solves = H.layer_solves - ls0;
       info->factor_bytes_read = H.solve_bytes - sb0;
