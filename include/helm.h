@@ -60,8 +60,9 @@ extern "C" {
                                 trees and keep the fastest (default: widths
                                 from the batch width alone)                  */
 #define HELM_FLAG_PROFILE_FWD 8 /* time only the forward substitution GEMM
-                                launches with HIP events; the other kernels
-                                run without events between them             */
+                                launches, each with start and stop events
+                                that the launch itself records; the other
+                                kernels run without events between them     */
 
 /* ---- precision of the local factors ----------------------------------- */
 #define HELM_FP64   0   /* complex128 fronts and substitutions              */
