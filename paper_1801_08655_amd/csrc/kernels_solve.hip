@@ -438,19 +438,21 @@ template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int mask) {
   return __shfl_xor(v, mask, 64);
 }
 
-// backward: one BM-row tile (BM = 32 or 64) and one K chunk per block; each
-// 16-lane quarter of a wave takes the rows m0 + g, m0 + g + 16, ... (BM/16
-// of them) together: its lanes walk the boundary index q (contiguous in the
-// stored block), load X(B[q]) once for all those rows and the factor entry
-// of every row, so that several independent factor loads are in flight per
-// lane; a butterfly over the quarter sums each row.
-template <typename T, int KC, int RPG>
+// backward: one BM-row tile (BM = 32 or 64) and one K chunk per block; the
+// 256 threads form 256 / GW groups of GW lanes and group g takes the rows
+// m0 + g, m0 + g + 256 / GW, ... (RPG of them) together: its lanes walk the
+// boundary index q (contiguous in the stored block), load X(B[q]) once for
+// all those rows and the factor entry of every row, so that several
+// independent factor loads are in flight per lane; a butterfly over the
+// group sums each row.
+template <typename T, int KC, int RPG, int GW = 16>
 __global__ void __launch_bounds__(256)
 k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  constexpr int bm = 16 * RPG;   // row tile: RPG rows per quarter
+  constexpr int NG = 256 / GW;
+  constexpr int bm = NG * RPG;   // row tile
   const int mt = blockIdx.x;
   const int2 tm = tmap[mt];
   const int a = tm.x;
@@ -463,7 +465,7 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int m0 = (local / tk.nch_b) * bm;
   const int kb = chunk * tk.kc_b;
   const int ke = min(f.b, kb + tk.kc_b);
-  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;   // 16 groups of 16 lanes
+  const int g = threadIdx.x / GW, gl = threadIdx.x % GW;
   const C* FT = reinterpret_cast<const C*>(L.fac) + f.fac;
   C* X = reinterpret_cast<C*>(L.X);
   const C* Z = reinterpret_cast<const C*>(L.Wt);
@@ -473,7 +475,7 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* col[RPG];
 #pragma unroll
   for (int r = 0; r < RPG; ++r) {
-    const int m = m0 + g + 16 * r;
+    const int m = m0 + g + NG * r;
     row_ok[r] = m < f.s;
     col[r] = FT + f.s + (long long)(row_ok[r] ? m : 0) * n;
   }
@@ -483,7 +485,7 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 #pragma unroll
     for (int c = 0; c < KC; ++c) acc[r][c] = czero<C>();
 #pragma unroll 2
-  for (int q = kb + gl; q < ke; q += 16) {
+  for (int q = kb + gl; q < ke; q += GW) {
     const C* xb = X + (long long)ld(B + q) * KC;
     C fa[RPG], xv[KC];
 #pragma unroll
@@ -500,13 +502,13 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
-      for (int off = 8; off > 0; off >>= 1) {
+      for (int off = GW / 2; off > 0; off >>= 1) {
         acc[r][c].x += shfl_xor_t(acc[r][c].x, off);
         acc[r][c].y += shfl_xor_t(acc[r][c].y, off);
       }
     }
     if (row_ok[r] && gl < KC) {
-      const int m = m0 + g + 16 * r;
+      const int m = m0 + g + NG * r;
       C z = acc[r][0];
 #pragma unroll
       for (int c = 1; c < KC; ++c)
@@ -547,11 +549,11 @@ void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
   if (total_tiles <= 0) return;
 #define HELM_BWDV(KC_)                                                                     \
   if (bm == 32)                                                                            \
-    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 2>), dim3(total_tiles), dim3(256), 0, st, fr,   \
-                       ids, tasks, n, tmap, layers, k, scratch);                           \
+    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 4, 32>), dim3(total_tiles), dim3(256), 0, st,   \
+                       fr, ids, tasks, n, tmap, layers, k, scratch);                       \
   else                                                                                     \
-    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 4>), dim3(total_tiles), dim3(256), 0, st, fr,   \
-                       ids, tasks, n, tmap, layers, k, scratch)
+    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 8, 32>), dim3(total_tiles), dim3(256), 0, st,   \
+                       fr, ids, tasks, n, tmap, layers, k, scratch)
   switch (k) {
     case 1: HELM_BWDV(1); break;
     case 2: HELM_BWDV(2); break;
