@@ -56,7 +56,6 @@ std::vector<double2> to_d2(const std::vector<cd>& v) {
 }
 
 int tiles64(long long n) { return (int)((n + 63) / 64); }
-int tiles128(long long n) { return (int)((n + 127) / 128); }
 int tiles16(long long n) { return (int)((n + 15) / 16); }
 
 }  // namespace

@@ -387,7 +387,7 @@ k_volume_norm2(const double2* __restrict__ x, long long N, int k,
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[(long long)c * gridDim.x + blockIdx.x] = red[0];
