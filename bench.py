@@ -57,6 +57,9 @@ def parse():
                     help="batched run instead: independent problems n in [64, 160]")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--rhs-scaling", action="store_true",
+                    help="RHS/s against the number of right-hand sides R = 1, 2, ..., 64 "
+                         "on one factorization of the workload")
     return ap.parse_args()
 
 
@@ -272,6 +275,38 @@ def serve_bench(args, torch, pt):
     print(json.dumps(out), flush=True)
 
 
+def rhs_scaling_bench(args, torch, pt):
+    """Throughput against the batch width R on one mixed-precision
+    factorization: R columns share every layer solve (the substitution GEMMs
+    take them as the N dimension), so RHS/s grows with R until the
+    substitutions reach the matrix-core bound."""
+    from helm_inputs import workload
+    wl = workload(args.workload)
+    m = wl.m()
+    log(f"[rhs-scaling] factorize {wl.name}")
+    s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
+                  ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4, err_target=1e-6,
+                  ir_max_steps=4, pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64,
+                  flags=0 if args.no_autotune else pt._lib.HELM_FLAG_AUTOTUNE)
+    points = []
+    for R in (1, 2, 4, 8, 16, 32, 64):
+        srcs = wl.point_sources(R)
+        _, info, total, lat = timed_solves(s, srcs, args.steps, args.warmup, torch)
+        pt_ = {"rhs": R, "rhs_per_s": R * args.steps / total,
+               "ms_per_step": 1e3 * total / args.steps,
+               "layer_solves_per_step": info["layer_solves"],
+               "ms_per_layer_solve": 1e3 * total / args.steps / max(1, info["layer_solves"]),
+               "gmres_iters": info["gmres_iters"], "est_error_max": info["est_error_max"]}
+        log(f"[rhs-scaling] {pt_}")
+        points.append(pt_)
+    s.close()
+    print(json.dumps({"metric": "RHS/s against the batch width R (mixed)",
+                      "unit": "RHS/s", "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic", "config": {"workload": wl.name, "n": list(wl.n),
+                                                      "layers": wl.n_layers},
+                      "points": points}), flush=True)
+
+
 def batch_bench(args, torch, pt):
     """Independent problems in one batched call: n ~ U{64..160} cubes with an
     8-pt PML, smooth random media (c in [0.8, 1.2]), 10 ppw, L = round(n/10),
@@ -324,6 +359,9 @@ def main():
 
     if args.serve:
         serve_bench(args, torch, pt)
+        return
+    if args.rhs_scaling:
+        rhs_scaling_bench(args, torch, pt)
         return
     if args.batch:
         if args.slots == 32:
