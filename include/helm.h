@@ -59,6 +59,9 @@ extern "C" {
                                 substitution GEMMs per depth of the front
                                 trees and keep the fastest (default: widths
                                 from the batch width alone)                  */
+#define HELM_FLAG_FULL_KRYLOV 16 /* GMRES on the whole polarized system rather
+                                 than on its up-going block (the operator is
+                                 block triangular; same stopping test)      */
 #define HELM_FLAG_PROFILE_FWD 8 /* time only the forward substitution GEMM
                                 launches, each with start and stop events
                                 that the launch itself records; the other

@@ -34,6 +34,7 @@ EXPORTED = [
 HELM_FLAG_PROFILE = 1
 HELM_FLAG_NO_GRAPHS = 2
 HELM_FLAG_AUTOTUNE = 4
+HELM_FLAG_FULL_KRYLOV = 16
 HELM_FLAG_PROFILE_FWD = 8
 
 

@@ -275,10 +275,24 @@ void Method::dot(const double2* a, const double2* b, long long V, double2* out) 
 // Arnoldi (modified Gram-Schmidt), norms and basis updates in FP64 on the
 // device; the (j+2) x k Hessenberg column is copied to the host where the
 // Givens rotations and the stopping test are applied per column.
+//
+// P M = I + K with K x depending on x_up alone (P M x = x + P(U x_up, 0)), so
+// the system is block triangular: (I + K_up) x_up = b_up, then x_down =
+// b_down - K_down x_up.  By default the Krylov space is built on the
+// up-going block only: a basis vector holds v in its up half and zeros in
+// its down half when P M is applied to it; the down half of the result,
+// K_down v, is then kept in the basis vector's own down half, so the update
+// x += sum y_i v_i accumulates K_down x_up there, and x_down = b_down - that
+// at the end.  The stopping test is the same as for the whole system: the
+// residual (0, r_up) against |b|.  HELM_FLAG_FULL_KRYLOV runs GMRES on the
+// whole polarized system instead.
 int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, int max_iter,
                   int restart, int* iters_out) {
   const long long V = 2 * Vp / k;             // polarized vector length per column
   const int m = std::max(1, std::min(restart, max_iter));
+  const bool up = !(H.opt.flags & HELM_FLAG_FULL_KRYLOV);
+  const long long off = up ? Vp : 0;          // first element of the Krylov part
+  const long long Vs = up ? V / 2 : V;        // its length per column
   if (!gw.p) {
     gw.alloc((size_t)V * k * sizeof(double2));
     gr.alloc((size_t)V * k * sizeof(double2));
@@ -300,23 +314,23 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
   int status = HELM_OK;
   std::vector<double> resid(k, 1.0);
   while (true) {
-    // r = b - A x  (first cycle: x = 0, r = b)
-    const double2* r0 = b;
+    // r = b - A x  (first cycle: x = 0, r = b), on the Krylov part
+    const double2* r0 = b + off;
     if (!first) {
       apply_A(x, w.as<double2>());
-      HELM_HIP(hipMemcpyAsync(r.p, b, (size_t)V * k * sizeof(double2),
+      HELM_HIP(hipMemcpyAsync(r.as<double2>() + off, b + off, (size_t)Vs * k * sizeof(double2),
                               hipMemcpyDeviceToDevice, H.st));
       HELM_HIP(hipMemsetAsync(hcol.p, 0, k * sizeof(double2), H.st));
       // r -= w  (alpha = 1 per column)
       std::vector<double2> ones(k, make_double2(1.0, 0.0));
       HELM_HIP(hipMemcpyAsync(hcol.p, ones.data(), k * sizeof(double2),
                               hipMemcpyHostToDevice, H.st));
-      kern::launch_axpy_cols(r.as<double2>(), w.as<double2>(), hcol.as<double2>(), -1.0, V, k,
-                             H.st);
-      r0 = r.as<double2>();
+      kern::launch_axpy_cols(r.as<double2>() + off, w.as<double2>() + off, hcol.as<double2>(),
+                             -1.0, Vs, k, H.st);
+      r0 = r.as<double2>() + off;
     }
     first = false;
-    dot(r0, r0, V, hcol.as<double2>());
+    dot(r0, r0, Vs, hcol.as<double2>());
     HELM_HIP(hipMemcpyAsync(hh.data(), hcol.p, k * sizeof(double2), hipMemcpyDeviceToHost, H.st));
     HELM_HIP(hipStreamSynchronize(H.st));
     std::vector<double> beta(k);
@@ -332,7 +346,8 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
     if (!any) break;
     if (total >= max_iter) { status = HELM_ENOCONV; break; }
     HELM_HIP(hipMemcpyAsync(scale.p, scl.data(), k * sizeof(double), hipMemcpyHostToDevice, H.st));
-    kern::launch_scale_cols(basis_vec(0), r0, scale.as<double>(), V, k, H.st);
+    kern::launch_scale_cols(basis_vec(0) + off, r0, scale.as<double>(), Vs, k, H.st);
+    if (up) HELM_HIP(hipMemsetAsync(basis_vec(0), 0, (size_t)Vp * sizeof(double2), H.st));
     // per-column Hessenberg, rotations and rhs
     std::vector<std::vector<cd>> Hm(k, std::vector<cd>((size_t)(m + 1) * m, 0.0));
     std::vector<std::vector<cd>> cs(k, std::vector<cd>(m)), sn(k, std::vector<cd>(m));
@@ -344,12 +359,17 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
     for (; j < m && total < max_iter; ++j) {
       double2* vj = basis_vec(j);
       apply_A(vj, w.as<double2>());
+      // K_down v_j into the down half of v_j (no longer an operand of P M)
+      if (up)
+        HELM_HIP(hipMemcpyAsync(vj, w.p, (size_t)Vp * sizeof(double2),
+                                hipMemcpyDeviceToDevice, H.st));
+      double2* wk = w.as<double2>() + off;
       for (int i = 0; i <= j; ++i) {
-        dot(basis_vec(i), w.as<double2>(), V, hcol.as<double2>() + (long long)i * k);
-        kern::launch_axpy_cols(w.as<double2>(), basis_vec(i),
-                               hcol.as<double2>() + (long long)i * k, -1.0, V, k, H.st);
+        dot(basis_vec(i) + off, wk, Vs, hcol.as<double2>() + (long long)i * k);
+        kern::launch_axpy_cols(wk, basis_vec(i) + off, hcol.as<double2>() + (long long)i * k,
+                               -1.0, Vs, k, H.st);
       }
-      dot(w.as<double2>(), w.as<double2>(), V, hcol.as<double2>() + (long long)(j + 1) * k);
+      dot(wk, wk, Vs, hcol.as<double2>() + (long long)(j + 1) * k);
       HELM_HIP(hipMemcpyAsync(hh.data(), hcol.p, (size_t)(j + 2) * k * sizeof(double2),
                               hipMemcpyDeviceToHost, H.st));
       HELM_HIP(hipStreamSynchronize(H.st));
@@ -394,8 +414,8 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
       if (j + 1 <= m) {
         HELM_HIP(hipMemcpyAsync(scale.p, scl.data(), k * sizeof(double), hipMemcpyHostToDevice,
                                 H.st));
-        kern::launch_scale_cols(basis_vec(j + 1), w.as<double2>(),
-                                scale.as<double>(), V, k, H.st);
+        kern::launch_scale_cols(basis_vec(j + 1) + off, wk, scale.as<double>(), Vs, k, H.st);
+        if (up) HELM_HIP(hipMemsetAsync(basis_vec(j + 1), 0, (size_t)Vp * sizeof(double2), H.st));
       }
       if (!any_run) { ++j; break; }
     }
@@ -426,6 +446,15 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
     for (int c = 0; c < k; ++c) conv &= !(active[c] && resid[c] > tol[c]);
     if (conv) break;
     if (total >= max_iter) { status = HELM_ENOCONV; break; }
+  }
+  if (up) {
+    // x_down = b_down - K_down x_up (the down half holds K_down x_up)
+    std::vector<double> minus(k, -1.0);
+    HELM_HIP(hipMemcpyAsync(scale.p, minus.data(), k * sizeof(double), hipMemcpyHostToDevice,
+                            H.st));
+    kern::launch_scale_cols(x, x, scale.as<double>(), V / 2, k, H.st);
+    kern::launch_add(x, x, b, Vp, H.st);
+    HELM_HIP(hipStreamSynchronize(H.st));
   }
   last_resid = resid;
   if (iters_out) *iters_out = total;

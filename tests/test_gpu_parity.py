@@ -361,3 +361,24 @@ def test_twelve_column_solve_matches_direct(precision, tol):
     s = _solver(wl, precision)
     u = s.solve_points(srcs).cpu().numpy().reshape(len(srcs), -1).T
     assert relative_error(u, ref).max() <= tol
+
+
+def test_up_going_block_krylov_matches_whole_system():
+    """GMRES on the up-going block of the block-triangular preconditioned
+    system (the default) and on the whole polarized system give the same
+    solution, and the block needs no more iterations."""
+    import paper_1801_08655_amd as pt
+    wl = workload("layered-28")
+    pb = _problem(wl)
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12)]
+    ref = SparseLU(pb.operator()).solve(point_source_rhs(pb.shape, srcs, wl.h))
+    out = {}
+    for name, flags in (("block", 0), ("whole", pt._lib.HELM_FLAG_FULL_KRYLOV)):
+        s = _solver(wl, "fp64", flags=flags)
+        u, info = s.solve_points(srcs, info=True)
+        out[name] = (u.cpu().numpy().reshape(len(srcs), -1).T, info["gmres_iters"])
+        s.close()
+    print({k: v[1] for k, v in out.items()})
+    assert relative_error(out["block"][0], ref).max() <= 1e-9
+    assert relative_error(out["whole"][0], ref).max() <= 1e-9
+    assert out["block"][1] <= out["whole"][1]
