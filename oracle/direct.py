@@ -45,7 +45,9 @@ def solve(H, F: np.ndarray) -> np.ndarray:
 
 
 def relative_error(u: np.ndarray, ref: np.ndarray) -> np.ndarray:
-    """Per-column relative l2 error over the full grid (PML included)."""
+    """Per-column relative l2 error |u - ref|_2 / |ref|_2 over the full grid
+    (PML included); a zero reference column gives |u|_2.  Pinned against
+    hand-computed values (tests/test_oracle_pins.py)."""
     u = np.atleast_2d(u.T).T if u.ndim == 1 else u
     ref = np.atleast_2d(ref.T).T if ref.ndim == 1 else ref
     num = np.linalg.norm(u - ref, axis=0)

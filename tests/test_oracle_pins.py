@@ -33,6 +33,40 @@ def _problem(n, p, ppw=10.0, model="const", seed=7, C=20.0):
 
 
 # --------------------------------------------------------------------------
+# the comparison yardstick
+# --------------------------------------------------------------------------
+
+def test_relative_error_hand_computed_values():
+    """relative_error against values worked out by hand: per column
+    |u - ref|_2 / |ref|_2 over every entry.  A squared norm, a missing square
+    root, a norm over rows instead of columns or the wrong denominator each
+    change at least one of these numbers."""
+    # one column scaled by (1 + 1e-3): error exactly 1e-3 (up to rounding)
+    ref = np.array([1.0 + 2.0j, -3.0, 0.5j, 4.0 - 1.0j])
+    assert relative_error(ref * (1 + 1e-3), ref)[0] == pytest.approx(1e-3, rel=1e-12)
+    # two columns with different, hand-computed errors on a 3 x 2 array
+    #   column 0: ref (3, 4, 0), deviation (0, 0.5, 0)   -> 0.5 / 5   = 0.1
+    #   column 1: ref (0, 1j, 0), deviation (2e-6, 0, 0) -> 2e-6 / 1 = 2e-6
+    ref2 = np.array([[3.0, 0.0], [4.0, 1.0j], [0.0, 0.0]])
+    u2 = ref2 + np.array([[0.0, 2e-6], [0.5, 0.0], [0.0, 0.0]])
+    err = relative_error(u2, ref2)
+    assert err.shape == (2,)
+    assert err[0] == pytest.approx(0.1, rel=1e-14)
+    assert err[1] == pytest.approx(2e-6, rel=1e-12)
+    # complex deviation: ref 1 + i, u 1 - i -> |-2i| / sqrt(2) = sqrt(2)
+    assert relative_error(np.array([1 - 1j]), np.array([1 + 1j]))[0] == \
+        pytest.approx(math.sqrt(2.0), rel=1e-14)
+    # deviation spread over several entries: ref (1, 1, 1, 1) (norm 2),
+    # deviation (0.3, 0.4, 0, 0) (norm 0.5) -> 0.25
+    assert relative_error(np.ones(4) + np.array([0.3, 0.4, 0, 0]), np.ones(4))[0] == \
+        pytest.approx(0.25, rel=1e-14)
+    # a zero reference column reports the absolute norm of u
+    assert relative_error(np.array([[3.0], [4.0]]), np.zeros((2, 1)))[0] == 5.0
+    # exact agreement
+    assert relative_error(ref2, ref2).max() == 0.0
+
+
+# --------------------------------------------------------------------------
 # operator structure
 # --------------------------------------------------------------------------
 
