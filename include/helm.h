@@ -66,6 +66,12 @@ extern "C" {
                                 launches, each with start and stop events
                                 that the launch itself records; the other
                                 kernels run without events between them     */
+#define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
+                                the factorization leaves one leaf front of
+                                layer 0 unassembled, so its pivots are exactly
+                                zero; the kernels run to the end (a zero pivot
+                                is replaced by one) and helm_factorize returns
+                                HELM_EZEROPIVOT                              */
 
 /* ---- precision of the local factors ----------------------------------- */
 #define HELM_FP64   0   /* complex128 fronts and substitutions              */
@@ -83,7 +89,7 @@ typedef struct {
   double pml_C;            /* PML strength C; <= 0 selects 20 * max(c)       */
   int    precision;        /* HELM_FP64 or HELM_MIXED                        */
   double gmres_tol;        /* stop on |P(f - M x)| <= tol |P f|              */
-  int    gmres_max_iter;   /* max GMRES iterations (no restart below this)   */
+  int    gmres_max_iter;   /* max GMRES iterations over all restart cycles  */
   double ir_tol;           /* mixed: stop refinement at |f-Hu| <= ir_tol |f| */
   int    ir_max_steps;     /* mixed: max refinement steps                    */
   double inner_tol;        /* mixed: GMRES tolerance of the first solve      */
@@ -97,6 +103,10 @@ typedef struct {
   int    max_rhs;          /* widest RHS batch one internal launch carries   */
   int    leaf_size;        /* nested-dissection leaf size (DOFs), 0 = default */
   int    flags;            /* HELM_FLAG_* bits, 0 by default */
+  int    gmres_restart;    /* GMRES restart length (basis vectors kept); 0 =
+                              as many as device memory allows, at most 60.
+                              A smaller value is honoured, and the memory
+                              bound still caps it                           */
 } helm_options;
 
 typedef struct {
@@ -135,7 +145,8 @@ typedef struct {
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,
  * gmres_tol 1e-10, gmres_max_iter 40, ir_tol 1e-9, ir_max_steps 6,
  * inner_tol 1e-3, inner_tol_refine 1e-4, err_target 0 (off), hbm_budget 0
- * (auto), device 0, stream NULL, max_rhs 64, leaf_size 64, flags 0. */
+ * (auto), device 0, stream NULL, max_rhs 64, leaf_size 64, flags 0,
+ * gmres_restart 0 (memory-bound, at most 60). */
 void helm_default_options(helm_options* opt);
 
 /* Planner (no device memory is touched).  Exact sizes from the symbolic
@@ -185,8 +196,11 @@ int helm_solve_dev(helm_handle* h, int n_rhs, const double* f_dev,
 
 /* Point sources: column r is amplitude[r] / h^3 at node node_index[r]
  * (index i + nx*(j + ny*k)); arrays are host pointers of length n_rhs
- * (amplitude: 2*n_rhs doubles, complex).  u_dev is a device array of
- * n_rhs volumes. */
+ * (amplitude: 2*n_rhs doubles, complex).  The 1/h^3 scale is the numerical
+ * Dirac delta of the classical finite-difference discretization (Section
+ * "Formulation", definition of the delta at a fixed depth), taken at a single
+ * node.  u_dev is a device array of n_rhs volumes.  Errors: HELM_EINVAL for
+ * a node outside the grid or a non-finite amplitude (nothing is solved). */
 int helm_solve_points(helm_handle* h, int n_rhs, const int64_t* node_index,
                       const double* amplitude, double* u_dev,
                       helm_solve_info* info);
@@ -237,9 +251,33 @@ int helm_device_peaks(int device, double* mfma_f32_tflops, double* mfma_f64_tflo
                       double* hbm_read_gbps, double* hbm_copy_gbps);
 
 /* Change the online-stage options of a factorized handle (gmres_tol,
- * gmres_max_iter, ir_tol, ir_max_steps, inner_tol, max_rhs, flags); the
- * geometry, precision, device and stream fields are ignored. */
+ * gmres_max_iter, gmres_restart, ir_tol, ir_max_steps, inner_tol,
+ * inner_tol_refine, err_target, max_rhs, flags); the geometry, precision,
+ * device and stream fields are ignored. */
 int helm_set_solve_options(helm_handle* h, const helm_options* opt);
+
+/* Record of the offline stage (Algorithm 1) of a factorized handle.
+ *   lu_flops     -- algorithmic real flops: an LU of every front,
+ *                   sum 4 (2/3 s^3 + 2 s^2 b + 2 s b^2) over fronts with s
+ *                   pivots and b boundary variables;
+ *   gj_flops     -- real flops the blocked Gauss-Jordan sweep executes (it
+ *                   also forms F11^-1, so that the substitutions are plain
+ *                   products);
+ *   pivot_min / pivot_max -- smallest and largest |pivot| chosen by the
+ *                   partial pivoting within the fully summed rows of each
+ *                   front;
+ *   diag_max     -- largest |diagonal entry| of the assembled operators;
+ *                   pivot_max / diag_max is the pivot growth;
+ *   factor_bytes -- resident factors; n_fronts, max_front -- over layers. */
+typedef struct {
+  double seconds;
+  double lu_flops, gj_flops;
+  double pivot_min, pivot_max, diag_max;
+  size_t factor_bytes;
+  long long n_fronts, max_front;
+} helm_factor_info;
+
+int helm_get_factor_info(const helm_handle* h, helm_factor_info* out);
 
 /* Release the factors and all device memory owned by the handle. */
 int helm_free(helm_handle* h);

@@ -198,6 +198,14 @@ class Solver:
         check(lib().helm_set_solve_options(self._h, ctypes.byref(self.opts)),
               "helm_set_solve_options")
 
+    def factor_info(self):
+        """Offline-stage record: LU and executed flops, pivot range and growth."""
+        fi = _lib.helm_factor_info()
+        check(lib().helm_get_factor_info(self._h, ctypes.byref(fi)), "helm_get_factor_info")
+        d = fi.as_dict()
+        d["pivot_growth"] = d["pivot_max"] / d["diag_max"] if d["diag_max"] > 0 else None
+        return d
+
     def kernel_stats(self, reset: bool = False):
         """Event-timed per-kernel-class statistics (needs flags=HELM_FLAG_PROFILE)."""
         arr = (_lib.helm_kernel_stat * 32)()

@@ -24,6 +24,7 @@ EXPORTED = [
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
     "helm_set_solve_options", "helm_tile_choices", "helm_device_peaks",
+    "helm_get_factor_info",
     # include/helm_serve.h
     "helm_server_default_options", "helm_server_create", "helm_server_add_model",
     "helm_server_submit", "helm_server_wait", "helm_server_poll", "helm_server_get_stats",
@@ -36,6 +37,7 @@ HELM_FLAG_NO_GRAPHS = 2
 HELM_FLAG_AUTOTUNE = 4
 HELM_FLAG_FULL_KRYLOV = 16
 HELM_FLAG_PROFILE_FWD = 8
+HELM_FLAG_TEST_ZERO_FRONT = 32
 
 
 class helm_grid(ctypes.Structure):
@@ -61,6 +63,7 @@ class helm_options(ctypes.Structure):
         ("max_rhs", ctypes.c_int),
         ("leaf_size", ctypes.c_int),
         ("flags", ctypes.c_int),
+        ("gmres_restart", ctypes.c_int),
     ]
 
 
@@ -106,6 +109,17 @@ class helm_solve_info(ctypes.Structure):
         for name, a in getattr(self, "_arrays", {}).items():
             d[name] = a.tolist()
         return d
+
+
+class helm_factor_info(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("lu_flops", ctypes.c_double),
+                ("gj_flops", ctypes.c_double), ("pivot_min", ctypes.c_double),
+                ("pivot_max", ctypes.c_double), ("diag_max", ctypes.c_double),
+                ("factor_bytes", ctypes.c_size_t), ("n_fronts", ctypes.c_longlong),
+                ("max_front", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class helm_kernel_stat(ctypes.Structure):
@@ -262,6 +276,8 @@ def lib():
     L.helm_tile_choices.restype = I
     L.helm_device_peaks.argtypes = [I] + [ctypes.POINTER(D)] * 4
     L.helm_device_peaks.restype = I
+    L.helm_get_factor_info.argtypes = [H, ctypes.POINTER(helm_factor_info)]
+    L.helm_get_factor_info.restype = I
     SV = ctypes.c_void_p
     L.helm_server_default_options.argtypes = [ctypes.POINTER(helm_server_options)]
     L.helm_server_default_options.restype = None

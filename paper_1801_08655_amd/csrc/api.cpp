@@ -28,6 +28,7 @@ helm_options resolve(const helm_options* o) {
   if (r.inner_tol_refine <= 0) r.inner_tol_refine = r.inner_tol;
   if (r.max_rhs <= 0) r.max_rhs = d.max_rhs;
   if (r.leaf_size <= 0) r.leaf_size = d.leaf_size;
+  if (r.gmres_restart < 0) r.gmres_restart = 0;
   return r;
 }
 
@@ -75,6 +76,8 @@ int factorize_common(const helm_grid* g, const double* m, bool on_device, double
   H.upload_geometry(mh.data(), false);
   H.build_fronts();
   H.factorize();
+  // the launch lists of every single-layer solve (the sweeps' unit of work)
+  for (int l = 0; l < H.G.L; ++l) H.single_sets.push_back(&H.layer_set({l}));
   *out = h.release();
   return HELM_OK;
 }
@@ -109,6 +112,7 @@ void helm_default_options(helm_options* o) {
   o->max_rhs = 64;
   o->leaf_size = 64;
   o->flags = 0;
+  o->gmres_restart = 0;
 }
 
 int helm_plan(const helm_grid* g, int pml_width, int n_layers, const helm_options* opt,
@@ -333,6 +337,7 @@ int helm_set_solve_options(helm_handle* h, const helm_options* opt) {
     Handle& H = h->impl;
     H.opt.gmres_tol = o.gmres_tol;
     H.opt.gmres_max_iter = o.gmres_max_iter;
+    H.opt.gmres_restart = o.gmres_restart;
     H.opt.ir_tol = o.ir_tol;
     H.opt.ir_max_steps = o.ir_max_steps;
     H.opt.inner_tol = o.inner_tol;
@@ -341,6 +346,26 @@ int helm_set_solve_options(helm_handle* h, const helm_options* opt) {
     H.opt.max_rhs = o.max_rhs;
     H.opt.flags = o.flags;
     H.set_profile(o.flags);
+    return HELM_OK;
+  });
+}
+
+int helm_get_factor_info(const helm_handle* h, helm_factor_info* out) {
+  return guard([&] {
+    HELM_REQUIRE(h && out, HELM_EINVAL, "null argument");
+    const Handle& H = h->impl;
+    std::memset(out, 0, sizeof(*out));
+    out->seconds = H.factor_seconds;
+    out->lu_flops = H.factor_flops;
+    out->gj_flops = H.factor_gj_flops;
+    out->pivot_min = H.pivot_min;
+    out->pivot_max = H.pivot_max;
+    out->diag_max = H.diag_max;
+    out->factor_bytes = H.bytes_factors;
+    out->n_fronts = H.n_fronts;
+    long long mf = 0;
+    for (const auto& P : H.G.layers) mf = std::max(mf, P.max_front);
+    out->max_front = mf;
     return HELM_OK;
   });
 }

@@ -327,6 +327,7 @@ void Handle::factorize_t() {
   fac.clear();
   bytes_factors = 0;
   factor_flops = 0;
+  factor_gj_flops = 0;
   HELM_REQUIRE(!opt.hbm_budget_bytes || plan_factor_elems(G) * elem <= opt.hbm_budget_bytes,
                HELM_ENOMEM, "factors exceed the memory budget");
   for (int l = 0; l < L; ++l) {
@@ -335,6 +336,7 @@ void Handle::factorize_t() {
     layers_h[l].fac = fac.back()->p;
     bytes_factors += (size_t)G.layers[l].fac_elems * elem;
     factor_flops += G.layers[l].factor_flops;
+    factor_gj_flops += G.layers[l].gj_flops;
   }
   // memory left for frontal workspaces: choose groups of consecutive layers
   size_t free_b = 0, total_b = 0;
@@ -376,8 +378,19 @@ void Handle::factorize_t() {
   }
 
   DevMem status;
-  status.alloc(sizeof(int));
-  HELM_HIP(hipMemsetAsync(status.p, 0, sizeof(int), st));
+  status.alloc(sizeof(kern::FactorStatus));
+  {
+    kern::FactorStatus s0{};
+    const double inf = INFINITY;
+    std::memcpy(&s0.pmin, &inf, sizeof(double));
+    HELM_HIP(hipMemcpyAsync(status.p, &s0, sizeof(s0), hipMemcpyHostToDevice, st));
+    HELM_HIP(hipStreamSynchronize(st));
+  }
+  // test hook: leave the first leaf front of layer 0 unassembled
+  int skip_front = -1;
+  if (opt.flags & HELM_FLAG_TEST_ZERO_FRONT)
+    for (int f = front_base[0]; f < front_base[1] && skip_front < 0; ++f)
+      if (fronts_h[f].child[0] < 0 && fronts_h[f].child[1] < 0) skip_front = f;
 
   for (const auto& grp : groups) {
     int maxd = 0;
@@ -455,7 +468,8 @@ void Handle::factorize_t() {
       prof_end(K_EXTEND_ADD, e0, 0, 2 * front_elems * elem);
       e0 = prof_begin(K_ORIG);
       kern::launch_orig_entries<T>(fr, ids, fd.n, fd.pRow.as<int2>(), pRow[fd.n], ld,
-                                   ws0.p, ws1.p, grid, st);
+                                   ws0.p, ws1.p, grid, skip_front,
+                                   status.as<kern::FactorStatus>(), st);
       prof_end(K_ORIG, e0, 0, 0);
       const int smax = fd.s_sorted[0];
       for (int k = 0; k < smax; k += nb) {
@@ -466,14 +480,16 @@ void Handle::factorize_t() {
           for (int a = 0; a < n_act; ++a) {
             double n = fronts_h[v[a]].s + fronts_h[v[a]].b;
             double nbf = std::min(nb, fronts_h[v[a]].s - k);
-            sw_flops += 8.0 * n * n * nbf;
+            // the LU's trailing update of this step (its share of the
+            // algorithmic count 4 (2/3 s^3 + 2 s^2 b + 2 s b^2))
+            sw_flops += 8.0 * (n - k - nbf) * (n - k - nbf) * nbf;
             sw_bytes += (2.0 * n * n + 2.0 * n * nbf) * elem;
           }
         hipEvent_t e1 = prof_begin(K_PANEL);
         kern::launch_panel<T>(fr, ids, n_act, smax - k, k, nb, ws0.p, ws1.p, panel.p,
                               fd.panel_off.as<long long>(), Dbuf.p, ipiv.as<int>(),
                               perm.as<int>(), fd.perm_off.as<long long>(),
-                              status.as<int>(), st);
+                              status.as<kern::FactorStatus>(), st);
         prof_end(K_PANEL, e1, 0, 0);
         e1 = prof_begin(K_SWAP_JO);
         kern::launch_swap_JO<T>(fr, ids, n_act, fd.pCol.as<int2>(), fd.pCol_h[n_act], k,
@@ -502,10 +518,19 @@ void Handle::factorize_t() {
       HELM_HIP(hipStreamSynchronize(st));
     }
   }
-  int st_h = 0;
-  HELM_HIP(hipMemcpyAsync(&st_h, status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  kern::FactorStatus st_h{};
+  HELM_HIP(hipMemcpyAsync(&st_h, status.p, sizeof(st_h), hipMemcpyDeviceToHost, st));
   HELM_HIP(hipStreamSynchronize(st));
-  HELM_REQUIRE(st_h == 0, HELM_EZEROPIVOT, "zero or non-finite pivot in a frontal matrix");
+  auto as_d = [](unsigned long long b) {
+    double v;
+    std::memcpy(&v, &b, sizeof(v));
+    return v;
+  };
+  pivot_min = std::sqrt(as_d(st_h.pmin));
+  pivot_max = std::sqrt(as_d(st_h.pmax));
+  diag_max = std::sqrt(as_d(st_h.dmax));
+  zero_pivots = st_h.flag;
+  HELM_REQUIRE(st_h.flag == 0, HELM_EZEROPIVOT, "zero or non-finite pivot in a frontal matrix");
   upload(fronts, fronts_h, st);
   upload_layers();
 }
@@ -819,11 +844,23 @@ void Handle::autotune_t(const LayerSet& set, int k, std::vector<TileChoice>& pla
 
 template <typename T>
 void Handle::solve_layers_t(const LayerSet& set, int k) {
+  run_layers_t<T>(set, k, layers_d.as<LayerDev>(), scratch.p, tile_plan(set, k).data(), true);
+}
+
+// The launches of one multi-RHS solve of the layers in `set`: X, Z, the
+// update buffers and the layer pointers through the table `ld`, split-K
+// partials in `scr`; column-tile widths per depth from `tp`, or from the
+// batch width alone when tp is null.  Timing events only when `timing` is
+// set and the profiling flags ask for them.
+template <typename T>
+void Handle::run_layers_t(const LayerSet& set, int k, const LayerDev* ld, void* scr,
+                          const TileChoice* tp, bool timing) {
   const FrontDev* fr = fronts.as<FrontDev>();
-  const LayerDev* ld = layers_d.as<LayerDev>();
+  auto prof_begin = [&](int cls) { return timing ? this->prof_begin(cls) : nullptr; };
   const double e = (double)elem, kk = (double)k;
-  void* scr = scratch.p;
-  const std::vector<TileChoice>& tp = tile_plan(set, k);
+  const int wdef = width_bn(k);
+  auto fwd_bn = [&](int d) { return tp ? tp[d].fwd_bn : wdef; };
+  auto bwd_bn = [&](int d) { return tp ? tp[d].bwd_bn : wdef; };
   for (int d = set.max_depth; d >= 0; --d) {
     const DepthList& D = *set.depth[d];
     if (D.n == 0) continue;
@@ -840,11 +877,11 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
       // timed by the launch itself: its start and stop, no event commands
       // between it and its neighbours
       hipEvent_t t0 = nullptr, t1 = nullptr;
-      if (timed(K_FWD_GEMM)) {
+      if (timing && timed(K_FWD_GEMM)) {
         t0 = take_event();
         t1 = take_event();
       }
-      launch_fwd<T>(D, fr, ld, k, scr, tp[d].fwd_bn, t0, t1);
+      launch_fwd<T>(D, fr, ld, k, scr, fwd_bn(d), t0, t1);
       // factor block read once; pivots read, Z written, boundary updates
       // written and the children's updates of the boundary rows read
       if (t0)
@@ -863,7 +900,7 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
     const int* ids = D.ids.as<int>();
     const SolveTask* tk = D.tasks.as<SolveTask>();
     hipEvent_t a = prof_begin(K_BWD_GEMM);
-    launch_bwd<T>(D, fr, ld, k, scr, tp[d].bwd_bn);
+    launch_bwd<T>(D, fr, ld, k, scr, bwd_bn(d));
     // factor block read once; X(B) rows read, Z(S) read, X(S) written
     prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
              D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
@@ -877,5 +914,14 @@ void Handle::solve_layers_t(const LayerSet& set, int k) {
 
 template void Handle::solve_layers_t<float>(const LayerSet&, int);
 template void Handle::solve_layers_t<double>(const LayerSet&, int);
+template void Handle::run_layers_t<float>(const LayerSet&, int, const LayerDev*, void*,
+                                          const TileChoice*, bool);
+template void Handle::run_layers_t<double>(const LayerSet&, int, const LayerDev*, void*,
+                                           const TileChoice*, bool);
+
+const LayerSet* Handle::find_layer_set(const std::vector<int>& layers) const {
+  auto it = sets.find(layers);
+  return it == sets.end() ? nullptr : it->second.get();
+}
 
 }  // namespace helm

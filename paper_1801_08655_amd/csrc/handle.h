@@ -95,7 +95,7 @@ struct Handle {
   hipStream_t st = nullptr;
   bool own_stream = false;
   int device = 0;
-  int nb = 64;                    // pivot block of the Gauss-Jordan sweep
+  int nb = kPivotBlock;           // pivot block of the Gauss-Jordan sweep
 
   // geometry on device
   DevMem m, bx, bxh, by, byh, bz, bzh, Bcoef;
@@ -160,7 +160,13 @@ struct Handle {
 
   // statistics
   double factor_seconds = 0;
-  double factor_flops = 0;
+  double factor_flops = 0;        // LU count of every front (algorithmic)
+  double factor_gj_flops = 0;     // flops the Gauss-Jordan sweep executes
+  // pivot statistics of the last factorization (device: status flag, then
+  // the bit patterns of min and max |pivot|^2 and of max |diagonal entry|^2
+  // of the assembled operator)
+  double pivot_min = 0, pivot_max = 0, diag_max = 0;
+  int zero_pivots = 0;
   long long layer_solves = 0;
   double solve_bytes = 0;
   size_t bytes_factors = 0;
@@ -176,6 +182,13 @@ struct Handle {
   // multi-RHS solve of the layers in `set` on their X buffers (k columns)
   void solve_layers(const LayerSet& set, int k);
   template <typename T> void solve_layers_t(const LayerSet& set, int k);
+  template <typename T> void run_layers_t(const LayerSet& set, int k, const LayerDev* ld,
+                                          void* scr, const TileChoice* tp, bool timing);
+  // the single-layer sets, built with the factors (used without allocation
+  // by the allocation-free local solve)
+  std::vector<const LayerSet*> single_sets;
+  // an existing layer set, or null (no allocation)
+  const LayerSet* find_layer_set(const std::vector<int>& layers) const;
   void upload_layers();
   double solve_elems(const LayerSet& set) const;
 };

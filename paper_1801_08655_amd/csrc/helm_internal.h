@@ -138,9 +138,22 @@ struct LayerPlan {
   long long ub_rows[2] = {0, 0};     // max over same-parity depths of sum b
   std::vector<long long> wt_off, ub_off;  // per front
   long long max_front = 0;
-  double factor_flops = 0;           // real flops of the block elimination
+  double factor_flops = 0;           // real flops of an LU of every front:
+                                     // 4 (2/3 s^3 + 2 s^2 b + 2 s b^2)
+  double gj_flops = 0;               // real flops the blocked Gauss-Jordan
+                                     // sweep executes (skipped tiles excluded)
   double solve_elems = 0;            // factor elements read by one solve
 };
+
+// Pivot block of the factorization's Gauss-Jordan sweep (columns per step).
+constexpr int kPivotBlock = 64;
+
+// Real flops the sweep of one front (s pivots, b boundary variables)
+// executes: per block step of nbf pivots, the rank-nbf update of every
+// 64 x 64 tile it does not skip (tiles inside the pivot rows or columns, and
+// tiles of eliminated rows x boundary columns, whose values are never read
+// again), plus the two products with the inverted pivot block.
+double gj_front_flops(int s, int b, int nb);
 
 struct Geometry {
   int nx = 0, ny = 0, nz = 0;

@@ -13,19 +13,31 @@ struct ReadTerms {
 };
 
 // --- factorization (kernels_factor.hip) -------------------------------------
+// Device record of a factorization: flag set on an exact-zero or non-finite
+// pivot; smallest and largest |pivot|^2 and largest |diagonal entry|^2 of
+// the assembled operator, as the bit patterns of non-negative doubles (which
+// order like the numbers, so integer atomics min / max them).
+struct FactorStatus {
+  int flag;
+  int pad;
+  unsigned long long pmin, pmax, dmax;
+};
 template <typename T>
 void launch_extend_add(const FrontDev* fronts, const int* ids, int n_ids,
                        const int2* tmap, int total, const LayerDev* layers,
                        void* ws0, void* ws1, hipStream_t st);
+// skip_front >= 0: that front is left unassembled (its pivots are then
+// exactly zero), a hook that lets tests reach the zero-pivot status
 template <typename T>
 void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
                          const int2* tmap, int total, const LayerDev* layers,
-                         void* ws0, void* ws1, const GridDev& g, hipStream_t st);
+                         void* ws0, void* ws1, const GridDev& g, int skip_front,
+                         FactorStatus* status, hipStream_t st);
 template <typename T>
 void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_rows,
                   int k, int nb, void* ws0, void* ws1, void* panel,
                   const long long* panel_off, void* D, int* ipiv, int* perm,
-                  const long long* perm_off, int* status, hipStream_t st);
+                  const long long* perm_off, FactorStatus* status, hipStream_t st);
 template <typename T>
 void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
                     const int2* tmap, int total, int k, int nb, void* ws0,
@@ -114,6 +126,8 @@ void launch_scale_cols(double2* y, const double2* x, const double* s, long long 
                        int k, hipStream_t st);
 void launch_add(double2* y, const double2* x, const double2* z, long long n,
                 hipStream_t st);
+// y = z - y in place (elementwise)
+void launch_rsub(double2* y, const double2* z, long long n, hipStream_t st);
 void launch_residual(const GridDev& g, const double2* f, const double2* u,
                      double2* r, int k, hipStream_t st);
 void launch_point_sources(double2* f, const long long* node, const double2* amp,

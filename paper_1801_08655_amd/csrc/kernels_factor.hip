@@ -108,36 +108,50 @@ __global__ void __launch_bounds__(256)
 k_orig_entries(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
                int n_ids, const int2* __restrict__ tmap,
                const LayerDev* __restrict__ layers, void* ws0, void* ws1,
-               GridDev g) {
+               GridDev g, int skip_front, FactorStatus* status) {
   using C = C_t<T>;
   const int2 tm = tmap[blockIdx.x];
   const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
   const int r = tm.y * 256 + threadIdx.x;
-  if (r >= f.s) return;
+  // a front left unassembled on request (exercises the zero-pivot status)
+  const bool valid = r < f.s && ids[a] != skip_front;
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
   C* F = front_ptr<T>(ws0, ws1, f);
-  const int nd = f.off + r;
-  const int nat = L.nd2nat[nd];
   const int nx = g.nx, ny = g.ny;
-  const int x = nat % nx, y = (nat / nx) % ny, z = nat / (nx * ny);
-  const double2 bx = g.bx[x], by = g.by[y], bz = L.bz[z];
-  const double ih2 = 1.0 / (g.h * g.h);
-  const double2 bxy = zmul(bx, by), bxz = zmul(bx, bz), byz = zmul(by, bz);
-  // six couplings: -x, +x, -y, +y, -z, +z
+  int x = 0, y = 0, z = 0;
   double2 cpl[6];
-  cpl[0] = zdiv(g.bxh[x], byz);
-  cpl[1] = zdiv(g.bxh[x + 1], byz);
-  cpl[2] = zdiv(g.byh[y], bxz);
-  cpl[3] = zdiv(g.byh[y + 1], bxz);
-  cpl[4] = zdiv(L.bzh[z], bxy);
-  cpl[5] = zdiv(L.bzh[z + 1], bxy);
-  int zg = L.lo + z;
-  zg = zg < L.s ? L.s : (zg > L.e ? L.e : zg);   // model copied into the local PML
-  const double mm = g.m[(long long)x + (long long)nx * ((long long)y + (long long)ny * zg)];
-  double2 dg = zdiv(make_double2(g.omega * g.omega * mm, 0.0), zmul(bxy, bz));
-  for (int q = 0; q < 6; ++q) { dg.x -= cpl[q].x * ih2; dg.y -= cpl[q].y * ih2; }
+  double2 dg = make_double2(0.0, 0.0);
+  const double ih2 = 1.0 / (g.h * g.h);
+  if (valid) {
+    const int nat = L.nd2nat[f.off + r];
+    x = nat % nx; y = (nat / nx) % ny; z = nat / (nx * ny);
+    const double2 bx = g.bx[x], by = g.by[y], bz = L.bz[z];
+    const double2 bxy = zmul(bx, by), bxz = zmul(bx, bz), byz = zmul(by, bz);
+    // six couplings: -x, +x, -y, +y, -z, +z
+    cpl[0] = zdiv(g.bxh[x], byz);
+    cpl[1] = zdiv(g.bxh[x + 1], byz);
+    cpl[2] = zdiv(g.byh[y], bxz);
+    cpl[3] = zdiv(g.byh[y + 1], bxz);
+    cpl[4] = zdiv(L.bzh[z], bxy);
+    cpl[5] = zdiv(L.bzh[z + 1], bxy);
+    int zg = L.lo + z;
+    zg = zg < L.s ? L.s : (zg > L.e ? L.e : zg);   // model copied into the local PML
+    const double mm = g.m[(long long)x + (long long)nx * ((long long)y + (long long)ny * zg)];
+    dg = zdiv(make_double2(g.omega * g.omega * mm, 0.0), zmul(bxy, bz));
+    for (int q = 0; q < 6; ++q) { dg.x -= cpl[q].x * ih2; dg.y -= cpl[q].y * ih2; }
+  }
+  {
+    // largest |diagonal entry|^2 of the operator: a wave-wide maximum, then
+    // one atomic per wave (bit patterns of non-negative doubles order like
+    // the numbers)
+    double d2 = dg.x * dg.x + dg.y * dg.y;
+    for (int off = 32; off > 0; off >>= 1) d2 = fmax(d2, __shfl_xor(d2, off));
+    if ((threadIdx.x & 63) == 0 && d2 > 0.0)
+      atomicMax(&status->dmax, (unsigned long long)__double_as_longlong(d2));
+  }
+  if (!valid) return;
   {
     C& d = F[(long long)r + (long long)r * n];
     d = cadd(d, from_d2<C>(dg));
@@ -189,7 +203,7 @@ __global__ void __launch_bounds__(NT)
 k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
         int k, int nb, void* ws0, void* ws1, void* panel_base,
         const long long* __restrict__ panel_off, void* D_base, int* ipiv_base,
-        int* perm_base, const long long* __restrict__ perm_off, int* status) {
+        int* perm_base, const long long* __restrict__ perm_off, FactorStatus* status) {
   using C = C_t<T>;
   constexpr int NW = NT / 64;
   constexpr bool LDSP = PR > 0;
@@ -215,6 +229,8 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   __shared__ double red_v[NW];
   __shared__ int red_i[NW];
   __shared__ int piv_row;
+  // smallest and largest |pivot|^2 of this panel (thread 0)
+  double pv_min = INFINITY, pv_max = 0.0;
   __syncthreads();
   // Blocked right-looking LU of the panel: columns in blocks of PB; inside
   // a block every column is pivoted, scaled and applied to the block's
@@ -252,8 +268,11 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
             bidx = red_i[w];
           }
         if (!(bv > 0.0) || !isfinite(bv)) {
-          atomicExch(status, 1);   // zero or non-finite pivot
+          atomicExch(&status->flag, 1);   // zero or non-finite pivot
           bidx = c;
+        } else {
+          pv_min = fmin(pv_min, bv);
+          pv_max = fmax(pv_max, bv);
         }
         piv_row = bidx;
         ipiv[c] = bidx;
@@ -317,6 +336,10 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       }
     }
     __syncthreads();
+  }
+  if (t == 0 && pv_max > 0.0) {
+    atomicMin(&status->pmin, (unsigned long long)__double_as_longlong(pv_min));
+    atomicMax(&status->pmax, (unsigned long long)__double_as_longlong(pv_max));
   }
   // D = U^-1 L^-1 of the leading nbf x nbf block, in LDS: X = L^-1 by
   // eliminating below each unit pivot, then D = U^-1 X from the last row up.
@@ -479,7 +502,12 @@ k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // rank-nb update of every entry outside the pivot rows / columns J:
 //   F(O, O) -= F(O, J) F(J, O)     (J rows already hold D * F(J, O))
 // Computed as C^T = B^T A^T so that the MFMA column index walks the
-// contiguous (row) dimension of the column-major front.
+// contiguous (row) dimension of the column-major front.  Entries of rows
+// already eliminated (< k) in boundary columns (>= s) are skipped: they
+// would accumulate F11^-1 F12, which neither the factor store (the
+// symmetric operator's backward step uses the transpose of -F21 F11^-1) nor
+// the parent's extend-add (the Schur block) ever reads.  Tiles that lie
+// wholly in J or in that block return at once.
 // --------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
@@ -495,8 +523,10 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int nbf = (f.s - k) < nb ? (f.s - k) : nb;
   const int nt = (n + GT - 1) / GT;
   const int tile = tm.y;
-  const int i0 = (tile % nt) * GT;   // C rows
-  const int j0 = (tile / nt) * GT;   // C columns
+  const int i0 = (tile % nt) * GT;   // rows of F
+  const int j0 = (tile / nt) * GT;   // columns of F
+  const bool rowsJ = i0 >= k && i0 + GT <= k + nbf, colsJ = j0 >= k && j0 + GT <= k + nbf;
+  if (rowsJ || colsJ || (i0 + GT <= k && j0 >= f.s)) return;   // uniform per block
   C* F = front_ptr<T>(ws0, ws1, f);
   // P rows = C columns j: B^T(j, q) = F[(k+q) + j n]
   View<T> pv{F + k, (long long)n, 1, n, nbf};
@@ -509,7 +539,8 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   using O = LaneOut<T, 64, 64>;
   const O o;
   auto outside = [&](int gi, int gj) {
-    return gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf);
+    return gi < n && gj < n && (gi < k || gi >= k + nbf) && (gj < k || gj >= k + nbf) &&
+           !(gi < k && gj >= f.s);
   };
   C cv[O::NR][O::NC];
 #pragma unroll
@@ -636,16 +667,17 @@ void launch_extend_add(const FrontDev* fronts, const int* ids, int n_ids,
 template <typename T>
 void launch_orig_entries(const FrontDev* fronts, const int* ids, int n_ids,
                          const int2* tmap, int total, const LayerDev* layers,
-                         void* ws0, void* ws1, const GridDev& g, hipStream_t st) {
+                         void* ws0, void* ws1, const GridDev& g, int skip_front,
+                         FactorStatus* status, hipStream_t st) {
   if (total <= 0) return;
   hipLaunchKernelGGL(k_orig_entries<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_ids, tmap, layers, ws0, ws1, g);
+                     n_ids, tmap, layers, ws0, ws1, g, skip_front, status);
 }
 template <typename T>
 void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_rows,
                   int k, int nb, void* ws0, void* ws1, void* panel,
                   const long long* panel_off, void* D, int* ipiv, int* perm,
-                  const long long* perm_off, int* status, hipStream_t st) {
+                  const long long* perm_off, FactorStatus* status, hipStream_t st) {
   if (n_active <= 0) return;
   // threads and panel home from the tallest panel of the launch
 #define HELM_PANEL(NT, PR)                                                          \
@@ -701,10 +733,11 @@ void launch_store_factor(const FrontDev* fronts, const int* ids, int n_ids,
                                      hipStream_t);                                 \
   template void launch_orig_entries<T>(const FrontDev*, const int*, int,          \
                                        const int2*, int, const LayerDev*, void*,    \
-                                       void*, const GridDev&, hipStream_t);        \
+                                       void*, const GridDev&, int, FactorStatus*,   \
+                                       hipStream_t);                                \
   template void launch_panel<T>(const FrontDev*, const int*, int, int, int, int, void*, \
                                 void*, void*, const long long*, void*, int*, int*, \
-                                const long long*, int*, hipStream_t);              \
+                                const long long*, FactorStatus*, hipStream_t);     \
   template void launch_swap_JO<T>(const FrontDev*, const int*, int, const int2*,    \
                                   int, int, int, void*, void*, const void*,        \
                                   const int*, const long long*, const long long*,  \

@@ -303,6 +303,16 @@ __global__ void k_add(double2* __restrict__ y, const double2* __restrict__ x,
   }
 }
 
+// y = z - y in place: each element is read and written by one thread, so y
+// is the only pointer that aliases nothing else
+__global__ void k_rsub(double2* y, const double2* __restrict__ z, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double2 a = y[e], b = z[e];
+    y[e] = make_double2(b.x - a.x, b.y - a.y);
+  }
+}
+
 // FP64 residual r = f - H u on the global grid (volumes RHS-major); f may be
 // null (then r = H u).  Same operator as the local assembly.
 __global__ void __launch_bounds__(256)
@@ -480,6 +490,9 @@ void launch_scale_cols(double2* y, const double2* x, const double* s, long long 
 void launch_add(double2* y, const double2* x, const double2* z, long long n,
                 hipStream_t st) {
   hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(256), 0, st, y, x, z, n);
+}
+void launch_rsub(double2* y, const double2* z, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_rsub, dim3(grid_for(n)), dim3(256), 0, st, y, z, n);
 }
 void launch_residual(const GridDev& g, const double2* f, const double2* u,
                      double2* r, int k, hipStream_t st) {

@@ -449,11 +449,7 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
   }
   if (up) {
     // x_down = b_down - K_down x_up (the down half holds K_down x_up)
-    std::vector<double> minus(k, -1.0);
-    HELM_HIP(hipMemcpyAsync(scale.p, minus.data(), k * sizeof(double), hipMemcpyHostToDevice,
-                            H.st));
-    kern::launch_scale_cols(x, x, scale.as<double>(), V / 2, k, H.st);
-    kern::launch_add(x, x, b, Vp, H.st);
+    kern::launch_rsub(x, b, Vp, H.st);
     HELM_HIP(hipStreamSynchronize(H.st));
   }
   last_resid = resid;
@@ -600,7 +596,7 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
                             H.st));
     int steps = 0;
     status = HELM_ENOCONV;
-    std::vector<double> dprev(k, 0.0);
+    std::vector<RefineTrack> track(k);
     StepNorms nm;
     for (int it = 0; it < std::max(1, o.ir_max_steps); ++it) {
       int it0 = info ? info->gmres_iters : 0;
@@ -611,20 +607,20 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
       double mx = 0, emx = 0;
       for (int c = 0; c < k; ++c) {
         mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
-        double est = refinement_error(it, dprev[c], nm.dn[c], nm.un[c]);
+        double est = refinement_error(it, track[c], nm.dn[c], nm.un[c]);
         emx = std::max(emx, est);
         est_c[c] = est;
         if (col_iters.size() == (size_t)k) iters_c[c] += col_iters[c];
-        const bool met = rel[c] <= o.ir_tol || (o.err_target > 0 && est <= o.err_target);
-        if (steps_c[c] == 0 && met) steps_c[c] = steps;
+        if (steps_c[c] == 0 && refinement_met(rel[c], est, o)) steps_c[c] = steps;
       }
-      dprev = nm.dn;
       if (info && it < 8) {
         info->ir_residual[it] = std::max(info->ir_residual[it], mx);
         info->ir_gmres_iters[it] = std::max(info->ir_gmres_iters[it], info->gmres_iters - it0);
       }
       if (info) info->est_error_max = emx;
-      if (mx <= o.ir_tol || (o.err_target > 0 && emx <= o.err_target)) {
+      bool all = true;
+      for (int c = 0; c < k; ++c) all = all && refinement_met(rel[c], est_c[c], o);
+      if (all) {
         status = HELM_OK;
         break;
       }
@@ -649,23 +645,41 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
 }
 
 // Error of the refined column after step `step` (0-based), estimated from
-// the contraction of the corrections: with q = |d_k| / |d_{k-1}| the
-// remaining error is about |d_k| q / (1 - q) relative to |u|.  Unknown
-// (1) after the first step.
-double refinement_error(int step, double dprev, double dcur, double unorm) {
+// the contraction of the corrections.  The correction of step k
+// approximates the error before it, so q_k = |d_k| / |d_{k-1}| measures the
+// contraction of the previous step; if the current step contracts by no
+// more than q, the remaining error is at most |d_k| q / (1 - q) relative to
+// |u|.  Guards: q is the larger of the last two measured ratios (from the
+// third step on), and an estimate with q > 1/2 (slow or erratic
+// contraction) is not trusted (reported as 1, unknown).  Unknown (1) after
+// the first step.
+double refinement_error(int step, RefineTrack& tr, double dcur, double unorm) {
+  const double dprev = tr.dprev, qprev = tr.qprev;
+  tr.dprev = dcur;
   if (unorm == 0) return 0.0;
   if (step == 0 || dprev <= 0) return 1.0;
-  double q = std::min(dcur / dprev, 0.99);
+  const double qk = dcur / dprev;
+  tr.qprev = qk;
+  const double q = step >= 2 ? std::max(qk, qprev) : qk;
+  if (!(q <= 0.5)) return 1.0;
   return dcur / unorm * q / (1.0 - q);
 }
 
+bool refinement_met(double rel, double est, const helm_options& o) {
+  return rel <= o.ir_tol || (o.err_target > 0 && est <= 0.5 * o.err_target);
+}
+
+// Restart length: the caller's gmres_restart when set, capped by what device
+// memory holds (basis vectors of 2 pair vectors x k columns each) and by 60.
 int Method::gmres_restart(int max_iter) const {
-  // bounded by memory: basis vectors of 2 pair vectors x k columns each
+  const int asked = H.opt.gmres_restart > 0 ? std::min(H.opt.gmres_restart, 60) : 60;
   size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return std::min(max_iter, 16);
-  size_t per = (size_t)2 * Vp * sizeof(double2);
-  size_t fit = per ? (size_t)(0.6 * free_b) / per : 64;
-  int m = (int)std::min<size_t>(fit > 3 ? fit - 3 : 1, 60);
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+    return std::max(1, std::min({max_iter, asked, 16}));
+  // vectors already allocated need no new memory
+  const size_t per = (size_t)2 * Vp * sizeof(double2);
+  const size_t fit = (per ? (size_t)(0.6 * free_b) / per : 64) + basis.size();
+  const int m = (int)std::min<size_t>(fit > 3 ? fit - 3 : 1, (size_t)asked);
   return std::max(1, std::min(max_iter, m));
 }
 

@@ -65,6 +65,16 @@ struct Method {
   int gmres_restart(int max_iter) const;
 };
 
-double refinement_error(int step, double dprev, double dcur, double unorm);
+// Per-column record of the refinement's corrections for the error estimate.
+struct RefineTrack {
+  double dprev = 0;   // |d| of the previous step
+  double qprev = 0;   // contraction ratio measured at the previous step
+};
+// Estimated relative error |u - H^-1 f| / |u| after a step whose correction
+// has norm dcur (see method.cpp); updates the record.
+double refinement_error(int step, RefineTrack& tr, double dcur, double unorm);
+// Whether a column may stop: FP64 residual at ir_tol, or estimated error at
+// most half of err_target (a factor-2 margin against the estimate).
+bool refinement_met(double rel, double est, const helm_options& o);
 
 }  // namespace helm

@@ -80,7 +80,7 @@ void Server::run_lane(Lane& ln) {
       for (int s = ln.occupied(); s < ln.K && !ln.queue.empty(); ++s) {
         Request* r = ln.queue.front();
         const int c = r->next_col++;
-        ln.slots[s] = Slot{r, c, 0, 0.0};
+        ln.slots[s] = Slot{r, c, 0, RefineTrack{}};
         if (r->info.t_first_ms < 0) r->info.t_first_ms = wall_ms() - t0;
         ln.node_h[s] = r->nodes[c];
         ln.amp_h[s] = r->amps[c];
@@ -126,8 +126,7 @@ void Server::run_lane(Lane& ln) {
         Slot& sl = ln.slots[s];
         const int st = sl.steps++;
         const double rel = nm.rel[s];
-        const double est = fp64 ? 0.0 : refinement_error(st, sl.dprev, nm.dn[s], nm.un[s]);
-        sl.dprev = nm.dn[s];
+        const double est = fp64 ? 0.0 : refinement_error(st, sl.track, nm.dn[s], nm.un[s]);
         bool f;
         int status = HELM_OK;
         if (fp64) {
@@ -136,7 +135,7 @@ void Server::run_lane(Lane& ln) {
           if (H.G.L > 1 && !(M.last_resid.size() > (size_t)s && M.last_resid[s] <= H.opt.gmres_tol))
             status = HELM_ENOCONV;
         } else {
-          const bool ok = rel <= H.opt.ir_tol || (H.opt.err_target > 0 && est <= H.opt.err_target);
+          const bool ok = refinement_met(rel, est, H.opt);
           f = ok || sl.steps >= std::max(1, H.opt.ir_max_steps);
           if (!ok) status = HELM_ENOCONV;
         }

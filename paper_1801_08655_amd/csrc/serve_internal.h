@@ -32,7 +32,7 @@ struct Slot {
   Request* req = nullptr;
   int col = -1;
   int steps = 0;
-  double dprev = 0;
+  RefineTrack track;
 };
 
 struct Lane {

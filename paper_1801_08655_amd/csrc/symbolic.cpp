@@ -110,6 +110,27 @@ struct NDBuilder {
 
 }  // namespace
 
+double gj_front_flops(int s, int b, int nb) {
+  const int n = s + b, T = 64;
+  const int nt = (n + T - 1) / T;
+  double fl = 0;
+  for (int k = 0; k < s; k += nb) {
+    const int nbf = std::min(nb, s - k);
+    for (int ti = 0; ti < nt; ++ti) {
+      const int i0 = ti * T, ri = std::min(T, n - i0);
+      const bool rowsJ = i0 >= k && i0 + T <= k + nbf, rowsDone = i0 + T <= k;
+      for (int tj = 0; tj < nt; ++tj) {
+        const int j0 = tj * T, cj = std::min(T, n - j0);
+        const bool colsJ = j0 >= k && j0 + T <= k + nbf;
+        if (rowsJ || colsJ || (rowsDone && j0 >= s)) continue;
+        fl += 8.0 * nbf * ri * cj;
+      }
+    }
+    fl += 2.0 * 8.0 * n * (double)nbf * nbf;
+  }
+  return fl;
+}
+
 void build_layer_plan(LayerPlan& P, int nx, int ny, int leaf) {
   const int t = P.t;
   P.n_loc = nx * ny * t;
@@ -187,6 +208,7 @@ void build_layer_plan(LayerPlan& P, int nx, int ny, int leaf) {
   P.fac_off.assign(nf, 0);
   long long acc = 0;
   P.factor_flops = 0;
+  P.gj_flops = 0;
   P.solve_elems = 0;
   P.max_front = 0;
   P.max_depth = 0;
@@ -194,8 +216,9 @@ void build_layer_plan(LayerPlan& P, int nx, int ny, int leaf) {
     const FrontHost& F = P.fronts[f];
     P.fac_off[f] = acc;
     acc += (long long)(F.s + F.b) * F.s;
-    double n = F.s + F.b;
-    P.factor_flops += 8.0 * n * n * F.s;
+    const double ss = F.s, bb = F.b;
+    P.factor_flops += 4.0 * (2.0 / 3.0 * ss * ss * ss + 2.0 * ss * ss * bb + 2.0 * ss * bb * bb);
+    P.gj_flops += gj_front_flops(F.s, F.b, kPivotBlock);
     P.solve_elems += (double)F.s * F.s + 2.0 * F.s * F.b;
     P.max_front = std::max<long long>(P.max_front, F.s + F.b);
     P.max_depth = std::max(P.max_depth, F.depth);
