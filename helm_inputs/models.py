@@ -211,6 +211,13 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     # the headline recipe shrunk until the oracle's direct solve takes seconds
     "layered-32": lambda: _wl_layered(n=32, pml=5, L=4, alpha=3, n_side=8,
                                        depth=6, ppw=8.0, name="layered-32"),
+    # the largest grids the oracle's direct solve handles in about half a
+    # minute, with many thin layers (L = 8: 3 or 4 interior planes each) and
+    # with the smooth recipe at L = 4
+    "layered-40": lambda: _wl_layered(n=40, pml=5, L=8, alpha=3, n_side=2,
+                                       depth=6, ppw=8.0, name="layered-40"),
+    "smooth-40": lambda: _wl_smooth(n=40, pml=5, L=4, alpha=4, sigma=3.0,
+                                     src_depth=9, name="smooth-40"),
 }
 
 
