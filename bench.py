@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--fp64-warmup", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fp64-loose-tol", type=float, default=1e-7,
+                    help="GMRES tolerance of the FP64 run at the mixed path's accuracy")
+    ap.add_argument("--inner-tol", type=float, default=1e-3,
+                    help="GMRES tolerance of the first mixed-precision solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", default=True,
                     help="time kernel classes with HIP events (roofline)")
@@ -155,7 +159,9 @@ def small_k_probe(s, wl, torch, layer=5, reps=3):
 
 def cpu_baseline():
     """The oracle (global sparse assembly + SuperLU direct solve, complex128)
-    on the same workload recipe at the largest grid it finishes in ~15 s."""
+    on the same workload recipe at the largest grid it finishes in ~15 s.
+    Returns the record and the oracle's solution (for the same-input GPU
+    comparison)."""
     import numpy as np
     from helm_inputs import workload
     from oracle.direct import SparseLU
@@ -177,13 +183,51 @@ def cpu_baseline():
     except Exception:
         cores = os.cpu_count() or 1
     return {"value": R / (t2 - t0), "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "value_solve_only": R / (t2 - t1),
+            "value_solve_only": R / (t2 - t1), "workload": wl.name,
+            "factor_s": t1 - t0, "solve_s": t2 - t1,
             "sample": f"oracle global direct solve (scipy SuperLU with threaded BLAS, "
                       f"complex128) of the {wl.n[0]}^3 layered-dipping workload of "
                       f"the same recipe (8 ppw, {wl.pml}-pt PML) with R={R} surface "
                       f"point sources; assembly+factorization {t1 - t0:.1f}s, solves "
                       f"{t2 - t1:.1f}s; value = R / (factorization + solves). The "
-                      "oracle cannot factor the 200^3 grid on the host in bounded time."}
+                      "oracle cannot factor the 200^3 grid on the host in bounded time."}, U
+
+
+def same_input_gpu(pt, torch, U_oracle):
+    """The GPU path on the oracle's own input (the layered recipe at 32^3, all
+    of its sources), both precisions: RHS/s including the factorization (as
+    the oracle's value) and for the solves alone, and each column's error
+    against the oracle's solution."""
+    import numpy as np
+    from helm_inputs import workload
+    wl = workload("layered-32")
+    out = {"workload": wl.name, "rhs": len(wl.sources)}
+    R = len(wl.sources)
+    for prec in ("mixed", "fp64"):
+        kw = dict(gmres_tol=1e-10) if prec == "fp64" else dict(
+            ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4, err_target=1e-6,
+            ir_max_steps=4)
+        # one untimed run first: code objects loaded, device warm
+        s = pt.Solver(wl.m(), wl.h, wl.omega, wl.pml, wl.n_layers, precision=prec,
+                      pml_local=wl.pml_local, pml_C=wl.pml_C, **kw)
+        s.solve_points(wl.sources)
+        s.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = pt.Solver(wl.m(), wl.h, wl.omega, wl.pml, wl.n_layers, precision=prec,
+                      pml_local=wl.pml_local, pml_C=wl.pml_C, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u = s.solve_points(wl.sources)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        uh = u.cpu().numpy().reshape(R, -1).T
+        err = np.linalg.norm(uh - U_oracle, axis=0) / np.linalg.norm(U_oracle, axis=0)
+        out[prec] = {"value": R / (t2 - t0), "value_solve_only": R / (t2 - t1),
+                     "factor_s": t1 - t0, "solve_s": t2 - t1,
+                     "err_vs_oracle_max": float(err.max())}
+        s.close()
+    return out
 
 
 def serve_bench(args, torch, pt):
@@ -380,30 +424,44 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    # the factorizations and the one-column probe time every kernel class;
-    # the timed steps time only the forward substitution GEMM launches (the
-    # roofline's kernel), so that the other kernels run without events
+    # The factorizations and the one-column probe time every kernel class.
+    # The timed steps run with the default flags (substitution sequences
+    # replayed from captured HIP graphs, no timing events); a separate step
+    # after them times the forward substitution GEMM launches (the roofline's
+    # kernel) with events, launch by launch.
     tune = 0 if args.no_autotune else pt._lib.HELM_FLAG_AUTOTUNE
     flags = (pt._lib.HELM_FLAG_PROFILE if args.profile else 0) | tune
-    step_flags = (pt._lib.HELM_FLAG_PROFILE_FWD if args.profile else 0) | tune
+    step_flags = tune
+    prof_flags = (pt._lib.HELM_FLAG_PROFILE_FWD if args.profile else 0) | tune
     common = dict(pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64, flags=flags)
+    mixed_kw = dict(ir_tol=1e-10, inner_tol=args.inner_tol, inner_tol_refine=1e-4,
+                    err_target=1e-6, ir_max_steps=4)
     extra = {}
 
     log(f"[mixed] factorize {wl.name}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
-                  ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4, err_target=1e-6,
-                  ir_max_steps=4, **common)
+                  **mixed_kw, **common)
     torch.cuda.synchronize()
     factor_s = time.perf_counter() - t0
     log(f"[mixed] factorized in {factor_s:.2f}s; warmup {args.warmup}, steps {args.steps}")
     fstats = s.kernel_stats(reset=True)
+    finfo = s.factor_info()
     s.set_options(flags=step_flags)
     u, info, total, lat = timed_solves(s, srcs, args.steps, args.warmup, torch)
+    value = R * args.steps / total
+    log(f"[mixed] {value:.2f} RHS/s ({1e3 * total / args.steps:.0f} ms per step)")
+    # the profiled step (forward GEMM launches timed one by one)
+    s.set_options(flags=prof_flags)
+    s.kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    u, _ = s.solve_points(srcs, info=True, out=u)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - tp
     kstats = s.kernel_stats()
     s.set_options(flags=flags)
-    value = R * args.steps / total
     # the same step with the 64 solution volumes handed back to host memory
     # (pinned): the PCIe-inclusive rate, reported beside the HBM-resident one
     u_host = torch.empty(u.shape, dtype=u.dtype, pin_memory=True)
@@ -415,6 +473,7 @@ def main():
             "rhs_per_s": R / (total / args.steps + t_copy)}
     rl = roofline({k: v for k, v in kstats.items() if k.startswith("solve_")}, "mixed",
                   wl.name)
+    rl["profiled_step_ms"] = 1e3 * tp
     small = small_k_probe(s, wl, torch)
     s.close()
     del s
@@ -425,6 +484,7 @@ def main():
     # after a ~130 GB release takes seconds of host time)
     u_ref = None
     fp64 = None
+    fp64_loose = None
     if not args.no_fp64:
         log(f"[fp64] factorize {wl.name}")
         torch.cuda.synchronize()
@@ -435,15 +495,26 @@ def main():
         f64_factor = time.perf_counter() - t0
         log(f"[fp64] factorized in {f64_factor:.2f}s; solving R={R}")
         extra["fp64_factor_kernels"] = s64.kernel_stats(reset=True)
+        extra["fp64_factor_info"] = s64.factor_info()
         s64.set_options(flags=step_flags)
         u_ref, info64, tot64, lat64 = timed_solves(s64, srcs, args.fp64_steps,
                                                    args.fp64_warmup, torch)
         fp64 = {"value": R * args.fp64_steps / tot64, "factor_s": f64_factor,
+                "gmres_tol": 1e-10,
                 "ms_per_step": 1e3 * tot64 / args.fp64_steps,
                 "gmres_iters": info64["gmres_iters"],
                 "rel_residual_max": info64["rel_residual_max"]}
-        extra["fp64_kernels"] = s64.kernel_stats()
         log(f"[fp64] {fp64}")
+        # the FP64 path stopped as soon as its error meets the mixed path's
+        # target: the speed-up of the precision alone, at equal accuracy
+        s64.set_options(gmres_tol=args.fp64_loose_tol)
+        u_l, info_l, tot_l, _ = timed_solves(s64, srcs, 1, 0, torch)
+        d = (u_l - u_ref).reshape(R, -1).norm(dim=1) / u_ref.reshape(R, -1).norm(dim=1)
+        fp64_loose = {"value": R / tot_l, "gmres_tol": args.fp64_loose_tol,
+                      "gmres_iters": info_l["gmres_iters"],
+                      "err_vs_fp64_max": float(d.max())}
+        log(f"[fp64 loose] {fp64_loose}")
+        del u_l
         s64.close()
         del s64
         torch.cuda.empty_cache()
@@ -454,10 +525,25 @@ def main():
         d = (u - u_ref).reshape(R, -1).norm(dim=1) / u_ref.reshape(R, -1).norm(dim=1)
         err = float(d.max())
         del u, u_host, u_ref
+        torch.cuda.empty_cache()
     rl["attainable_peak"] = attain["mfma_f32_tflops"]
     rl["frac_of_attainable"] = rl["achieved"] / attain["mfma_f32_tflops"]
     for name in ("solve_fwd_gemm", "solve_bwd_gemm"):
         small[name]["frac_of_attainable_read"] = small[name]["GB/s"] / attain["hbm_read_gbps"]
+    # factorization: the LU count over the time of every factor kernel
+    fk_ms = sum(v["total_ms"] for k, v in fstats.items() if k.startswith("factor_"))
+    sw = fstats.get("factor_sweep_gemm", {})
+    factor_roofline = {
+        "lu_flops": finfo["lu_flops"], "gj_flops_executed": finfo["gj_flops"],
+        "kernel_s": fk_ms * 1e-3,
+        "achieved_tflops": finfo["lu_flops"] / max(fk_ms * 1e-3, 1e-12) / 1e12,
+        "frac": finfo["lu_flops"] / max(fk_ms * 1e-3, 1e-12) / PEAK["fp32_mfma"],
+        "executed_tflops": finfo["gj_flops"] / max(fk_ms * 1e-3, 1e-12) / 1e12,
+        "sweep_gemm_s": sw.get("total_ms", 0.0) * 1e-3,
+        "sweep_gemm_lu_share_tflops": sw.get("flops", 0.0) / max(sw.get("total_ms", 0.0)
+                                                                 * 1e-3, 1e-12) / 1e12,
+        "pivot_min": finfo["pivot_min"], "pivot_max": finfo["pivot_max"],
+        "pivot_growth": finfo["pivot_growth"]}
     out = {
         "metric": METRIC,
         "value": value,
@@ -479,7 +565,11 @@ def main():
         "err_vs_fp64_max": err,
         "fp64": fp64,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "fp64_at_matched_accuracy": fp64_loose,
+        "speedup_vs_fp64_matched_accuracy": (value / fp64_loose["value"]) if fp64_loose
+        else None,
         "factor_s": factor_s,
+        "factor": factor_roofline,
         "gmres_iters": info["gmres_iters"],
         "ir_steps": info["ir_steps"],
         "rel_residual_max": info["rel_residual_max"],
@@ -497,7 +587,13 @@ def main():
     out.update(extra)
     if not args.no_cpu_baseline:
         log("[cpu] oracle baseline")
-        out["cpu_baseline"] = cpu_baseline()
+        cb, U32 = cpu_baseline()
+        out["cpu_baseline"] = cb
+        log("[gpu] the oracle's input on the GPU")
+        same = same_input_gpu(pt, torch, U32)
+        same["mixed_over_oracle"] = same["mixed"]["value"] / cb["value"]
+        same["fp64_over_oracle"] = same["fp64"]["value"] / cb["value"]
+        out["same_input"] = same
     print(json.dumps(out), flush=True)
 
 
