@@ -15,11 +15,13 @@ Everything here is plain NumPy/SciPy in complex128:
   (dense LAPACK solve for tiny grids, SuperLU otherwise);
 * ``polarized`` -- the method itself on the CPU, step by step in the paper's
   order (Algorithms 1-10), with an unfused preconditioner and a textbook
-  GMRES; used to pin intermediate operators (sweeps, reflections, traces).
+  GMRES (or Bi-CGSTAB); used to pin intermediate operators (sweeps,
+  reflections, traces); also the unpolarized SIE of Algorithms 2-3;
+* ``gmres``, ``bicgstab`` -- textbook Krylov iterations.
 
 Readings of silent or garbled passages are listed in the module docstrings
 that use them.  Functions whose results are not pinned by an independent
 check say "parity unpinned" in their docstring.
 """
 
-from . import discretization, direct, polarized, gmres  # noqa: F401
+from . import discretization, direct, polarized, gmres, bicgstab  # noqa: F401

@@ -50,6 +50,7 @@ from typing import List
 
 import numpy as np
 
+from .bicgstab import bicgstab
 from .discretization import Problem, layers, local_operator
 from .direct import SparseLU
 from .gmres import gmres
@@ -229,8 +230,11 @@ class PolarizedTraces:
         return u
 
     def solve(self, f: np.ndarray, tol: float = 1e-10, restart: int = 60,
-              maxiter: int = 200):
-        """u for the volume source f[k, j, i]; returns (u, iterations, history)."""
+              maxiter: int = 200, krylov: str = "gmres"):
+        """u for the volume source f[k, j, i]; returns (u, iterations, history).
+        krylov: "gmres" (Eq. precond_polarized_SIE solved by GMRES, as in the
+        experiments) or "bicgstab" (the memory-lean alternative the paper
+        names); both on the same left-preconditioned polarized system."""
         f = np.asarray(f, dtype=np.complex128)
         if self.L == 1:
             return self.G(0, f.copy()), 0, [0.0]
@@ -249,7 +253,67 @@ class PolarizedTraces:
 
         pd, pu = self.precondition(fd, fu)
         b = np.concatenate([pd.ravel(), pu.ravel()])
-        x, iters, hist = gmres(PM, b, tol=tol, restart=restart, maxiter=maxiter)
+        if krylov == "bicgstab":
+            x, iters, hist = bicgstab(PM, b, tol=tol, maxiter=maxiter)
+        else:
+            x, iters, hist = gmres(PM, b, tol=tol, restart=restart, maxiter=maxiter)
         ud, uu = split(x)
         traces = ud + uu
         return self.reconstruct(f, traces), iters, hist
+
+    # ------------------------------------------------------------------
+    # the unpolarized surface integral equation (Eq. SIE, Algorithms 2-3)
+    # ------------------------------------------------------------------
+    # Reading (G12, G13): the Green's representation restricted to the
+    # layer's own interface planes gives, for the exact traces u,
+    #   a_j = [G^j (f^j + J_top^j(u_{j-1}) + J_bot^j(u_j))](e_j),
+    #   b_j = [G^{j+1} (f^{j+1} + J_top^{j+1}(u_j) + J_bot^{j+1}(u_{j+1}))](s_{j+1}),
+    # i.e. (I - GJ) u = v with v_j = ([G^j f^j](e_j), [G^{j+1} f^{j+1}](s_{j+1})).
+    # Algorithm 3 applies GJ - I and Algorithm 2 pairs it with +v, which is
+    # inconsistent in sign; the consistent system (I - GJ) u = v is solved.
+    # The index typos of Algorithm 3 (layer 1's planes) are read as the
+    # layer's own first and last bulk planes.
+    def sie_rhs(self, f: np.ndarray) -> np.ndarray:
+        """v of the unpolarized SIE: local solves of the partitioned source read
+        on each layer's own interface planes (lines 2-8 of Algorithm 2)."""
+        v = self.zero_pairs()
+        for l, g in enumerate(self.geo):
+            w = self.G(l, self.restrict_source(l, f))
+            if l <= self.L - 2:
+                v[l][0] = w[g.local(g.e)]
+            if l >= 1:
+                v[l - 1][1] = w[g.local(g.s)]
+        return v
+
+    def apply_sie(self, x: np.ndarray) -> np.ndarray:
+        """(I - GJ) x: every layer solves its two interface sources (all layers
+        independent, Algorithm 3) and is read on its own interface planes."""
+        y = x.copy()
+        for l, g in enumerate(self.geo):
+            src = self.zeros_local(l)
+            if l >= 1:
+                self.add_J_top(l, src, x[l - 1])
+            if l <= self.L - 2:
+                self.add_J_bot(l, src, x[l])
+            w = self.G(l, src)
+            if l <= self.L - 2:
+                y[l][0] -= w[g.local(g.e)]
+            if l >= 1:
+                y[l - 1][1] -= w[g.local(g.s)]
+        return y
+
+    def solve_unpolarized(self, f: np.ndarray, tol: float = 1e-10, restart: int = 60,
+                          maxiter: int = 400):
+        """u by GMRES on the unpolarized SIE (no preconditioner), then the
+        reconstruction of Algorithm 2; returns (u, iterations, history)."""
+        f = np.asarray(f, dtype=np.complex128)
+        if self.L == 1:
+            return self.G(0, f.copy()), 0, [0.0]
+        v = self.sie_rhs(f)
+        shape = v.shape
+
+        def A(x):
+            return self.apply_sie(x.reshape(shape)).ravel()
+
+        x, iters, hist = gmres(A, v.ravel(), tol=tol, restart=restart, maxiter=maxiter)
+        return self.reconstruct(f, x.reshape(shape)), iters, hist
