@@ -66,6 +66,15 @@ extern "C" {
                                 launches, each with start and stop events
                                 that the launch itself records; the other
                                 kernels run without events between them     */
+#define HELM_FLAG_BICGSTAB 64  /* Bi-CGSTAB instead of GMRES on the preconditioned
+                                polarized system (the memory-lean Krylov method
+                                named in Section "Method of Polarized traces":
+                                six work vectors per column, two operator
+                                applications per iteration)                   */
+#define HELM_FLAG_UNPOLARIZED 128 /* GMRES on the unpolarized SIE (Eq. "SIE",
+                                Algorithms 2-3, sign made consistent: (I - GJ) u
+                                = v) without preconditioner: every iteration
+                                is one batched solve of all layers at once    */
 #define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
                                 the factorization leaves one leaf front of
                                 layer 0 unassembled, so its pivots are exactly
@@ -96,7 +105,8 @@ typedef struct {
   double inner_tol_refine; /* mixed: GMRES tolerance of later refinement steps
                               (<= 0: same as inner_tol)                      */
   double err_target;       /* mixed: also stop once the estimated error of
-                              every column is below this (<= 0: off)         */
+                              every column is at most half of this (a factor
+                              2 margin against the estimate; <= 0: off)      */
   size_t hbm_budget_bytes; /* 0 = 90% of free device memory                  */
   int    device;           /* HIP device ordinal                             */
   void*  stream;           /* hipStream_t for the *_dev entry points (NULL = default) */
@@ -107,6 +117,10 @@ typedef struct {
                               as many as device memory allows, at most 60.
                               A smaller value is honoured, and the memory
                               bound still caps it                           */
+  double inner_tol_final;  /* mixed: GMRES tolerance of a step taken when a
+                              column's estimated error is already within
+                              err_target but not within the half of it that
+                              stops the column (<= 0: inner_tol_refine)     */
 } helm_options;
 
 typedef struct {
@@ -125,9 +139,12 @@ typedef struct {
                                 refinement step (first 8 steps)              */
   double est_error_max;      /* mixed: max over columns of the estimated
                                 relative error |u - H^-1 f| / |u|, from the
-                                contraction of successive corrections
-                                (|d_k|/|u| * q/(1-q), q = |d_k|/|d_{k-1}|);
-                                1 when only one step was taken               */
+                                contraction of successive corrections:
+                                |d_k|/|u| * q/(1-q), q = |d_k|/|d_{k-1}|
+                                (from the third step the larger of the last
+                                two ratios; scaled by tol_k/tol_{k-1} when
+                                step k's GMRES tolerance is looser); 1 when
+                                only one step was taken or q > 1/2           */
   int    ir_gmres_iters[8];  /* GMRES iterations of each refinement step     */
   /* Per right-hand side: arrays of n_rhs entries owned by the caller, each
    * may be NULL; set them before the call (they survive the call's reset of
@@ -140,13 +157,15 @@ typedef struct {
                                 never did; 1 for FP64)                        */
   int*    rhs_gmres_iters;   /* GMRES iterations in which the column was
                                 still active, summed over refinement steps   */
+  double krylov_bytes;       /* device bytes of the Krylov vectors (basis or
+                                Bi-CGSTAB work vectors) the solve held       */
 } helm_solve_info;
 
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,
  * gmres_tol 1e-10, gmres_max_iter 40, ir_tol 1e-9, ir_max_steps 6,
  * inner_tol 1e-3, inner_tol_refine 1e-4, err_target 0 (off), hbm_budget 0
  * (auto), device 0, stream NULL, max_rhs 64, leaf_size 64, flags 0,
- * gmres_restart 0 (memory-bound, at most 60). */
+ * gmres_restart 0 (memory-bound, at most 60), inner_tol_final 1e-2. */
 void helm_default_options(helm_options* opt);
 
 /* Planner (no device memory is touched).  Exact sizes from the symbolic
@@ -252,7 +271,8 @@ int helm_device_peaks(int device, double* mfma_f32_tflops, double* mfma_f64_tflo
 
 /* Change the online-stage options of a factorized handle (gmres_tol,
  * gmres_max_iter, gmres_restart, ir_tol, ir_max_steps, inner_tol,
- * inner_tol_refine, err_target, max_rhs, flags); the geometry, precision,
+ * inner_tol_refine, inner_tol_final, err_target, max_rhs, flags); the
+ * geometry, precision,
  * device and stream fields are ignored. */
 int helm_set_solve_options(helm_handle* h, const helm_options* opt);
 

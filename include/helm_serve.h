@@ -21,10 +21,12 @@
  *    slot count that covers them, so a lightly loaded lane does not pay for
  *    its empty slots.  A column leaves its slot, and its volume is copied to the
  *    request's output, when its relative residual reaches ir_tol or its
- *    estimated error reaches err_target, or after ir_max_steps steps
- *    (request status HELM_ENOCONV).  The first step of a column uses the
- *    handle's inner_tol, later steps inner_tol_refine; for an FP64 handle
- *    one step with gmres_tol solves the column.
+ *    estimated error reaches half of err_target, or after ir_max_steps
+ *    steps (request status HELM_ENOCONV).  The first step of a column uses
+ *    the handle's inner_tol, later steps inner_tol_refine, and a step taken
+ *    when the estimate is within err_target but not within half of it
+ *    inner_tol_final; for an FP64 handle one step with gmres_tol solves the
+ *    column.
  *  - The arithmetic of a column does not depend on the other columns of its
  *    lane, so a request's result is the same alone and in a mix (up to the
  *    rounding order of the GEMM tiles, which does not depend on the

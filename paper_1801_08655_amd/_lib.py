@@ -38,6 +38,8 @@ HELM_FLAG_AUTOTUNE = 4
 HELM_FLAG_FULL_KRYLOV = 16
 HELM_FLAG_PROFILE_FWD = 8
 HELM_FLAG_TEST_ZERO_FRONT = 32
+HELM_FLAG_BICGSTAB = 64
+HELM_FLAG_UNPOLARIZED = 128
 
 
 class helm_grid(ctypes.Structure):
@@ -64,6 +66,7 @@ class helm_options(ctypes.Structure):
         ("leaf_size", ctypes.c_int),
         ("flags", ctypes.c_int),
         ("gmres_restart", ctypes.c_int),
+        ("inner_tol_final", ctypes.c_double),
     ]
 
 
@@ -87,6 +90,7 @@ class helm_solve_info(ctypes.Structure):
         ("rhs_est_error", ctypes.c_void_p),
         ("rhs_ir_steps", ctypes.c_void_p),
         ("rhs_gmres_iters", ctypes.c_void_p),
+        ("krylov_bytes", ctypes.c_double),
     ]
     PER_RHS = ("rhs_rel_residual", "rhs_est_error", "rhs_ir_steps", "rhs_gmres_iters")
 

@@ -113,6 +113,7 @@ void helm_default_options(helm_options* o) {
   o->leaf_size = 64;
   o->flags = 0;
   o->gmres_restart = 0;
+  o->inner_tol_final = 1e-2;
 }
 
 int helm_plan(const helm_grid* g, int pml_width, int n_layers, const helm_options* opt,
@@ -342,6 +343,7 @@ int helm_set_solve_options(helm_handle* h, const helm_options* opt) {
     H.opt.ir_max_steps = o.ir_max_steps;
     H.opt.inner_tol = o.inner_tol;
     H.opt.inner_tol_refine = o.inner_tol_refine;
+    H.opt.inner_tol_final = o.inner_tol_final;
     H.opt.err_target = o.err_target;
     H.opt.max_rhs = o.max_rhs;
     H.opt.flags = o.flags;

@@ -7,9 +7,11 @@ namespace helm {
 namespace kern {
 
 // out(a|b) = sx * R(X)(a|b) + sum_i (ca_i in_i(a), cb_i in_i(b))
+// Only the planes of `planes` are written (bit 0: a, bit 1: b).
 struct ReadTerms {
   const double2* in[3];
   double ca[3], cb[3];
+  int planes;
 };
 
 // --- factorization (kernels_factor.hip) -------------------------------------
@@ -128,6 +130,9 @@ void launch_add(double2* y, const double2* x, const double2* z, long long n,
                 hipStream_t st);
 // y = z - y in place (elementwise)
 void launch_rsub(double2* y, const double2* z, long long n, hipStream_t st);
+// y[v, c] = x[v, c] + alpha[c] y[v, c]   (alpha per column, complex)
+void launch_xpay_cols(double2* y, const double2* x, const double2* alpha, long long V, int k,
+                      hipStream_t st);
 void launch_residual(const GridDev& g, const double2* f, const double2* u,
                      double2* r, int k, hipStream_t st);
 void launch_point_sources(double2* f, const long long* node, const double2* amp,

@@ -201,6 +201,7 @@ __global__ void k_readout(LayerDev L, int bottom, double sx, ReadTerms terms,
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < 2 * total;
        e += (long long)gridDim.x * blockDim.x) {
     const int p = (int)(e / total);
+    if (!((terms.planes >> p) & 1)) continue;
     const long long r = e % total;
     const long long sp = r / k;
     const int c = (int)(r % k);
@@ -300,6 +301,17 @@ __global__ void k_add(double2* __restrict__ y, const double2* __restrict__ x,
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     y[e] = make_double2(x[e].x + z[e].x, x[e].y + z[e].y);
+  }
+}
+
+// y[v, c] = x[v, c] + alpha[c] y[v, c]   (alpha per column, complex)
+__global__ void k_xpay_cols(double2* __restrict__ y, const double2* __restrict__ x,
+                            const double2* __restrict__ alpha, long long V, int k) {
+  const long long total = V * k;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double2 a = alpha[e % k], b = y[e], c = x[e];
+    y[e] = make_double2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
   }
 }
 
@@ -490,6 +502,10 @@ void launch_scale_cols(double2* y, const double2* x, const double* s, long long 
 void launch_add(double2* y, const double2* x, const double2* z, long long n,
                 hipStream_t st) {
   hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(256), 0, st, y, x, z, n);
+}
+void launch_xpay_cols(double2* y, const double2* x, const double2* alpha, long long V, int k,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_xpay_cols, dim3(grid_for(V * k)), dim3(256), 0, st, y, x, alpha, V, k);
 }
 void launch_rsub(double2* y, const double2* z, long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_rsub, dim3(grid_for(n)), dim3(256), 0, st, y, z, n);

@@ -90,10 +90,16 @@ void Method::readout(int l, int bottom, double sx, const kern::ReadTerms& t, dou
     kern::launch_readout<float>(H.layers_h[l], bottom, sx, t, out, H.G.nx, H.G.ny, k, H.st);
 }
 
+kern::ReadTerms Method::planes(kern::ReadTerms t, int mask) {
+  t.planes = mask;
+  return t;
+}
+
 kern::ReadTerms Method::terms(const double2* a, double ca, double cb, const double2* b,
                               double cb_a, double cb_b, const double2* c, double cc_a,
                               double cc_b) {
   kern::ReadTerms t{};
+  t.planes = 3;
   t.in[0] = a; t.ca[0] = ca; t.cb[0] = cb;
   t.in[1] = b; t.ca[1] = cb_a; t.cb[1] = cb_b;
   t.in[2] = c; t.ca[2] = cc_a; t.cb[2] = cc_b;
@@ -286,16 +292,19 @@ void Method::dot(const double2* a, const double2* b, long long V, double2* out) 
 // at the end.  The stopping test is the same as for the whole system: the
 // residual (0, r_up) against |b|.  HELM_FLAG_FULL_KRYLOV runs GMRES on the
 // whole polarized system instead.
-int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, int max_iter,
-                  int restart, int* iters_out) {
-  const long long V = 2 * Vp / k;             // polarized vector length per column
+//
+// The same driver solves any KrylovSystem: the unpolarized SIE uses it with
+// one pair vector per column and no block structure.
+int Method::gmres(const KrylovSystem& S, const double2* b, double2* x,
+                  const std::vector<double>& tol, int max_iter, int restart, int* iters_out) {
+  const long long V = S.V;                    // vector length per column
   const int m = std::max(1, std::min(restart, max_iter));
-  const bool up = !(H.opt.flags & HELM_FLAG_FULL_KRYLOV);
-  const long long off = up ? Vp : 0;          // first element of the Krylov part
-  const long long Vs = up ? V / 2 : V;        // its length per column
+  const bool up = S.block;
+  const long long off = S.off;                // first element of the Krylov part
+  const long long Vs = S.Vs;                  // its length per column
   if (!gw.p) {
-    gw.alloc((size_t)V * k * sizeof(double2));
-    gr.alloc((size_t)V * k * sizeof(double2));
+    gw.alloc((size_t)2 * Vp * sizeof(double2));
+    gr.alloc((size_t)2 * Vp * sizeof(double2));
   }
   DevMem& w = gw;
   DevMem& r = gr;
@@ -317,7 +326,7 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
     // r = b - A x  (first cycle: x = 0, r = b), on the Krylov part
     const double2* r0 = b + off;
     if (!first) {
-      apply_A(x, w.as<double2>());
+      S.apply(x, w.as<double2>());
       HELM_HIP(hipMemcpyAsync(r.as<double2>() + off, b + off, (size_t)Vs * k * sizeof(double2),
                               hipMemcpyDeviceToDevice, H.st));
       HELM_HIP(hipMemsetAsync(hcol.p, 0, k * sizeof(double2), H.st));
@@ -347,7 +356,7 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
     if (total >= max_iter) { status = HELM_ENOCONV; break; }
     HELM_HIP(hipMemcpyAsync(scale.p, scl.data(), k * sizeof(double), hipMemcpyHostToDevice, H.st));
     kern::launch_scale_cols(basis_vec(0) + off, r0, scale.as<double>(), Vs, k, H.st);
-    if (up) HELM_HIP(hipMemsetAsync(basis_vec(0), 0, (size_t)Vp * sizeof(double2), H.st));
+    if (up) HELM_HIP(hipMemsetAsync(basis_vec(0), 0, (size_t)off * sizeof(double2), H.st));
     // per-column Hessenberg, rotations and rhs
     std::vector<std::vector<cd>> Hm(k, std::vector<cd>((size_t)(m + 1) * m, 0.0));
     std::vector<std::vector<cd>> cs(k, std::vector<cd>(m)), sn(k, std::vector<cd>(m));
@@ -358,10 +367,10 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
     int j = 0;
     for (; j < m && total < max_iter; ++j) {
       double2* vj = basis_vec(j);
-      apply_A(vj, w.as<double2>());
+      S.apply(vj, w.as<double2>());
       // K_down v_j into the down half of v_j (no longer an operand of P M)
       if (up)
-        HELM_HIP(hipMemcpyAsync(vj, w.p, (size_t)Vp * sizeof(double2),
+        HELM_HIP(hipMemcpyAsync(vj, w.p, (size_t)off * sizeof(double2),
                                 hipMemcpyDeviceToDevice, H.st));
       double2* wk = w.as<double2>() + off;
       for (int i = 0; i <= j; ++i) {
@@ -415,7 +424,8 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
         HELM_HIP(hipMemcpyAsync(scale.p, scl.data(), k * sizeof(double), hipMemcpyHostToDevice,
                                 H.st));
         kern::launch_scale_cols(basis_vec(j + 1) + off, wk, scale.as<double>(), Vs, k, H.st);
-        if (up) HELM_HIP(hipMemsetAsync(basis_vec(j + 1), 0, (size_t)Vp * sizeof(double2), H.st));
+        if (up)
+          HELM_HIP(hipMemsetAsync(basis_vec(j + 1), 0, (size_t)off * sizeof(double2), H.st));
       }
       if (!any_run) { ++j; break; }
     }
@@ -449,12 +459,212 @@ int Method::gmres(const double2* b, double2* x, const std::vector<double>& tol, 
   }
   if (up) {
     // x_down = b_down - K_down x_up (the down half holds K_down x_up)
-    kern::launch_rsub(x, b, Vp, H.st);
+    kern::launch_rsub(x, b, off, H.st);
     HELM_HIP(hipStreamSynchronize(H.st));
   }
   last_resid = resid;
   if (iters_out) *iters_out = total;
   return status;
+}
+
+// The preconditioned polarized system P M x = P f (on its up-going block
+// unless HELM_FLAG_FULL_KRYLOV).
+Method::KrylovSystem Method::polarized_system() {
+  KrylovSystem S;
+  S.V = 2 * Vp / k;
+  S.block = !(H.opt.flags & HELM_FLAG_FULL_KRYLOV);
+  S.off = S.block ? Vp : 0;
+  S.Vs = S.block ? S.V / 2 : S.V;
+  S.apply = [this](const double2* v, double2* w) { apply_A(v, w); };
+  return S;
+}
+
+// The unpolarized SIE (I - GJ) x = v on one pair vector per column.
+Method::KrylovSystem Method::sie_system() {
+  KrylovSystem S;
+  S.V = Vp / k;
+  S.off = 0;
+  S.Vs = S.V;
+  S.block = false;
+  S.apply = [this](const double2* v, double2* w) { apply_sie(v, w); };
+  return S;
+}
+
+// Batched Bi-CGSTAB (one independent iteration per column, van der Vorst's
+// recurrences with the shadow residual r_hat = r_0 and x_0 = 0) on the
+// system S, as the memory-lean alternative to GMRES: six work vectors per
+// column whatever the iteration count.  On the up-going block of the
+// polarized system the down half of every A-product (K_down p, K_down s) is
+// accumulated with the same coefficients as the up half, so that the down
+// half of x ends as K_down x_up and x_down = b_down - K_down x_up as in
+// GMRES.  Stopping test: |r| <= tol |b| per column (r the recurrence's
+// residual of the Krylov part, |b| of the whole right-hand side); a column
+// that converges or breaks down (rho or (r_hat, v) exactly zero) keeps its
+// iterate.  The per-column scalars are formed on the host from device dot
+// products.
+int Method::bicgstab(const KrylovSystem& S, const double2* b, double2* x,
+                     const std::vector<double>& tol, int max_iter, int* iters_out) {
+  const long long off = S.off, Vs = S.Vs, V = S.V;
+  const bool up = S.block;
+  double2* r = basis_vec(0) + off;
+  double2* rh = basis_vec(1) + off;
+  double2* pf = basis_vec(2);          // p, zero outside the Krylov part
+  double2* vf = basis_vec(3);          // A p
+  double2* sf = basis_vec(4);          // s, zero outside the Krylov part
+  double2* tf = basis_vec(5);          // A s
+  double2* p = pf + off;
+  double2* s = sf + off;
+  double2* hc = hcol.as<double2>();
+  HELM_HIP(hipMemsetAsync(x, 0, (size_t)V * k * sizeof(double2), H.st));
+  if (up) {
+    HELM_HIP(hipMemsetAsync(pf, 0, (size_t)off * sizeof(double2), H.st));
+    HELM_HIP(hipMemsetAsync(sf, 0, (size_t)off * sizeof(double2), H.st));
+  }
+  const size_t kb = (size_t)Vs * k * sizeof(double2);
+  HELM_HIP(hipMemcpyAsync(r, b + off, kb, hipMemcpyDeviceToDevice, H.st));
+  HELM_HIP(hipMemcpyAsync(rh, b + off, kb, hipMemcpyDeviceToDevice, H.st));
+  HELM_HIP(hipMemcpyAsync(p, b + off, kb, hipMemcpyDeviceToDevice, H.st));
+  // norms: |b| (whole vector) and |r_0|
+  std::vector<double2> hh((size_t)4 * k);
+  auto fetch = [&](int n) {
+    HELM_HIP(hipMemcpyAsync(hh.data(), hc, (size_t)n * k * sizeof(double2),
+                            hipMemcpyDeviceToHost, H.st));
+    HELM_HIP(hipStreamSynchronize(H.st));
+  };
+  auto upload = [&](const std::vector<cd>& a, int slot) {
+    std::vector<double2> d(k);
+    for (int c = 0; c < k; ++c) d[c] = make_double2(a[c].real(), a[c].imag());
+    HELM_HIP(hipMemcpyAsync(hc + (long long)slot * k, d.data(), k * sizeof(double2),
+                            hipMemcpyHostToDevice, H.st));
+  };
+  dot(b, b, V, hc);
+  dot(r, r, Vs, hc + k);
+  fetch(2);
+  std::vector<double> bnorm(k), resid(k);
+  std::vector<char> active(k);
+  for (int c = 0; c < k; ++c) {
+    bnorm[c] = std::sqrt(std::max(hh[c].x, 0.0));
+    resid[c] = bnorm[c] > 0 ? std::sqrt(std::max(hh[k + c].x, 0.0)) / bnorm[c] : 0.0;
+    active[c] = bnorm[c] > 0 && resid[c] > tol[c];
+  }
+  col_iters.assign(k, 0);
+  std::vector<cd> rho_old(k, 1.0), alpha(k, 0.0), omega(k, 1.0), rho(k), beta(k);
+  int it = 0, status = HELM_OK;
+  auto any_active = [&] {
+    for (char a : active) if (a) return true;
+    return false;
+  };
+  while (any_active()) {
+    if (it >= max_iter) { status = HELM_ENOCONV; break; }
+    dot(rh, r, Vs, hc);
+    fetch(1);
+    for (int c = 0; c < k; ++c) {
+      rho[c] = cd(hh[c].x, hh[c].y);
+      if (active[c] && rho[c] == 0.0) active[c] = 0;   // breakdown: keep the iterate
+    }
+    if (it > 0) {
+      // p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega)
+      std::vector<cd> mw(k), bt(k);
+      for (int c = 0; c < k; ++c) {
+        const bool ok = active[c] && omega[c] != 0.0;
+        bt[c] = ok ? (rho[c] / rho_old[c]) * (alpha[c] / omega[c]) : 0.0;
+        mw[c] = ok ? omega[c] : 0.0;
+      }
+      upload(mw, 0);
+      upload(bt, 1);
+      kern::launch_axpy_cols(p, vf + off, hc, -1.0, Vs, k, H.st);
+      kern::launch_xpay_cols(p, r, hc + k, Vs, k, H.st);
+    }
+    S.apply(pf, vf);
+    dot(rh, vf + off, Vs, hc);
+    fetch(1);
+    for (int c = 0; c < k; ++c) {
+      const cd den(hh[c].x, hh[c].y);
+      alpha[c] = (active[c] && den != 0.0) ? rho[c] / den : 0.0;
+      if (active[c] && den == 0.0) active[c] = 0;
+    }
+    upload(alpha, 0);
+    // s = r - alpha v; x += alpha p (and the down half accumulates alpha K_down p)
+    HELM_HIP(hipMemcpyAsync(s, r, kb, hipMemcpyDeviceToDevice, H.st));
+    kern::launch_axpy_cols(s, vf + off, hc, -1.0, Vs, k, H.st);
+    kern::launch_axpy_cols(x + off, p, hc, 1.0, Vs, k, H.st);
+    if (up) kern::launch_axpy_cols(x, vf, hc, 1.0, off / k, k, H.st);
+    ++it;
+    dot(s, s, Vs, hc + k);
+    fetch(2);
+    std::vector<char> run = active;
+    for (int c = 0; c < k; ++c) {
+      if (!active[c]) continue;
+      ++col_iters[c];
+      resid[c] = std::sqrt(std::max(hh[k + c].x, 0.0)) / bnorm[c];
+      if (resid[c] <= tol[c]) run[c] = 0;          // converged on the half step
+    }
+    S.apply(sf, tf);
+    dot(tf + off, s, Vs, hc);
+    dot(tf + off, tf + off, Vs, hc + k);
+    fetch(2);
+    for (int c = 0; c < k; ++c) {
+      const cd ts(hh[c].x, hh[c].y);
+      const double tt = hh[k + c].x;
+      omega[c] = (run[c] && tt > 0) ? ts / tt : 0.0;
+    }
+    upload(omega, 0);
+    // x += omega s (down half: omega K_down s); r = s - omega t
+    kern::launch_axpy_cols(x + off, s, hc, 1.0, Vs, k, H.st);
+    if (up) kern::launch_axpy_cols(x, tf, hc, 1.0, off / k, k, H.st);
+    HELM_HIP(hipMemcpyAsync(r, s, kb, hipMemcpyDeviceToDevice, H.st));
+    kern::launch_axpy_cols(r, tf + off, hc, -1.0, Vs, k, H.st);
+    dot(r, r, Vs, hc);
+    fetch(1);
+    for (int c = 0; c < k; ++c) {
+      if (!run[c]) { active[c] = 0; continue; }
+      resid[c] = std::sqrt(std::max(hh[c].x, 0.0)) / bnorm[c];
+      if (resid[c] <= tol[c] || omega[c] == 0.0) active[c] = 0;
+      rho_old[c] = rho[c];
+    }
+  }
+  if (up) {
+    kern::launch_rsub(x, b, off, H.st);
+    HELM_HIP(hipStreamSynchronize(H.st));
+  }
+  last_resid = resid;
+  if (iters_out) *iters_out = it;
+  return status;
+}
+
+// out = (I - GJ) x for the unpolarized SIE: every layer solves the sources
+// of its two interfaces (all layers in one batched solve) and is read on its
+// own interface planes: out_j = x_j - (w^j(e_j), w^{j+1}(s_{j+1})).
+void Method::apply_sie(const double2* x, double2* out) {
+  const int L = H.G.L;
+  for (int l = 0; l < L; ++l) {
+    zero_X(l);
+    if (l >= 1) jump(l, pair(x, l - 1), nullptr, 0);
+    if (l <= L - 2) jump(l, pair(x, l), nullptr, 1);
+  }
+  H.solve_layers(*set_all, k);
+  for (int l = 0; l < L; ++l) {
+    if (l <= L - 2) readout(l, 1, -1.0, planes(terms(pair(x, l), 1, 0), 1), pair(out, l));
+    if (l >= 1) readout(l, 0, -1.0, planes(terms(pair(x, l - 1), 0, 1), 2), pair(out, l - 1));
+  }
+}
+
+// v of the unpolarized SIE: the local solves of the partitioned source read
+// on each layer's own interface planes.
+void Method::sie_rhs(const double2* f, double2* v) {
+  const int L = H.G.L;
+  scatter_sources(f);
+  H.solve_layers(*set_all, k);
+  for (int l = 0; l < L; ++l) {
+    if (l <= L - 2) readout(l, 1, 1.0, planes(terms(), 1), pair(v, l));
+    if (l >= 1) readout(l, 0, 1.0, planes(terms(), 2), pair(v, l - 1));
+  }
+}
+
+// Device bytes of the Krylov vectors held (basis or Bi-CGSTAB work vectors,
+// plus GMRES's two temporaries).
+double Method::krylov_bytes() const {
+  return (double)(basis.size() * 2 * Vp + (gw.p ? 4 * Vp : 0)) * sizeof(double2);
 }
 
 double2* Method::basis_vec(int i) {
@@ -492,16 +702,27 @@ int Method::polarized_solve(const double2* f, double2* u, const std::vector<doub
     bpol.alloc((size_t)2 * Vp * sizeof(double2));
     xpol.alloc((size_t)2 * Vp * sizeof(double2));
   }
-  precondition_source(f, bpol.as<double2>(), bpol.as<double2>() + Vp);
+  const bool unpol = H.opt.flags & HELM_FLAG_UNPOLARIZED;
+  if (unpol) sie_rhs(f, bpol.as<double2>());
+  else precondition_source(f, bpol.as<double2>(), bpol.as<double2>() + Vp);
   HELM_HIP(hipStreamSynchronize(H.st));
   double t1 = now_ms();
   int iters = 0;
-  int st = gmres(bpol.as<double2>(), xpol.as<double2>(), tol, max_iter, restart, &iters);
+  int st;
+  if (unpol)
+    st = gmres(sie_system(), bpol.as<double2>(), xpol.as<double2>(), tol, max_iter, restart,
+               &iters);
+  else if (H.opt.flags & HELM_FLAG_BICGSTAB)
+    st = bicgstab(polarized_system(), bpol.as<double2>(), xpol.as<double2>(), tol, max_iter,
+                  &iters);
+  else
+    st = gmres(polarized_system(), bpol.as<double2>(), xpol.as<double2>(), tol, max_iter,
+               restart, &iters);
   HELM_HIP(hipStreamSynchronize(H.st));
   double t2 = now_ms();
-  // traces u_j = u_down_j + u_up_j
-  double2* tr = fpol.as<double2>();
-  kern::launch_add(tr, xpol.as<double2>(), xpol.as<double2>() + Vp, Vp, H.st);
+  // traces u_j = u_down_j + u_up_j (the unpolarized SIE solves for them)
+  double2* tr = unpol ? xpol.as<double2>() : fpol.as<double2>();
+  if (!unpol) kern::launch_add(tr, xpol.as<double2>(), xpol.as<double2>() + Vp, Vp, H.st);
   reconstruct(f, tr, u);
   HELM_HIP(hipStreamSynchronize(H.st));
   double t3 = now_ms();
@@ -510,6 +731,7 @@ int Method::polarized_solve(const double2* f, double2* u, const std::vector<doub
     info->t_gmres_ms += t2 - t1;
     info->t_reconstruct_ms += t3 - t2;
     info->gmres_iters += iters;
+    info->krylov_bytes = std::max(info->krylov_bytes, krylov_bytes());
   }
   return st;
 }
@@ -600,14 +822,15 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
     StepNorms nm;
     for (int it = 0; it < std::max(1, o.ir_max_steps); ++it) {
       int it0 = info ? info->gmres_iters : 0;
-      std::vector<double> tol(k, it == 0 ? o.inner_tol : o.inner_tol_refine);
+      std::vector<double> tol(k);
+      for (int c = 0; c < k; ++c) tol[c] = refinement_tol(it, track[c], o);
       refine_step(f, u, r, vd.as<double2>(), tol, nm, info);
       rel = nm.rel;
       ++steps;
       double mx = 0, emx = 0;
       for (int c = 0; c < k; ++c) {
         mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
-        double est = refinement_error(it, track[c], nm.dn[c], nm.un[c]);
+        double est = refinement_error(it, track[c], nm.dn[c], nm.un[c], tol[c]);
         emx = std::max(emx, est);
         est_c[c] = est;
         if (col_iters.size() == (size_t)k) iters_c[c] += col_iters[c];
@@ -649,20 +872,43 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
 // approximates the error before it, so q_k = |d_k| / |d_{k-1}| measures the
 // contraction of the previous step; if the current step contracts by no
 // more than q, the remaining error is at most |d_k| q / (1 - q) relative to
-// |u|.  Guards: q is the larger of the last two measured ratios (from the
-// third step on), and an estimate with q > 1/2 (slow or erratic
-// contraction) is not trusted (reported as 1, unknown).  Unknown (1) after
-// the first step.
-double refinement_error(int step, RefineTrack& tr, double dcur, double unorm) {
-  const double dprev = tr.dprev, qprev = tr.qprev;
+// |u|.  Guards:
+//  - q is the larger of the last two measured ratios (from the third step
+//    on);
+//  - a step whose GMRES tolerance is looser than the previous step's is
+//    taken to contract less in proportion (q scaled by tol / tol_prev): a
+//    step limited by its GMRES tolerance contracts in proportion to it, one
+//    limited by the complex64 rounding does not change;
+//  - an estimate with q > 1/2 (slow or erratic contraction) is not trusted
+//    (reported as 1, unknown).
+// Unknown (1) after the first step.
+double refinement_error(int step, RefineTrack& tr, double dcur, double unorm, double tol) {
+  const double dprev = tr.dprev, qprev = tr.qprev, tprev = tr.tprev;
   tr.dprev = dcur;
-  if (unorm == 0) return 0.0;
-  if (step == 0 || dprev <= 0) return 1.0;
-  const double qk = dcur / dprev;
-  tr.qprev = qk;
-  const double q = step >= 2 ? std::max(qk, qprev) : qk;
-  if (!(q <= 0.5)) return 1.0;
-  return dcur / unorm * q / (1.0 - q);
+  tr.tprev = tol;
+  double est = 1.0;
+  if (unorm == 0) {
+    est = 0.0;
+  } else if (step > 0 && dprev > 0) {
+    const double qk = dcur / dprev;
+    tr.qprev = qk;
+    double q = step >= 2 ? std::max(qk, qprev) : qk;
+    if (tprev > 0 && tol > tprev) q *= tol / tprev;
+    if (q <= 0.5) est = dcur / unorm * q / (1.0 - q);
+  }
+  tr.est = est;
+  return est;
+}
+
+// Tolerance of a column's next step: inner_tol for the first solve; once the
+// estimated error is within err_target (but not yet within the half of it
+// that stops the column), the step only has to shrink the error by a modest
+// factor, and runs to the looser inner_tol_final; otherwise inner_tol_refine.
+double refinement_tol(int step, const RefineTrack& tr, const helm_options& o) {
+  if (step == 0) return o.inner_tol;
+  if (o.err_target > 0 && tr.est <= o.err_target && o.inner_tol_final > 0)
+    return std::max(o.inner_tol_final, o.inner_tol_refine);
+  return o.inner_tol_refine;
 }
 
 bool refinement_met(double rel, double est, const helm_options& o) {

@@ -1,6 +1,7 @@
 // Online stage of the method on one batch of k right-hand-side columns.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "handle.h"
@@ -34,6 +35,8 @@ struct Method {
   void jump(int l, const double2* a, const double2* b, int bottom, double ca = 1.0,
             double cb = 1.0, const double2* c = nullptr, double cc = 1.0);
   void readout(int l, int bottom, double sx, const kern::ReadTerms& t, double2* out);
+  // the same terms with only the read-out planes of `mask` written (1: a, 2: b)
+  static kern::ReadTerms planes(kern::ReadTerms t, int mask);
   static kern::ReadTerms terms(const double2* a = nullptr, double ca = 0, double cb = 0,
                                const double2* b = nullptr, double cb_a = 0,
                                double cb_b = 0, const double2* c = nullptr,
@@ -47,8 +50,25 @@ struct Method {
   void precondition_source(const double2* f, double2* od, double2* ou);
   void reconstruct(const double2* f, const double2* tr, double2* u);
   void dot(const double2* a, const double2* b, long long V, double2* out);
-  int gmres(const double2* b, double2* x, const std::vector<double>& tol, int max_iter,
-            int restart, int* iters);
+  // A linear system for the Krylov solvers: per column, vectors of V
+  // elements (column fastest); the Krylov space lives on the elements
+  // [off, off + Vs k) of a vector; with `block`, A applied to a vector that
+  // is zero below off also returns a part below off that belongs to the
+  // solution's down half (the block-triangular polarized system).
+  struct KrylovSystem {
+    long long V = 0, off = 0, Vs = 0;
+    bool block = false;
+    std::function<void(const double2*, double2*)> apply;
+  };
+  KrylovSystem polarized_system();
+  KrylovSystem sie_system();
+  int gmres(const KrylovSystem& S, const double2* b, double2* x,
+            const std::vector<double>& tol, int max_iter, int restart, int* iters);
+  int bicgstab(const KrylovSystem& S, const double2* b, double2* x,
+               const std::vector<double>& tol, int max_iter, int* iters);
+  void apply_sie(const double2* x, double2* out);
+  void sie_rhs(const double2* f, double2* v);
+  double krylov_bytes() const;
   int polarized_solve(const double2* f, double2* u, double tol, int max_iter,
                       int restart, helm_solve_info* info);
   int polarized_solve(const double2* f, double2* u, const std::vector<double>& tol,
@@ -69,10 +89,15 @@ struct Method {
 struct RefineTrack {
   double dprev = 0;   // |d| of the previous step
   double qprev = 0;   // contraction ratio measured at the previous step
+  double tprev = 0;   // GMRES tolerance of the previous step
+  double est = 1;     // estimated error after the last step (1: unknown)
 };
 // Estimated relative error |u - H^-1 f| / |u| after a step whose correction
-// has norm dcur (see method.cpp); updates the record.
-double refinement_error(int step, RefineTrack& tr, double dcur, double unorm);
+// has norm dcur and whose GMRES ran to tolerance tol (see method.cpp);
+// updates the record.
+double refinement_error(int step, RefineTrack& tr, double dcur, double unorm, double tol);
+// GMRES tolerance of a column's next step (0-based step index).
+double refinement_tol(int step, const RefineTrack& tr, const helm_options& o);
 // Whether a column may stop: FP64 residual at ir_tol, or estimated error at
 // most half of err_target (a factor-2 margin against the estimate).
 bool refinement_met(double rel, double est, const helm_options& o);

@@ -119,14 +119,15 @@ void Server::run_lane(Lane& ln) {
       std::vector<double> tol(w, 0.0);
       for (int s = 0; s < w; ++s)
         tol[s] = fp64 ? H.opt.gmres_tol
-                      : (ln.slots[s].steps == 0 ? H.opt.inner_tol : H.opt.inner_tol_refine);
+                      : refinement_tol(ln.slots[s].steps, ln.slots[s].track, H.opt);
       M.refine_step(F, U, R, ln.D.as<double2>(), tol, nm, nullptr);
       std::vector<char> fin(ln.K, 0);
       for (int s = 0; s < occ; ++s) {
         Slot& sl = ln.slots[s];
         const int st = sl.steps++;
         const double rel = nm.rel[s];
-        const double est = fp64 ? 0.0 : refinement_error(st, sl.track, nm.dn[s], nm.un[s]);
+        const double est =
+            fp64 ? 0.0 : refinement_error(st, sl.track, nm.dn[s], nm.un[s], tol[s]);
         bool f;
         int status = HELM_OK;
         if (fp64) {
