@@ -324,6 +324,25 @@ int helm_layer_info(const helm_handle* h, int l, int* s, int* e, int* lo,
 int helm_layer_solve_dev(helm_handle* h, int l, int k, const double* r_dev,
                          double* w_dev);
 
+/* Allocation-free variant of helm_layer_solve_dev, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, layout and result as
+ * helm_layer_solve_dev (and the same kernels), but the solve's workspace --
+ * the solve vector, the forward results, the update buffers and the split-K
+ * partial products of layer l for k columns, plus the kernels' layer table --
+ * lives in a static device array of HELM_NOALLOC_SCRATCH_BYTES per GPU (held
+ * until the process ends) instead of the handle's allocations; it calls no
+ * hipMalloc, hipFree or other allocating routine and never replays a graph.
+ * Errors: HELM_EINVAL for bad arguments, HELM_ENOMEM (nothing launched) when
+ * the workspace of k columns of this layer exceeds the array.  Every call on
+ * one GPU uses that GPU's single array: calls that overlap on one GPU (other
+ * handles or streams, other threads) race and must be serialized by the
+ * caller.  Nothing in the array needs to start at zero: each call writes
+ * every byte it reads. */
+#define HELM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int helm_layer_solve_noalloc_dev(helm_handle* h, int l, int k, const double* r_dev,
+                                 double* w_dev);
+
 /* FP64 residual r = f - H u of the global 7-point operator (device arrays of
  * k volumes, RHS-major).  With f_dev == NULL it returns H u. */
 int helm_apply_operator_dev(helm_handle* h, int k, const double* f_dev,

@@ -167,6 +167,17 @@ class Solver:
               "helm_layer_solve_dev")
         return w
 
+    def layer_solve_noalloc(self, l: int, r, w=None):
+        """Same as layer_solve through the allocation-free entry point (the
+        output tensor may be passed in, so that nothing is allocated)."""
+        import torch
+        r = r.contiguous()
+        if w is None:
+            w = torch.empty_like(r)
+        check(lib().helm_layer_solve_noalloc_dev(self._h, l, r.shape[0], _ptr(r), _ptr(w)),
+              "helm_layer_solve_noalloc_dev")
+        return w
+
     def apply_operator(self, u, f=None):
         """f - H u (or H u when f is None), FP64 on the GPU."""
         import torch

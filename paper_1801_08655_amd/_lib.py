@@ -24,7 +24,7 @@ EXPORTED = [
     "helm_strerror", "helm_last_error", "helm_layer_info", "helm_layer_solve_dev",
     "helm_apply_operator_dev", "helm_polarized_op_dev", "helm_kernel_stats",
     "helm_set_solve_options", "helm_tile_choices", "helm_device_peaks",
-    "helm_get_factor_info",
+    "helm_get_factor_info", "helm_layer_solve_noalloc_dev",
     # include/helm_serve.h
     "helm_server_default_options", "helm_server_create", "helm_server_add_model",
     "helm_server_submit", "helm_server_wait", "helm_server_poll", "helm_server_get_stats",
@@ -40,6 +40,7 @@ HELM_FLAG_PROFILE_FWD = 8
 HELM_FLAG_TEST_ZERO_FRONT = 32
 HELM_FLAG_BICGSTAB = 64
 HELM_FLAG_UNPOLARIZED = 128
+HELM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class helm_grid(ctypes.Structure):
@@ -267,6 +268,8 @@ def lib():
     L.helm_layer_info.restype = I
     L.helm_layer_solve_dev.argtypes = [H, I, I, P, P]
     L.helm_layer_solve_dev.restype = I
+    L.helm_layer_solve_noalloc_dev.argtypes = [H, I, I, P, P]
+    L.helm_layer_solve_noalloc_dev.restype = I
     L.helm_apply_operator_dev.argtypes = [H, I, P, P, P]
     L.helm_apply_operator_dev.restype = I
     L.helm_polarized_op_dev.argtypes = [H, I, I, P, P]

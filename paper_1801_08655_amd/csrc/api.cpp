@@ -73,6 +73,7 @@ int factorize_common(const helm_grid* g, const double* m, bool on_device, double
   Handle& H = h->impl;
   build_geometry(H.G, *g, omega, pml_width, n_layers, o.pml_local, C, o.leaf_size);
   H.init_device(o);
+  (void)noalloc_scratch(H.device);   // set-up of the allocation-free entry point
   H.upload_geometry(mh.data(), false);
   H.build_fronts();
   H.factorize();

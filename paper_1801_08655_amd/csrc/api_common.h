@@ -16,6 +16,10 @@ struct helm_handle {
 
 namespace helm {
 
+// Device address of this device's static scratch array of the
+// allocation-free entry point (looked up once per device, with it current).
+void* noalloc_scratch(int device);
+
 // Run f(); map a thrown Error to its status code and record its text for
 // helm_last_error.  No exception crosses the C ABI.
 template <class F>
