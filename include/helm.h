@@ -142,9 +142,10 @@ typedef struct {
                                 contraction of successive corrections:
                                 |d_k|/|u| * q/(1-q), q = |d_k|/|d_{k-1}|
                                 (from the third step the larger of the last
-                                two ratios; scaled by tol_k/tol_{k-1} when
-                                step k's GMRES tolerance is looser); 1 when
-                                only one step was taken or q > 1/2           */
+                                two ratios; scaled by res_k/res_{k-1} when
+                                step k's GMRES stopped at a larger relative
+                                residual res_k); 1 when only one step was
+                                taken or q > 1/2                             */
   int    ir_gmres_iters[8];  /* GMRES iterations of each refinement step     */
   /* Per right-hand side: arrays of n_rhs entries owned by the caller, each
    * may be NULL; set them before the call (they survive the call's reset of

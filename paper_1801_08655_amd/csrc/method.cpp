@@ -687,6 +687,7 @@ int Method::polarized_solve(const double2* f, double2* u, const std::vector<doub
   double t0 = now_ms();
   col_iters.assign(k, 0);
   if (L == 1) {
+    last_resid.assign(k, 0.0);   // a direct solve: no Krylov residual
     scatter_sources(f);
     H.solve_layers(*set_all, k);
     if (H.prec == HELM_FP64)
@@ -830,7 +831,9 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
       double mx = 0, emx = 0;
       for (int c = 0; c < k; ++c) {
         mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
-        double est = refinement_error(it, track[c], nm.dn[c], nm.un[c], tol[c]);
+        // the relative residual GMRES reached stands for the step's tolerance
+        const double teff = last_resid.size() == (size_t)k ? last_resid[c] : tol[c];
+        double est = refinement_error(it, track[c], nm.dn[c], nm.un[c], teff);
         emx = std::max(emx, est);
         est_c[c] = est;
         if (col_iters.size() == (size_t)k) iters_c[c] += col_iters[c];
@@ -875,10 +878,11 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
 // |u|.  Guards:
 //  - q is the larger of the last two measured ratios (from the third step
 //    on);
-//  - a step whose GMRES tolerance is looser than the previous step's is
-//    taken to contract less in proportion (q scaled by tol / tol_prev): a
-//    step limited by its GMRES tolerance contracts in proportion to it, one
-//    limited by the complex64 rounding does not change;
+//  - a step whose GMRES reached a larger relative residual than the
+//    previous step's is taken to contract less in proportion (q scaled by
+//    tol / tol_prev, tol the residual GMRES reached): a step limited by its
+//    GMRES residual contracts in proportion to it, one limited by the
+//    complex64 rounding does not change;
 //  - an estimate with q > 1/2 (slow or erratic contraction) is not trusted
 //    (reported as 1, unknown).
 // Unknown (1) after the first step.

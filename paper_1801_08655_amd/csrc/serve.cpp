@@ -126,8 +126,9 @@ void Server::run_lane(Lane& ln) {
         Slot& sl = ln.slots[s];
         const int st = sl.steps++;
         const double rel = nm.rel[s];
+        const double teff = M.last_resid.size() > (size_t)s ? M.last_resid[s] : tol[s];
         const double est =
-            fp64 ? 0.0 : refinement_error(st, sl.track, nm.dn[s], nm.un[s], tol[s]);
+            fp64 ? 0.0 : refinement_error(st, sl.track, nm.dn[s], nm.un[s], teff);
         bool f;
         int status = HELM_OK;
         if (fp64) {
