@@ -75,6 +75,13 @@ extern "C" {
                                 Algorithms 2-3, sign made consistent: (I - GJ) u
                                 = v) without preconditioner: every iteration
                                 is one batched solve of all layers at once    */
+#define HELM_FLAG_NO_PRUNE 256 /* the sweep solves of the GMRES iterations run
+                                every front of the layer; by default they skip
+                                the fronts that neither their interface sources
+                                nor their interface read-outs reach (Section
+                                "Local Solves: Parallel Multi-frontal Methods":
+                                sources supported on the interfaces, only the
+                                boundary values needed)                       */
 #define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
                                 the factorization leaves one leaf front of
                                 layer 0 unassembled, so its pivots are exactly

@@ -40,6 +40,7 @@ HELM_FLAG_PROFILE_FWD = 8
 HELM_FLAG_TEST_ZERO_FRONT = 32
 HELM_FLAG_BICGSTAB = 64
 HELM_FLAG_UNPOLARIZED = 128
+HELM_FLAG_NO_PRUNE = 256
 HELM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 

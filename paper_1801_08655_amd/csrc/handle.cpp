@@ -565,6 +565,53 @@ void Handle::ensure_workspace(int k) {
 const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
   auto it = sets.find(layers);
   if (it != sets.end()) return *it->second;
+  auto S = make_set(layers, nullptr);
+  auto& ref = *S;
+  sets[layers] = std::move(S);
+  return ref;
+}
+
+// Interface planes of layer l (local z of the extended layer): the top pair
+// (s - 1, s) and the bottom pair (e, e + 1), where they exist.
+static bool touches(const FrontHost& F, const LayerPlan& P, int mask, int l, int L) {
+  int pl[4], n = 0;
+  if ((mask & kPruneTop) && l >= 1) { pl[n++] = P.s - 1 - P.lo; pl[n++] = P.s - P.lo; }
+  if ((mask & kPruneBottom) && l <= L - 2) { pl[n++] = P.e - P.lo; pl[n++] = P.e + 1 - P.lo; }
+  for (int i = 0; i < n; ++i)
+    if (F.box.lo[2] <= pl[i] && pl[i] < F.box.hi[2]) return true;
+  return false;
+}
+
+// Launch lists of one local solve of layer l whose sources lie on the
+// interface planes of `src` and whose result is read only on those of
+// `read` (kPruneTop / kPruneBottom bits).  The right-hand side is zero
+// outside the source planes, so a front whose subtree holds none of them has
+// a zero forward result and a zero update for its parent: the forward pass
+// skips it (and its parent drops it as a child).  Only the values of the
+// read-out planes are wanted, and every node is computed by the backward step
+// of the front that owns it from the fronts above it, so the backward pass
+// keeps the fronts whose subtree holds a read-out plane (with a zero forward
+// result where the forward pass skipped them).  The skipped work is exact
+// zeros: the result on the read-out planes is the full solve's.
+const LayerSet& Handle::pruned_set(int l, int src, int read) {
+  const std::vector<int> key{l, src, read};
+  auto it = psets.find(key);
+  if (it != psets.end()) return *it->second;
+  const LayerPlan& P = G.layers[l];
+  Prune pr;
+  pr.fwd.assign(n_fronts, 1);
+  pr.bwd.assign(n_fronts, 1);
+  for (size_t q = 0; q < P.fronts.size(); ++q) {
+    pr.fwd[front_base[l] + q] = touches(P.fronts[q], P, src, l, G.L);
+    pr.bwd[front_base[l] + q] = touches(P.fronts[q], P, read, l, G.L);
+  }
+  auto S = make_set({l}, &pr);
+  auto& ref = *S;
+  psets[key] = std::move(S);
+  return ref;
+}
+
+std::unique_ptr<LayerSet> Handle::make_set(const std::vector<int>& layers, const Prune* pr) {
   auto S = std::make_unique<LayerSet>();
   S->layers = layers;
   int maxd = 0;
@@ -584,12 +631,20 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
     kc = (kc + 15) / 16 * 16;
     nch = (K + kc - 1) / kc;
   };
+  auto fwd_on = [&](int f) { return !pr || pr->fwd[f]; };
+  auto bwd_on = [&](int f) { return !pr || pr->bwd[f]; };
   for (int d = 0; d <= maxd; ++d) {
     auto D = std::make_unique<DepthList>();
-    std::vector<int> ids;
+    std::vector<int> ids, all;   // backward list (flagged ids: ids_raw)
     for (int l : layers)
       if (d <= G.layers[l].max_depth)
-        for (int q : G.layers[l].by_depth[d]) ids.push_back(front_base[l] + q);
+        for (int q : G.layers[l].by_depth[d]) all.push_back(front_base[l] + q);
+    std::vector<int> ids_raw;
+    for (int f : all)
+      if (bwd_on(f)) {
+        ids.push_back(f);
+        ids_raw.push_back(f | (fwd_on(f) ? 0 : kZeroZ));
+      }
     const size_t n = ids.size();
     // backward: every front; a 32-row tile when the pivot blocks are small,
     // K (boundary) split when the depth has few tiles
@@ -623,13 +678,22 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
     // forward: every front takes the GEMM; only fronts with children need
     // the extend-add gather (leaves read their pivots straight from X)
     std::vector<int> idsS, idsL;   // S: fronts with children (gather), L: all
-    for (int f : ids) {
+    std::vector<int> idsS_raw, idsL_raw;
+    for (int f : all) {
+      if (!fwd_on(f)) continue;
       const FrontDev& F = fronts_h[f];
       const double sbs = (double)(F.s + F.b) * F.s;
+      int flags = 0;
+      for (int c = 0; c < 2; ++c)
+        if (F.child[c] >= 0 && !fwd_on(F.child[c])) flags |= kSkipChild0 << c;
+      const bool kids = (F.child[0] >= 0 && !(flags & kSkipChild0)) ||
+                        (F.child[1] >= 0 && !(flags & kSkipChild1));
       idsL.push_back(f);
+      idsL_raw.push_back(f | flags);
       D->fl_s += F.s; D->fl_b += F.b; D->fl_sbs += sbs;
-      if (F.child[0] >= 0 || F.child[1] >= 0) {
+      if (kids) {
         idsS.push_back(f);
+        idsS_raw.push_back(f | flags);
         D->fs_s += F.s; D->fs_b += F.b;
       }
     }
@@ -655,12 +719,14 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
     D->n = (int)n;
     D->nS = (int)idsS.size();
     D->nL = (int)nl;
-    upload(D->ids, ids, st);
+    for (int f : ids) S->elems += (double)fronts_h[f].b * fronts_h[f].s;
+    for (int f : idsL) S->elems += (double)(fronts_h[f].s + fronts_h[f].b) * fronts_h[f].s;
+    upload(D->ids, ids_raw, st);
     upload(D->tasks, tasks, st);
     upload(D->pBw, tile_map(pBw), st);
     upload(D->rB, tile_map(rB), st);
-    upload(D->idsS, idsS, st);
-    upload(D->idsL, idsL, st);
+    upload(D->idsS, idsS_raw, st);
+    upload(D->idsL, idsL_raw, st);
     upload(D->tasksL, tasksL, st);
     upload(D->pSB, tile_map(pSB), st);
     upload(D->pF, tile_map(pF), st);
@@ -675,16 +741,10 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
     S->depth.push_back(std::move(D));
   }
   HELM_HIP(hipStreamSynchronize(st));
-  auto& ref = *S;
-  sets[layers] = std::move(S);
-  return ref;
+  return S;
 }
 
-double Handle::solve_elems(const LayerSet& set) const {
-  double e = 0;
-  for (int l : set.layers) e += G.layers[l].solve_elems;
-  return e;
-}
+double Handle::solve_elems(const LayerSet& set) const { return set.elems; }
 
 void Handle::solve_layers(const LayerSet& set, int k) {
   size_t need = (size_t)std::max<long long>(set.scratch_rows, 1) * std::max(k, kcap) * elem;
@@ -863,7 +923,7 @@ void Handle::run_layers_t(const LayerSet& set, int k, const LayerDev* ld, void* 
   auto bwd_bn = [&](int d) { return tp ? tp[d].bwd_bn : wdef; };
   for (int d = set.max_depth; d >= 0; --d) {
     const DepthList& D = *set.depth[d];
-    if (D.n == 0) continue;
+    if (D.nL == 0) continue;   // (a pruned set may run a front forward only)
     hipEvent_t a = nullptr;
     if (D.nS > 0) {
       a = prof_begin(K_FWD_GATHER);

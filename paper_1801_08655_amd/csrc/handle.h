@@ -69,9 +69,13 @@ struct PendingEvent {
   hipEvent_t a, b;
   double flops, bytes;
 };
+// Interface-plane masks of a pruned local solve.
+constexpr int kPruneTop = 1, kPruneBottom = 2;
+
 struct LayerSet {
   std::vector<int> layers;
   int max_depth = 0;
+  double elems = 0;             // factor elements one solve reads
   long long scratch_rows = 0;   // max over depths
   std::vector<std::unique_ptr<DepthList>> depth;
 };
@@ -179,6 +183,14 @@ struct Handle {
   template <typename T> void factorize_t();
   void ensure_workspace(int k);
   const LayerSet& layer_set(const std::vector<int>& layers);
+  // launch lists of a single-layer solve whose sources lie on the interface
+  // planes of `src` and whose result is read on those of `read` (kPrune*)
+  const LayerSet& pruned_set(int l, int src, int read);
+  struct Prune {
+    std::vector<char> fwd, bwd;   // per global front: in the forward / backward pass
+  };
+  std::unique_ptr<LayerSet> make_set(const std::vector<int>& layers, const Prune* pr);
+  std::map<std::vector<int>, std::unique_ptr<LayerSet>> psets;
   // multi-RHS solve of the layers in `set` on their X buffers (k columns)
   void solve_layers(const LayerSet& set, int k);
   template <typename T> void solve_layers_t(const LayerSet& set, int k);

@@ -60,6 +60,15 @@ struct FrontDev {
   int pad;
 };
 
+// The launch lists of a solve may carry flags in the top bits of a front id
+// (solves pruned to the fronts that touch their sources and read-outs): the
+// front's child 0 or 1 contributes nothing (its subtree holds no source), or
+// its forward result Z(S) is zero (no source below it, but a read-out).
+constexpr int kFrontIdMask = (1 << 27) - 1;
+constexpr int kSkipChild0 = 1 << 27;
+constexpr int kSkipChild1 = 1 << 28;
+constexpr int kZeroZ = 1 << 29;
+
 // Split of one front's substitution GEMMs along K (the pivot / boundary
 // dimension) into chunks computed by separate workgroups; partial products
 // go to a scratch area and are summed in a fixed order.

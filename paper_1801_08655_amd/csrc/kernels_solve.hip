@@ -30,12 +30,13 @@ template <typename T> struct ChildSum {
   const C_t<T>* Uc;
   long long cub[2];
   const int* inv[2];
-  __device__ ChildSum(const FrontDev* fronts, const FrontDev& f, const LayerDev& L) {
+  // raw: the list entry of the front (flags kSkipChild0/1 drop a child)
+  __device__ ChildSum(const FrontDev* fronts, const FrontDev& f, const LayerDev& L, int raw) {
     Uc = reinterpret_cast<const C_t<T>*>(L.Ub[f.ub_parity ^ 1]);
     for (int slot = 0; slot < 2; ++slot) {
       cub[slot] = 0;
       inv[slot] = nullptr;
-      if (f.child[slot] >= 0) {
+      if (f.child[slot] >= 0 && !(raw & (kSkipChild0 << slot))) {
         cub[slot] = fronts[f.child[slot]].ub;
         inv[slot] = L.inv + f.inv[slot];
       }
@@ -63,11 +64,12 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   using C = C_t<T>;
   const int2 tm = tmap[blockIdx.x];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const LayerDev& L = layers[f.layer];
   const int r0 = tm.y * RT;
   C* X = reinterpret_cast<C*>(L.X);
-  const ChildSum<T> cs(fronts, f, L);
+  const ChildSum<T> cs(fronts, f, L, raw);
   const int rows = (f.s - r0) < RT ? (f.s - r0) : RT;
   const int total = rows * k;
   // EPT elements (row, column) per thread and pass: child rows first, then
@@ -176,7 +178,8 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int2 tm = tmap[mt];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
@@ -200,7 +203,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     });
     return;
   }
-  fwd_epilogue<T, BM, BN>(acc, f, ChildSum<T>(fronts, f, L), reinterpret_cast<C*>(L.Wt),
+  fwd_epilogue<T, BM, BN>(acc, f, ChildSum<T>(fronts, f, L, raw), reinterpret_cast<C*>(L.Wt),
                           ub_ptr<T>(L, f.ub_parity), m0, n0, k);
 }
 
@@ -216,7 +219,8 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   using C = C_t<T>;
   const int2 tm = tmap[blockIdx.x];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
@@ -225,7 +229,7 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* S = reinterpret_cast<const C*>(scratch);
   C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
-  const ChildSum<T> cs(fronts, f, L);
+  const ChildSum<T> cs(fronts, f, L, raw);
   // RED_EPT elements per thread at a time: all their loads, then the stores
   for (int e0 = 0; e0 < rows * k; e0 += NT * RED_EPT) {
     C z[RED_EPT];
@@ -264,7 +268,8 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int2 tm = tmap[mt];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
@@ -300,7 +305,8 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 #pragma unroll
     for (int j = 0; j < O::NC; ++j) {
       const int gm = m0 + o.r[i], gc = n0 + o.c[j];
-      zv[i][j] = ld_or_zero(gm < f.s && gc < k, Z + (long long)(f.off + gm) * k + gc);
+      zv[i][j] = ld_or_zero(gm < f.s && gc < k && !(raw & kZeroZ),
+                            Z + (long long)(f.off + gm) * k + gc);
     }
 #pragma unroll
   for (int i = 0; i < O::NR; ++i)
@@ -320,7 +326,8 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   using C = C_t<T>;
   const int2 tm = tmap[blockIdx.x];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int r0 = tm.y * RT;
@@ -336,7 +343,7 @@ k_bwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       z[j] = czero<C>();
       if (e >= rows * k) continue;
       const int gm = r0 + e / k, gc = e % k;
-      z[j] = ld(Z + (long long)(f.off + gm) * k + gc);
+      z[j] = ld_or_zero(!(raw & kZeroZ), Z + (long long)(f.off + gm) * k + gc);
       for (int ch = 0; ch < tk.nch_b; ++ch)
         z[j] = cadd(z[j], ld(S + (tk.scr_b + (long long)ch * f.s + gm) * k + gc));
     }
@@ -373,7 +380,8 @@ k_fwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int mt = blockIdx.x;
   const int2 tm = tmap[mt];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
@@ -410,7 +418,7 @@ k_fwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   C* Z = reinterpret_cast<C*>(L.Wt);
   C* Uo = ub_ptr<T>(L, f.ub_parity);
   C* S = reinterpret_cast<C*>(scratch);
-  const ChildSum<T> cs(fronts, f, L);
+  const ChildSum<T> cs(fronts, f, L, raw);
   C add[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) add[c] = czero<C>();
@@ -456,7 +464,8 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const int mt = blockIdx.x;
   const int2 tm = tmap[mt];
   const int a = tm.x;
-  const FrontDev f = fronts[ids[a]];
+  const int raw = ids[a];
+  const FrontDev f = fronts[raw & kFrontIdMask];
   const SolveTask tk = tasks[a];
   const LayerDev& L = layers[f.layer];
   const int n = f.s + f.b;
@@ -515,7 +524,7 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
         if (gl == c) z = acc[r][c];
       const long long idx = (long long)(f.off + m) * KC + gl;
       if (tk.nch_b > 1) st(S + (tk.scr_b + (long long)chunk * f.s + m) * KC + gl, z);
-      else st(X + idx, cadd(ld(Z + idx), z));
+      else st(X + idx, cadd(ld_or_zero(!(raw & kZeroZ), Z + idx), z));
     }
   }
 }

@@ -108,6 +108,15 @@ kern::ReadTerms Method::terms(const double2* a, double ca, double cb, const doub
 
 void Method::solve_single(int l) { H.solve_layers(*single[l], k); }
 
+// A single-layer solve whose sources lie on the interface planes of `src`
+// and whose result is read on those of `read` (kPruneTop / kPruneBottom):
+// the launch lists keep only the fronts those planes reach (the result on
+// the read-out planes is unchanged); HELM_FLAG_NO_PRUNE runs every front.
+void Method::solve_planes(int l, int src, int read) {
+  if (H.opt.flags & HELM_FLAG_NO_PRUNE) solve_single(l);
+  else H.solve_layers(H.pruned_set(l, src, read), k);
+}
+
 // (zd, zu) = P (vd, vu); vu may be null (zero)
 void Method::apply_P(const double2* vd, const double2* vu, double2* od, double2* ou) {
   const int L = H.G.L;
@@ -174,21 +183,22 @@ void Method::apply_A(const double2* x, double2* out) {
   double2* kp = keep.as<double2>();
   if (L >= 2) {
     // z_down_0 = -(U x_up)_0
+    constexpr int T = kPruneTop, B = kPruneBottom;
     zero_X(0);
     jump(0, pair(xu, 0), nullptr, 1, -1.0);
-    solve_single(0);
+    solve_planes(0, B, B);
     readout(0, 1, 1.0, terms(pair(xu, 0), 1, 0), pair(od, 0));
     for (int l = 1; l <= L - 2; ++l) {
       zero_X(l);
       jump(l, pair(od, l - 1), pair(xu, l - 1), 0, 1.0, -1.0);
       jump(l, pair(xu, l), nullptr, 1, -1.0);
-      solve_single(l);
+      solve_planes(l, T | B, T | B);
       readout(l, 1, 1.0, terms(pair(xu, l), 1, 0), pair(od, l));
       readout(l, 0, 1.0, terms(), pair(kp, l - 1));      // keep_{l-1} - V_{l-1}
     }
     zero_X(L - 1);
     jump(L - 1, pair(od, L - 2), nullptr, 0);
-    solve_single(L - 1);
+    solve_planes(L - 1, T, T);
     readout(L - 1, 0, 1.0, terms(), pair(kp, L - 2));    // keep_{L-2}
     // upward: z_up_{L-2} = keep_{L-2} - (0, z_down_{L-2,b})
     readout(L - 1, 0, 0.0, terms(pair(kp, L - 2), 1, 1, pair(od, L - 2), 0, -1),
@@ -197,7 +207,7 @@ void Method::apply_A(const double2* x, double2* out) {
       zero_X(j + 1);
       jump(j + 1, pair(ou, j + 1), pair(od, j + 1), 1, 1.0, 1.0, pair(xu, j + 1), 1.0);
       jump(j + 1, pair(xu, j), nullptr, 0);
-      solve_single(j + 1);
+      solve_planes(j + 1, T | B, T);
       readout(j + 1, 0, 1.0, terms(pair(kp, j), 1, 1, pair(od, j), 0, -1), pair(ou, j));
     }
   }

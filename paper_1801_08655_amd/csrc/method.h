@@ -42,6 +42,7 @@ struct Method {
                                double cb_b = 0, const double2* c = nullptr,
                                double cc_a = 0, double cc_b = 0);
   void solve_single(int l);
+  void solve_planes(int l, int src, int read);
   void apply_P(const double2* vd, const double2* vu, double2* od, double2* ou);
   void apply_U(const double2* xu, double2* out);
   void apply_A(const double2* x, double2* out);

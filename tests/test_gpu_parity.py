@@ -106,6 +106,38 @@ def test_interface_operators_match_oracle(homog):
     assert relative_error(ga, ref)[0] <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["homogeneous-25", "layered-28", "layered-40"])
+def test_pruned_sweep_solves_match_full_solves(name):
+    """P M applied with the sweep solves pruned to the fronts their interface
+    sources and read-outs reach (the default) and with every front
+    (HELM_FLAG_NO_PRUNE): the skipped work is exact zeros, so the results
+    agree to rounding (the split of the pruned lists' GEMMs may differ), and
+    both match the oracle's P (M x)."""
+    import paper_1801_08655_amd as pt
+    wl = workload(name)
+    pb = _problem(wl)
+    k = 3
+    nx, ny, _ = wl.n
+    Lm = wl.n_layers - 1
+    x = _rand((2 * Lm * 2 * ny * nx * k,), 91)
+    gx = torch.from_numpy(x).cuda()
+    full = _solver(wl, "fp64", flags=pt._lib.HELM_FLAG_NO_PRUNE).polarized_op(1, gx, k)
+    pruned = _solver(wl, "fp64").polarized_op(1, gx, k)
+    a, b = pruned.cpu().numpy(), full.cpu().numpy()
+    dev = np.linalg.norm(a - b) / np.linalg.norm(b)
+    print(name, "pruned vs full", dev)
+    assert dev <= 1e-12
+    # the oracle's P (M x) column by column
+    pt_cpu = PolarizedTraces(pb, wl.n_layers, wl.pml_local)
+    half = Lm * 2 * ny * nx * k
+    xd = x[:half].reshape(Lm, 2, ny, nx, k)
+    xu = x[half:].reshape(Lm, 2, ny, nx, k)
+    refs = [pt_cpu.precondition(*pt_cpu.apply_M(xd[..., c], xu[..., c])) for c in range(k)]
+    ref = np.concatenate([_pairs_gpu_layout([r[0] for r in refs]),
+                          _pairs_gpu_layout([r[1] for r in refs])])
+    assert relative_error(a, ref)[0] <= 1e-10
+
+
 def test_profile_flags_time_only_what_they_name(homog):
     """HELM_FLAG_PROFILE times every substitution kernel class,
     HELM_FLAG_PROFILE_FWD only the forward GEMM; timing never changes the
