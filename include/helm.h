@@ -82,6 +82,16 @@ extern "C" {
                                 "Local Solves: Parallel Multi-frontal Methods":
                                 sources supported on the interfaces, only the
                                 boundary values needed)                       */
+#define HELM_FLAG_GEMM_4M 512 /* complex64 substitution GEMMs form each complex
+                                product from four real matrix-core products;
+                                by default they take three (Pr Qr, Pi Qi and
+                                (Pr + Pi)(Qr + Qi)), whose rounding error is
+                                bounded in norm rather than per component.
+                                No effect on HELM_FP64 handles               */
+#define HELM_FLAG_FACTOR_3M 1024 /* the complex64 factorization's sweep GEMM
+                                forms each complex product from three real
+                                products (default: four).  No effect on
+                                HELM_FP64 handles                            */
 #define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
                                 the factorization leaves one leaf front of
                                 layer 0 unassembled, so its pivots are exactly

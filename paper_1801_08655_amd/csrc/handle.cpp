@@ -113,6 +113,17 @@ void Handle::set_profile(int flags) {
   profile_mask = 0;
   if (flags & HELM_FLAG_PROFILE) profile_mask = (1u << K_NCLASS) - 1;
   if (flags & HELM_FLAG_PROFILE_FWD) profile_mask |= 1u << K_FWD_GEMM;
+  // the product forms of the complex64 GEMMs; graphs and tile choices made
+  // with the other substitution form are dropped
+  factor3m = prec == HELM_MIXED && (flags & HELM_FLAG_FACTOR_3M);
+  const bool m3 = prec == HELM_MIXED && !(flags & HELM_FLAG_GEMM_4M);
+  if (m3 != gemm3m) {
+    if (st) HELM_HIP(hipStreamSynchronize(st));
+    clear_graphs();
+    tiles.clear();
+    tuned.clear();
+    gemm3m = m3;
+  }
 }
 
 // An event recorded on the handle's stream, for the timing of class cls
@@ -499,7 +510,7 @@ void Handle::factorize_t() {
         prof_end(K_SWAP_JO, e1, 0, 0);
         e1 = prof_begin(K_SWEEP_GEMM);
         kern::launch_sweep_gemm<T>(fr, ids, n_act, fd.pFull.as<int2>(), fd.pFull_h[n_act],
-                                   k, nb, ws0.p, ws1.p, st);
+                                   k, nb, ws0.p, ws1.p, factor3m, st);
         prof_end(K_SWEEP_GEMM, e1, sw_flops, sw_bytes);
         e1 = prof_begin(K_UPDATE_OJ);
         kern::launch_update_OJ<T>(fr, ids, n_act, fd.pCol.as<int2>(), fd.pCol_h[n_act], k,
@@ -796,7 +807,7 @@ void Handle::launch_fwd(const DepthList& D, const FrontDev* fr, const LayerDev* 
                              D.pF.as<int2>(), D.tF, ld, k, scr, st, t0, t1);
   else
     kern::launch_fwd_gemm<T>(fr, D.idsL.as<int>(), D.tasksL.as<SolveTask>(), D.nL,
-                             D.pF.as<int2>(), D.tF, ld, k, scr, bn, st, t0, t1);
+                             D.pF.as<int2>(), D.tF, ld, k, scr, bn, gemm3m, st, t0, t1);
 }
 template <typename T>
 void Handle::launch_bwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
@@ -806,7 +817,7 @@ void Handle::launch_bwd(const DepthList& D, const FrontDev* fr, const LayerDev* 
                              D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, st);
   else
     kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
-                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, bn, st);
+                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, bn, gemm3m, st);
 }
 
 const std::vector<Handle::TileChoice>& Handle::tile_plan(const LayerSet& set, int k) {

@@ -47,9 +47,10 @@ void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
                     const long long* panel_off, const long long* perm_off,
                     hipStream_t st);
 template <typename T>
+// m3: three real products per complex product (complex64 only)
 void launch_sweep_gemm(const FrontDev* fronts, const int* ids, int n_active,
                        const int2* tmap, int total, int k, int nb, void* ws0,
-                       void* ws1, hipStream_t st);
+                       void* ws1, bool m3, hipStream_t st);
 template <typename T>
 void launch_update_OJ(const FrontDev* fronts, const int* ids, int n_active,
                       const int2* tmap, int total, int k, int nb, void* ws0,
@@ -67,10 +68,12 @@ void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tm
                        int total, const LayerDev* layers, int k, hipStream_t st);
 template <typename T>
 // t0 / t1 non-null: the launch records its own start and stop in them
-// (timing of the kernel alone, without event commands around it)
+// (timing of the kernel alone, without event commands around it).
+// m3: three real products per complex product (complex64 only; ignored for
+// complex128).
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bn, hipStream_t st, hipEvent_t t0 = nullptr,
+                     void* scratch, int bn, bool m3, hipStream_t st, hipEvent_t t0 = nullptr,
                      hipEvent_t t1 = nullptr);
 // vector path of the substitutions for k <= 4 columns (same tiles and
 // scratch layout as launch_fwd_gemm / launch_bwd_gemm with 64-row tiles)
@@ -90,7 +93,7 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, int bn, hipStream_t st);
+                     void* scratch, int bm, int bn, bool m3, hipStream_t st);
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int2* tmap, int total, const LayerDev* layers, int k,

@@ -187,10 +187,22 @@ template <int W> constexpr int kmajor_stride() {
   static_assert(W == 16 || W == 32 || W == 64, "k-major rows are padded for 16, 32 or 64");
   return W == 64 ? 80 : 48;
 }
-template <typename T, int BM, int BN = GT, bool PKM = false> struct GemmSmem {
-  T P[PKM ? 2 * GK : BM][PKM ? kmajor_stride<BM>() : PSTR];
-  T Q1[2 * GK][kmajor_stride<BN>()];
-  T Q2[2 * GK][kmajor_stride<BN>()];
+//
+// The three-product form (M3, complex64 substitutions): the complex product
+// is formed from the real products Pr Qr, Pi Qi and (Pr + Pi)(Qr + Qi)
+// (re = t1 - t2, im = t3 - t1 - t2), so a complex multiply-add costs three
+// real ones on the matrix cores instead of four.  Each operand is staged as
+// three real planes of GK rows (k-major P and Q: plane * GK + k; row-major
+// P: r, plane * GK + k with stride 3 GK + 4, which puts the 16 rows of a read
+// on distinct multiples of 4 banks, offset by k).  Its rounding error is
+// bounded in norm, not element by element: an imaginary part much smaller
+// than |P||Q| carries a larger relative error than in the four-product form.
+constexpr int PSTR3 = 3 * GK + 4;
+template <typename T, int BM, int BN = GT, bool PKM = false, bool M3 = false> struct GemmSmem {
+  static constexpr int NPL = M3 ? 3 : 2;   // real rows per complex k
+  T P[PKM ? NPL * GK : BM][PKM ? kmajor_stride<BM>() : (M3 ? PSTR3 : PSTR)];
+  T Q1[NPL * GK][kmajor_stride<BN>()];
+  T Q2[M3 ? 1 : 2 * GK][kmajor_stride<BN>()];
 };
 
 // The 4 waves of a block tile it as WR x WC sub-tiles of RW x CW, each made
@@ -259,8 +271,8 @@ __device__ __forceinline__ void stage_load(Stage<T, BM, BN>& g, const View<T>& p
   }
 }
 
-template <typename T, int BM, int BN, bool FAST_R, bool FAST_C>
-__device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN, FAST_R>& sm,
+template <typename T, int BM, int BN, bool FAST_R, bool FAST_C, bool M3 = false>
+__device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN, FAST_R, M3>& sm,
                                             const Stage<T, BM, BN>& g) {
   const int t = threadIdx.x;
 #pragma unroll
@@ -268,12 +280,23 @@ __device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN, FAST_R>& sm,
     const int e = t + it * 256;
     int r, k;
     if (FAST_R) { r = e % BM; k = e / BM; } else { k = e % GK; r = e / GK; }
-    if (FAST_R) {
-      sm.P[2 * k][r] = g.p[it].x;
-      sm.P[2 * k + 1][r] = g.p[it].y;
+    const C_t<T> x = g.p[it];
+    if constexpr (M3) {
+      if (FAST_R) {
+        sm.P[k][r] = x.x;
+        sm.P[GK + k][r] = x.y;
+        sm.P[2 * GK + k][r] = x.x + x.y;
+      } else {
+        sm.P[r][k] = x.x;
+        sm.P[r][GK + k] = x.y;
+        sm.P[r][2 * GK + k] = x.x + x.y;
+      }
+    } else if (FAST_R) {
+      sm.P[2 * k][r] = x.x;
+      sm.P[2 * k + 1][r] = x.y;
     } else {
-      sm.P[r][2 * k] = g.p[it].x;
-      sm.P[r][2 * k + 1] = g.p[it].y;
+      sm.P[r][2 * k] = x.x;
+      sm.P[r][2 * k + 1] = x.y;
     }
   }
 #pragma unroll
@@ -282,30 +305,86 @@ __device__ __forceinline__ void stage_store(GemmSmem<T, BM, BN, FAST_R>& sm,
     int c, kq;
     if (FAST_C) { c = e % BN; kq = e / BN; } else { kq = e % GK; c = e / GK; }
     const C_t<T> y = g.q[it];
-    sm.Q1[2 * kq][c] = y.x;
-    sm.Q1[2 * kq + 1][c] = -y.y;
-    sm.Q2[2 * kq][c] = y.y;
-    sm.Q2[2 * kq + 1][c] = y.x;
+    if constexpr (M3) {
+      sm.Q1[kq][c] = y.x;
+      sm.Q1[GK + kq][c] = y.y;
+      sm.Q1[2 * GK + kq][c] = y.x + y.y;
+    } else {
+      sm.Q1[2 * kq][c] = y.x;
+      sm.Q1[2 * kq + 1][c] = -y.y;
+      sm.Q2[2 * kq][c] = y.y;
+      sm.Q2[2 * kq + 1][c] = y.x;
+    }
   }
 }
 
 // Accumulators of one wave: its RW x CW complex sub-tile as MB x NB MFMA
 // 16x16 blocks (real and imaginary parts).
-template <typename T, int BM, int BN = GT> struct WaveAcc {
+// In the three-product form re, t and im accumulate Pr Qr, Pi Qi and
+// (Pr + Pi)(Qr + Qi) until finish() turns them into the real and imaginary
+// parts.
+template <typename T, int BM, int BN = GT, bool M3 = false> struct WaveAcc {
   using G = WaveGrid<BM, BN>;
   typename Mfma<T>::v4 re[G::MB][G::NB], im[G::MB][G::NB];
+  typename Mfma<T>::v4 t[M3 ? G::MB : 1][M3 ? G::NB : 1];
   __device__ void zero() {
 #pragma unroll
     for (int a = 0; a < G::MB; ++a)
 #pragma unroll
       for (int b = 0; b < G::NB; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { re[a][b][v] = 0; im[a][b][v] = 0; }
+        for (int v = 0; v < 4; ++v) {
+          re[a][b][v] = 0;
+          im[a][b][v] = 0;
+          if (M3) t[M3 ? a : 0][M3 ? b : 0][v] = 0;
+        }
+  }
+  __device__ void finish() {
+    if constexpr (M3) {
+#pragma unroll
+      for (int a = 0; a < G::MB; ++a)
+#pragma unroll
+        for (int b = 0; b < G::NB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T t1 = re[a][b][v], t2 = t[a][b][v];
+            re[a][b][v] = t1 - t2;
+            im[a][b][v] = im[a][b][v] - t1 - t2;
+          }
+    }
   }
 };
 
 // One sub-step (4 real K = 2 complex) of MFMAs for this wave: lane l
 // supplies A'[l%16][l/16] and B'[l/16][l%16] of each 16x16x4 block (real form).
+// Three-product sub-step: 4 complex K, lane l at complex k = kk (plane rows
+// kk, GK + kk, 2 GK + kk).
+template <typename T, int BM, int BN, bool PKM>
+__device__ __forceinline__ void mfma_sub3(const GemmSmem<T, BM, BN, PKM, true>& sm,
+                                          WaveAcc<T, BM, BN, true>& acc, int wr, int wc,
+                                          int li, int kk) {
+  using G = WaveGrid<BM, BN>;
+  T a[3][G::MB], b[3][G::NB];
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl) {
+#pragma unroll
+    for (int bm = 0; bm < G::MB; ++bm) {
+      const int r = wr * G::RW + bm * 16 + li;
+      a[pl][bm] = PKM ? sm.P[pl * GK + kk][r] : sm.P[r][pl * GK + kk];
+    }
+#pragma unroll
+    for (int bn = 0; bn < G::NB; ++bn) b[pl][bn] = sm.Q1[pl * GK + kk][wc * G::CW + bn * 16 + li];
+  }
+#pragma unroll
+  for (int bm = 0; bm < G::MB; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < G::NB; ++bn) {
+      acc.re[bm][bn] = Mfma<T>::op(a[0][bm], b[0][bn], acc.re[bm][bn]);
+      acc.t[bm][bn] = Mfma<T>::op(a[1][bm], b[1][bn], acc.t[bm][bn]);
+      acc.im[bm][bn] = Mfma<T>::op(a[2][bm], b[2][bn], acc.im[bm][bn]);
+    }
+}
+
 template <typename T, int BM, int BN, bool PKM>
 __device__ __forceinline__ void mfma_sub(const GemmSmem<T, BM, BN, PKM>& sm,
                                          WaveAcc<T, BM, BN>& acc, int wr, int wc, int li,
@@ -337,12 +416,23 @@ __device__ __forceinline__ void mfma_sub(const GemmSmem<T, BM, BN, PKM>& sm,
 // the extra registers cost more than that gains); otherwise the sub-steps
 // past the valid complex columns of a partial last step (zero-filled in LDS)
 // are skipped (kvalid is the same for the whole block).
-template <typename T, int BM, int BN, bool PKM>
-__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN, PKM>& sm,
-                                          WaveAcc<T, BM, BN>& acc, int wr, int wc, int lane,
+template <typename T, int BM, int BN, bool PKM, bool M3>
+__device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN, PKM, M3>& sm,
+                                          WaveAcc<T, BM, BN, M3>& acc, int wr, int wc, int lane,
                                           int kvalid) {
   const int li = lane & 15, lq = lane >> 4;
-  if (sizeof(T) == 4 && kvalid >= GK) {
+  if constexpr (M3) {
+    if (kvalid >= GK) {
+#pragma unroll
+      for (int p = 0; p < GK / 4; ++p) mfma_sub3<T, BM, BN, PKM>(sm, acc, wr, wc, li, 4 * p + lq);
+    } else {
+#pragma unroll
+      for (int p = 0; p < GK / 4; ++p) {
+        if (4 * p >= kvalid) break;
+        mfma_sub3<T, BM, BN, PKM>(sm, acc, wr, wc, li, 4 * p + lq);
+      }
+    }
+  } else if (sizeof(T) == 4 && kvalid >= GK) {
 #pragma unroll
     for (int p = 0; p < GK / 2; ++p) mfma_sub<T, BM, BN, PKM>(sm, acc, wr, wc, li, 4 * p + lq);
   } else {
@@ -358,9 +448,9 @@ __device__ __forceinline__ void mfma_step(const GemmSmem<T, BM, BN, PKM>& sm,
 // starting at r0, columns of Q from `qv` starting at c0.  The global loads
 // of the next K step are issued before the matrix-core work of the current
 // one, so their latency overlaps the MFMAs.
-template <typename T, int BM, bool P_FAST_R, bool Q_FAST_C, int BN>
-__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN, P_FAST_R>& sm,
-                                          WaveAcc<T, BM, BN>& acc,
+template <typename T, int BM, bool P_FAST_R, bool Q_FAST_C, int BN, bool M3 = false>
+__device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN, P_FAST_R, M3>& sm,
+                                          WaveAcc<T, BM, BN, M3>& acc,
                                           const View<T>& pv, const View<T>& qv,
                                           int r0, int c0, int kbeg, int kend) {
   using G = WaveGrid<BM, BN>;
@@ -373,15 +463,16 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<T, BM, BN, P_FAST_R>& sm,
   stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, kbeg, kend);
   stage_index<T, BM, BN, Q_FAST_C>(g, qv, kbeg + GK, kend);
   for (int k0 = kbeg; k0 < kend; k0 += GK) {
-    stage_store<T, BM, BN, P_FAST_R, Q_FAST_C>(sm, g);
+    stage_store<T, BM, BN, P_FAST_R, Q_FAST_C, M3>(sm, g);
     __syncthreads();
     if (k0 + GK < kend) {
       stage_load<T, BM, BN, P_FAST_R, Q_FAST_C>(g, pv, qv, r0, c0, k0 + GK, kend);
       stage_index<T, BM, BN, Q_FAST_C>(g, qv, k0 + 2 * GK, kend);
     }
-    mfma_step<T, BM, BN, P_FAST_R>(sm, acc, wr, wc, lane, kend - k0);
+    mfma_step<T, BM, BN, P_FAST_R, M3>(sm, acc, wr, wc, lane, kend - k0);
     __syncthreads();
   }
+  acc.finish();
 }
 
 // Output rows and columns (tile offsets) of this lane's accumulators, in the
@@ -402,8 +493,8 @@ template <typename T, int BM, int BN> struct LaneOut {
   }
 };
 
-template <typename T, int BM, int BN>
-__device__ __forceinline__ C_t<T> acc_at(const WaveAcc<T, BM, BN>& acc, int i, int j) {
+template <typename T, int BM, int BN, bool M3>
+__device__ __forceinline__ C_t<T> acc_at(const WaveAcc<T, BM, BN, M3>& acc, int i, int j) {
   C_t<T> z;
   z.x = acc.re[i / 4][j][i % 4];
   z.y = acc.im[i / 4][j][i % 4];
@@ -412,8 +503,8 @@ __device__ __forceinline__ C_t<T> acc_at(const WaveAcc<T, BM, BN>& acc, int i, i
 
 // Visit this lane's outputs: f(r, c, value) with r (0..BM-1), c (0..BN-1) the
 // tile-local MFMA row / column.
-template <typename T, int BM, int BN, class F>
-__device__ __forceinline__ void for_each_acc(const WaveAcc<T, BM, BN>& acc, F&& f) {
+template <typename T, int BM, int BN, bool M3, class F>
+__device__ __forceinline__ void for_each_acc(const WaveAcc<T, BM, BN, M3>& acc, F&& f) {
   using G = WaveGrid<BM, BN>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave / G::WC, wc = wave % G::WC;

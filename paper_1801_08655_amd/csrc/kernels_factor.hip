@@ -509,13 +509,13 @@ k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // the parent's extend-add (the Schur block) ever reads.  Tiles that lie
 // wholly in J or in that block return at once.
 // --------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
+template <typename T, bool M3>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (M3 ? 3 : 4) : 1, 8)))
 k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
              int n_active, const int2* __restrict__ tmap, int k, int nb,
              void* ws0, void* ws1) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T, 64, 64, false> sm;
+  __shared__ GemmSmem<T, 64, 64, false, M3> sm;
   const int2 tm = tmap[blockIdx.x];
   const int a = tm.x;
   const FrontDev f = fronts[ids[a]];
@@ -532,7 +532,7 @@ k_sweep_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> pv{F + k, (long long)n, 1, n, nbf};
   // Q columns = C rows i: A^T(q, i) = F[i + (k+q) n]
   View<T> qv{F + (long long)k * n, 1, (long long)n, n, nbf};
-  WaveAcc<T, 64> acc;
+  WaveAcc<T, 64, 64, M3> acc;
   gemm_tile<T, 64, false, true>(sm, acc, pv, qv, j0, i0, 0, nbf);
   // F(i, j) -= acc: every entry of the lane is loaded before the first store
   // (one latency for the group instead of a load-store chain per entry)
@@ -703,10 +703,15 @@ void launch_swap_JO(const FrontDev* fronts, const int* ids, int n_active,
 template <typename T>
 void launch_sweep_gemm(const FrontDev* fronts, const int* ids, int n_active,
                        const int2* tmap, int total, int k, int nb, void* ws0,
-                       void* ws1, hipStream_t st) {
+                       void* ws1, bool m3, hipStream_t st) {
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_sweep_gemm<T>, dim3(total), dim3(256), 0, st, fronts, ids,
-                     n_active, tmap, k, nb, ws0, ws1);
+  constexpr bool C64 = sizeof(T) == 4;   // the three-product form is for complex64
+  if (C64 && m3)
+    hipLaunchKernelGGL((k_sweep_gemm<T, C64>), dim3(total), dim3(256), 0, st, fronts, ids,
+                       n_active, tmap, k, nb, ws0, ws1);
+  else
+    hipLaunchKernelGGL((k_sweep_gemm<T, false>), dim3(total), dim3(256), 0, st, fronts, ids,
+                       n_active, tmap, k, nb, ws0, ws1);
 }
 template <typename T>
 void launch_update_OJ(const FrontDev* fronts, const int* ids, int n_active,
@@ -743,7 +748,7 @@ void launch_store_factor(const FrontDev* fronts, const int* ids, int n_ids,
                                   const int*, const long long*, const long long*,  \
                                   hipStream_t);                                    \
   template void launch_sweep_gemm<T>(const FrontDev*, const int*, int, const int2*, \
-                                     int, int, int, void*, void*, hipStream_t);    \
+                                     int, int, int, void*, void*, bool, hipStream_t); \
   template void launch_update_OJ<T>(const FrontDev*, const int*, int, const int2*,  \
                                     int, int, int, void*, void*, const void*,      \
                                     const long long*, hipStream_t);                \

@@ -108,9 +108,13 @@ k_fwd_gather(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // substitution GEMM tiles: 4 for the complex64 tiles, which then fit in 128
 // registers without spilling (at its default the compiler spends up to
 // ~160 on hoisting LDS reads and drops to 3 waves, which measured slower);
-// no floor for the 64 x 64 and the complex128 tiles, which would spill.
-template <typename T, int BM, int BN> constexpr int gemm_waves() {
-  return (sizeof(T) == 4 && !(BM == 64 && BN == 64)) ? 4 : 1;
+// 3 for the three-product 64 x 64 tile (2 at the compiler's default); no
+// floor for the four-product 64 x 64 and the complex128 tiles, which would
+// spill.
+template <typename T, int BM, int BN, bool M3> constexpr int gemm_waves() {
+  if (sizeof(T) != 4) return 1;
+  if (BM == 64 && BN == 64) return M3 ? 3 : 1;
+  return 4;
 }
 
 // Forward GEMM epilogue of an unsplit front: pivot rows to Z, boundary rows
@@ -118,8 +122,8 @@ template <typename T, int BM, int BN> constexpr int gemm_waves() {
 // all of this lane's outputs are loaded first, then the child values, then
 // the results are stored, so that the latencies of each group of loads
 // overlap instead of following one another output by output.
-template <typename T, int BM, int BN>
-__device__ __forceinline__ void fwd_epilogue(const WaveAcc<T, BM, BN>& acc, const FrontDev& f,
+template <typename T, int BM, int BN, bool M3>
+__device__ __forceinline__ void fwd_epilogue(const WaveAcc<T, BM, BN, M3>& acc, const FrontDev& f,
                                              const ChildSum<T>& cs, C_t<T>* Z, C_t<T>* Uo,
                                              int m0, int n0, int k) {
   using C = C_t<T>;
@@ -166,14 +170,15 @@ __device__ __forceinline__ void fwd_epilogue(const WaveAcc<T, BM, BN>& acc, cons
 
 // forward, step 2: [X(S); Ub] = [F11^-1 w_S; Ub - F21 F11^-1 w_S], the K
 // (pivot) dimension optionally split into chunks (partials to scratch).
-template <typename T, int BN>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<T, FWD_BM, BN>(), 8)))
+// M3: the three-product complex form (complex64 only).
+template <typename T, int BN, bool M3>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<T, FWD_BM, BN, M3>(), 8)))
 k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
   constexpr int BM = FWD_BM;
-  __shared__ GemmSmem<T, BM, BN, true> sm;
+  __shared__ GemmSmem<T, BM, BN, true, M3> sm;
   const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int2 tm = tmap[mt];
@@ -193,7 +198,7 @@ k_fwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   const C* X = reinterpret_cast<const C*>(L.X);
   View<T> pv{FT, 1, (long long)n, n, f.s};
   View<T> qv{X + (long long)f.off * k, 1, (long long)k, k, f.s};
-  WaveAcc<T, BM, BN> acc;
+  WaveAcc<T, BM, BN, M3> acc;
   gemm_tile<T, BM, true, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   if (tk.nch_f > 1) {
     C* S = reinterpret_cast<C*>(scratch);
@@ -257,13 +262,13 @@ k_fwd_reduce(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // backward: X(S) = Z(S) + (-F21 F11^-1)^T X(B); X(B) is read in place
 // through the front's boundary index list, the K (boundary) dimension
 // optionally split.  Fronts without boundary (roots) just copy Z(S).
-template <typename T, int BM, int BN>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<T, BM, BN>(), 8)))
+template <typename T, int BM, int BN, bool M3>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<T, BM, BN, M3>(), 8)))
 k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            const SolveTask* __restrict__ tasks, int n_ids, const int2* __restrict__ tmap,
            const LayerDev* __restrict__ layers, int k, void* scratch) {
   using C = C_t<T>;
-  __shared__ GemmSmem<T, BM, BN, false> sm;
+  __shared__ GemmSmem<T, BM, BN, false, M3> sm;
   const int ntn = (k + BN - 1) / BN;
   const int mt = blockIdx.x / ntn, nt = blockIdx.x % ntn;
   const int2 tm = tmap[mt];
@@ -284,7 +289,7 @@ k_bwd_gemm(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   View<T> pv{FT + f.s, (long long)n, 1, f.s, f.b};
   // Q(c, q) = X[B[q] k + c]
   View<T> qv{X, 1, (long long)k, k, f.b, L.bidx + f.bidx};
-  WaveAcc<T, BM, BN> acc;
+  WaveAcc<T, BM, BN, M3> acc;
   gemm_tile<T, BM, false, true>(sm, acc, pv, qv, m0, n0, kb, ke);
   if (tk.nch_b > 1) {
     C* S = reinterpret_cast<C*>(scratch);
@@ -587,23 +592,23 @@ void launch_fwd_gather(const FrontDev* fr, const int* ids, int n, const int2* tm
 template <typename T>
 void launch_fwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bn, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+                     void* scratch, int bn, bool m3, hipStream_t st, hipEvent_t t0,
+                     hipEvent_t t1) {
   if (total_tiles <= 0) return;
   const int ntn = (k + bn - 1) / bn;
   const dim3 grid(total_tiles * ntn);
-#define HELM_FWD(BN_)                                                                       \
+#define HELM_FWD(BN_, M3_)                                                                  \
   if (t0)                                                                                   \
-    hipExtLaunchKernelGGL((k_fwd_gemm<T, BN_>), grid, dim3(256), 0, st, t0, t1, 0, fr, ids, \
-                          tasks, n, tmap, layers, k, scratch);                              \
+    hipExtLaunchKernelGGL((k_fwd_gemm<T, BN_, M3_>), grid, dim3(256), 0, st, t0, t1, 0, fr, \
+                          ids, tasks, n, tmap, layers, k, scratch);                         \
   else                                                                                      \
-    hipLaunchKernelGGL((k_fwd_gemm<T, BN_>), grid, dim3(256), 0, st, fr, ids, tasks, n,     \
-                       tmap, layers, k, scratch)
-  if (bn == 16) {
-    HELM_FWD(16);
-  } else if (bn == 32) {
-    HELM_FWD(32);
+    hipLaunchKernelGGL((k_fwd_gemm<T, BN_, M3_>), grid, dim3(256), 0, st, fr, ids, tasks,   \
+                       n, tmap, layers, k, scratch)
+  constexpr bool C64 = sizeof(T) == 4;   // the three-product form is for complex64
+  if (C64 && m3) {
+    if (bn == 16) HELM_FWD(16, C64); else if (bn == 32) HELM_FWD(32, C64); else HELM_FWD(64, C64);
   } else {
-    HELM_FWD(64);
+    if (bn == 16) HELM_FWD(16, false); else if (bn == 32) HELM_FWD(32, false); else HELM_FWD(64, false);
   }
 #undef HELM_FWD
 }
@@ -622,20 +627,30 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, int bn, hipStream_t st) {
+                     void* scratch, int bm, int bn, bool m3, hipStream_t st) {
   if (total_tiles <= 0) return;
   // a 32 x 16 tile has fewer MFMA blocks than waves: use 32 columns there
   if (bm == 32 && bn == 16) bn = 32;
   const int ntn = (k + bn - 1) / bn;
   const dim3 grid(total_tiles * ntn);
-#define HELM_BWD(BM_, BN_)                                                              \
-  hipLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_>), grid, dim3(256), 0, st, fr, ids, tasks, \
+#define HELM_BWD(BM_, BN_, M3_)                                                              \
+  hipLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_, M3_>), grid, dim3(256), 0, st, fr, ids, tasks, \
                      n, tmap, layers, k, scratch)
-  if (bm == 32) {
-    if (bn == 32) HELM_BWD(32, 32); else HELM_BWD(32, 64);
-  } else {
-    if (bn == 16) HELM_BWD(64, 16); else if (bn == 32) HELM_BWD(64, 32); else HELM_BWD(64, 64);
+#define HELM_BWD_ALL(M3_)                                                                   \
+  if (bm == 32) {                                                                           \
+    if (bn == 32) HELM_BWD(32, 32, M3_); else HELM_BWD(32, 64, M3_);                        \
+  } else {                                                                                  \
+    if (bn == 16) HELM_BWD(64, 16, M3_);                                                    \
+    else if (bn == 32) HELM_BWD(64, 32, M3_);                                               \
+    else HELM_BWD(64, 64, M3_);                                                             \
   }
+  constexpr bool C64 = sizeof(T) == 4;   // the three-product form is for complex64
+  if (C64 && m3) {
+    HELM_BWD_ALL(C64)
+  } else {
+    HELM_BWD_ALL(false)
+  }
+#undef HELM_BWD_ALL
 #undef HELM_BWD
 }
 template <typename T>
@@ -656,13 +671,14 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                                      int, const LayerDev*, int, hipStream_t);        \
   template void launch_fwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
-                                   void*, int, hipStream_t, hipEvent_t, hipEvent_t); \
+                                   void*, int, bool, hipStream_t, hipEvent_t,         \
+                                   hipEvent_t);                                      \
   template void launch_fwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int2*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);                      \
   template void launch_bwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
-                                   void*, int, int, hipStream_t);                    \
+                                   void*, int, int, bool, hipStream_t);              \
   template void launch_bwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int2*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);

@@ -4,6 +4,8 @@
     python -m paper_1801_08655_amd.rocprof_summary traffic <fetch_dir> <write_dir>
         --kernel REGEX --copy REGEX --copy-bytes N --class NAME --out FILE
     python -m paper_1801_08655_amd.rocprof_summary mfma <dir> --class LABEL=REGEX ...
+    python -m paper_1801_08655_amd.rocprof_summary timeline <dir> --class LABEL=REGEX ...
+        [--flops-from PMC_DIR]
 
 ``stats`` prints the per-kernel table of a ``--kernel-trace --stats`` run.
 ``traffic`` combines a ``--pmc FETCH_SIZE`` run and a ``--pmc WRITE_SIZE``
@@ -162,6 +164,78 @@ def cmd_mfma(a):
               f"{flops / t / 1e3:.1f} |")
 
 
+def read_intervals(d):
+    """[(start ns, end ns, kernel name, queue)] of every dispatch of a
+    ``--kernel-trace`` run, sorted by start."""
+    rows = []
+    for path in _find(d, "*kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                q = r.get("Stream_Id") or r.get("Queue_Id") or "0"
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                             r["Kernel_Name"], q))
+    rows.sort()
+    return rows
+
+
+def _union(iv):
+    """Total length covered by the intervals [(start, end)] (sorted by start)."""
+    tot, cur_s, cur_e = 0, None, None
+    for s, e in iv:
+        if cur_e is None or s > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    if cur_e is not None:
+        tot += cur_e - cur_s
+    return tot
+
+
+def cmd_timeline(a):
+    """Concurrency of a kernel trace: the span from the first start to the
+    last end, the time at least one kernel runs, the mean number of kernels
+    in flight while any runs (summed durations over covered time), the
+    distinct streams, and per class the summed kernel time, the time the
+    class covers and, with --flops-from (a ``--pmc`` run of the same command
+    with SQ_INSTS_VALU_MFMA_MOPS_F32), the executed MFMA flops over the time
+    the class covers."""
+    rows = read_intervals(a.dir)
+    if not rows:
+        raise SystemExit("empty trace")
+    span = max(e for _, e, _, _ in rows) - rows[0][0]
+    busy = _union([(s, e) for s, e, _, _ in rows])
+    summed = sum(e - s for s, e, _, _ in rows)
+    # peak number of kernels in flight
+    ev = sorted([(s, 1) for s, _, _, _ in rows] + [(e, -1) for _, e, _, _ in rows])
+    cur = peak = 0
+    for _, d in ev:
+        cur += d
+        peak = max(peak, cur)
+    print(f"dispatches: {len(rows)}; streams: {len({q for *_, q in rows})}")
+    print(f"span {span / 1e9:.3f} s; some kernel running {busy / 1e9:.3f} s "
+          f"({busy / span:.3f} of the span); summed kernel time {summed / 1e9:.3f} s; "
+          f"mean kernels in flight while busy {summed / busy:.2f}; peak {peak}")
+    mops = {}
+    if a.flops_from:
+        for spec in a.cls:
+            label, rx = spec.split("=", 1)
+            vals = read_counters(a.flops_from, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+            mops[label] = sum(v for n, v in vals if re.search(rx, n))
+    print("| class | dispatches | summed ms | covered ms | mean in flight | executed TFLOP/s over covered time |")
+    print("|---|---|---|---|---|---|")
+    for spec in a.cls:
+        label, rx = spec.split("=", 1)
+        sel = [(s, e) for s, e, n, _ in rows if re.search(rx, n)]
+        if not sel:
+            continue
+        cov = _union(sel)
+        tot = sum(e - s for s, e in sel)
+        rate = f"{512.0 * mops[label] / cov / 1e3:.1f}" if label in mops else "-"
+        print(f"| {label} | {len(sel)} | {tot / 1e6:.1f} | {cov / 1e6:.1f} | {tot / cov:.2f} | {rate} |")
+
+
 def read_traffic(path):
     """Parsed ``key: value`` file written by ``traffic`` (None if missing)."""
     if not os.path.exists(path):
@@ -203,8 +277,15 @@ def main(argv=None):
     m.add_argument("--dtype", default="F32")
     m.add_argument("--simds", type=int, default=1024)
     m.add_argument("--xcds", type=int, default=8)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("dir")
+    tl.add_argument("--class", dest="cls", action="append", default=[],
+                    help="LABEL=REGEX of a kernel class (repeatable)")
+    tl.add_argument("--flops-from", default=None,
+                    help="directory of a --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 run of the same command")
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "mfma": cmd_mfma}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "mfma": cmd_mfma,
+     "timeline": cmd_timeline}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -4,7 +4,9 @@ an MI355X):
 * Bi-CGSTAB on the preconditioned polarized system (HELM_FLAG_BICGSTAB),
   on its up-going block and on the whole system;
 * GMRES on the unpolarized SIE of Algorithms 2-3 with the sign made
-  consistent (HELM_FLAG_UNPOLARIZED), without preconditioner.
+  consistent (HELM_FLAG_UNPOLARIZED), without preconditioner;
+* the product forms of the complex64 GEMMs (three or four real products
+  per complex product, in the substitutions and in the factorization).
 
 Each solution is compared column by column with the oracle's global direct
 solve (complex128 <= 1e-9 at tolerance 1e-10, mixed precision <= 1e-6), and
@@ -107,3 +109,58 @@ def test_variant_iteration_counts_follow_the_oracle(name):
     assert abs(got["unpolarized"][0] - it_u) <= max(2, it_u // 10)
     assert got["bicgstab"][1] < got["gmres"][1] or got["gmres"][0] <= 4
     assert got["unpolarized"][0] > got["gmres"][0]
+
+
+@pytest.mark.parametrize("k", [3, 21, 70])
+def test_product_forms_of_the_local_solve(k):
+    """complex64 local solves with three real products per complex product
+    (the default) and with four (HELM_FLAG_GEMM_4M), at batch widths that
+    reach the 16-, 32- and 64-column tiles and a ragged second 64-column
+    tile, each against SuperLU on the oracle's H^l; complex128 ignores the
+    flag bit for bit."""
+    import paper_1801_08655_amd as pt
+    from oracle.discretization import local_operator
+    wl = workload("homogeneous-25")
+    pb = Problem(wl.m(), wl.h, wl.omega, wl.pml, wl.pml_C)
+    nx, ny, nz = wl.n
+    l = 1
+    rng = np.random.default_rng(40 + k)
+    s3 = _solver(wl, "mixed")
+    s4 = _solver(wl, "mixed", flags=pt._lib.HELM_FLAG_GEMM_4M)
+    _, _, lo, hi = s3.layer_info(l)
+    t = hi - lo + 1
+    r = rng.standard_normal((k, t, ny, nx)) + 1j * rng.standard_normal((k, t, ny, nx))
+    rt = torch.from_numpy(r).cuda()
+    Hl = local_operator(pb, wl.n_layers, wl.pml_local, l)
+    ref = SparseLU(Hl).solve(r.reshape(k, -1).T)
+    e = {}
+    for name, s in (("3M", s3), ("4M", s4)):
+        w = s.layer_solve(l, rt).cpu().numpy()
+        e[name] = relative_error(w.reshape(k, -1).T, ref)
+        s.close()
+    print("k", k, "max rel err 3M", e["3M"].max(), "4M", e["4M"].max())
+    assert e["3M"].max() <= 2e-4 and e["4M"].max() <= 2e-4
+    d64 = _solver(wl, "fp64")
+    d64b = _solver(wl, "fp64", flags=pt._lib.HELM_FLAG_GEMM_4M | pt._lib.HELM_FLAG_FACTOR_3M)
+    a = d64.layer_solve(l, rt)
+    b = d64b.layer_solve(l, rt)
+    assert torch.equal(a, b)
+    assert relative_error(a.cpu().numpy().reshape(k, -1).T, ref).max() <= 1e-11
+
+
+@pytest.mark.parametrize("flags", ["GEMM_4M", "FACTOR_3M", "GEMM_4M|FACTOR_3M"])
+def test_product_forms_of_the_mixed_solve(flags):
+    """The whole mixed-precision method with the other product forms of the
+    complex64 GEMMs (the default form is covered by every other mixed test)
+    against the oracle's direct solve."""
+    import paper_1801_08655_amd as pt
+    wl, pb, srcs, F, ref = _case("layered-28")
+    fl = 0
+    for f in flags.split("|"):
+        fl |= getattr(pt._lib, "HELM_FLAG_" + f)
+    s = _solver(wl, "mixed", flags=fl, err_target=1e-6)
+    u, info = s.solve_points(srcs, info=True)
+    err = relative_error(u.cpu().numpy().reshape(len(srcs), -1).T, ref)
+    print(flags, "err", err, "refinement steps", info["ir_steps"])
+    assert err.max() <= 1e-6
+    s.close()
