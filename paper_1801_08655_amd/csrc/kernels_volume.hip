@@ -283,9 +283,10 @@ __global__ void k_axpy_cols(double2* __restrict__ y, const double2* __restrict__
   }
 }
 
-// y[v, c] = x[v, c] * s[c]  (s real, per column)
-__global__ void k_scale_cols(double2* __restrict__ y, const double2* __restrict__ x,
-                             const double* __restrict__ s, long long V, int k) {
+// y[v, c] = x[v, c] * s[c]  (s real, per column); y may be x (each element
+// is read and written by one thread), so y and x are not restrict
+__global__ void k_scale_cols(double2* y, const double2* x, const double* __restrict__ s,
+                             long long V, int k) {
   const long long total = V * k;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -295,9 +296,8 @@ __global__ void k_scale_cols(double2* __restrict__ y, const double2* __restrict_
   }
 }
 
-// y = x + z (elementwise)
-__global__ void k_add(double2* __restrict__ y, const double2* __restrict__ x,
-                      const double2* __restrict__ z, long long n) {
+// y = x + z (elementwise); y may be x or z
+__global__ void k_add(double2* y, const double2* x, const double2* z, long long n) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     y[e] = make_double2(x[e].x + z[e].x, x[e].y + z[e].y);
