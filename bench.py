@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--batch", action="store_true",
                     help="batched run instead: independent problems n in [64, 160]")
     ap.add_argument("--batch-count", type=int, default=32)
+    ap.add_argument("--batch-resident", type=int, default=0,
+                    help="at most this many problems resident at once (0: as many as "
+                         "memory admits; 1: one after the other, no overlap)")
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--rhs-scaling", action="store_true",
                     help="RHS/s against the number of right-hand sides R = 1, 2, ..., 64 "
@@ -364,7 +367,8 @@ def batch_bench(args, torch, pt):
     log(f"[batch] building {len(wls)} models")
     probs = [Problem(w.m(), w.h, w.omega, w.pml, w.n_layers, w.sources) for w in wls]
     log("[batch] solving")
-    res, summ = solve_batch(probs, slots=args.slots, host_output=True, precision="mixed",
+    res, summ = solve_batch(probs, slots=args.slots, max_resident=args.batch_resident,
+                            host_output=True, precision="mixed",
                             pml_local=4, ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4,
                             err_target=1e-6, ir_max_steps=4,
                             flags=pt._lib.HELM_FLAG_AUTOTUNE)
@@ -376,7 +380,8 @@ def batch_bench(args, torch, pt):
         "data": "synthetic",
         "config": {"workload": f"{len(wls)} problems, n in [64,160], 8-pt PML, smooth random "
                                "c in [0.8,1.2], 10 ppw, L=round(n/10), R in [1,256]",
-                   "slots_per_problem": args.slots, "n": [w.n[0] for w in wls],
+                   "slots_per_problem": args.slots, "max_resident": args.batch_resident,
+                   "n": [w.n[0] for w in wls],
                    "rhs": [len(w.sources) for w in wls]},
         "summary": summ,
         "all_ok": all(i["status"] == 0 for i in infos),
