@@ -202,6 +202,16 @@ def cmd_timeline(a):
     with SQ_INSTS_VALU_MFMA_MOPS_F32), the executed MFMA flops over the time
     the class covers."""
     rows = read_intervals(a.dir)
+    if a.window_match:
+        # the dispatches from the start of the window_from-th last match to the
+        # start of the window_to-th last match (0: to the end of the trace)
+        rx = re.compile(a.window_match)
+        starts = [s for s, _, n, _ in rows if rx.search(n)]
+        lo = starts[-a.window_from]
+        hi = starts[-a.window_to] if a.window_to > 0 else float("inf")
+        rows = [r for r in rows if lo <= r[0] < hi]
+        print(f"window: from the {a.window_from}-th last to the "
+              f"{a.window_to or 'end'}-th last dispatch matching `{a.window_match}`")
     if not rows:
         raise SystemExit("empty trace")
     span = max(e for _, e, _, _ in rows) - rows[0][0]
@@ -283,6 +293,10 @@ def main(argv=None):
                     help="LABEL=REGEX of a kernel class (repeatable)")
     tl.add_argument("--flops-from", default=None,
                     help="directory of a --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 run of the same command")
+    tl.add_argument("--window-match", default=None,
+                    help="restrict to a window delimited by dispatches matching this regex")
+    tl.add_argument("--window-from", type=int, default=0)
+    tl.add_argument("--window-to", type=int, default=0)
     a = ap.parse_args(argv)
     {"stats": cmd_stats, "traffic": cmd_traffic, "mfma": cmd_mfma,
      "timeline": cmd_timeline}[a.cmd](a)
