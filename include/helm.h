@@ -88,10 +88,11 @@ extern "C" {
                                 (Pr + Pi)(Qr + Qi)), whose rounding error is
                                 bounded in norm rather than per component.
                                 No effect on HELM_FP64 handles               */
-#define HELM_FLAG_FACTOR_3M 1024 /* the complex64 factorization's sweep GEMM
-                                forms each complex product from three real
-                                products (default: four).  No effect on
-                                HELM_FP64 handles                            */
+#define HELM_FLAG_FACTOR_4M 1024 /* the complex64 factorization's sweep GEMM
+                                forms each complex product from four real
+                                products (default: three, as the
+                                substitutions).  No effect on HELM_FP64
+                                handles                                      */
 #define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
                                 the factorization leaves one leaf front of
                                 layer 0 unassembled, so its pivots are exactly

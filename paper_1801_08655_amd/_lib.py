@@ -42,7 +42,7 @@ HELM_FLAG_BICGSTAB = 64
 HELM_FLAG_UNPOLARIZED = 128
 HELM_FLAG_NO_PRUNE = 256
 HELM_FLAG_GEMM_4M = 512
-HELM_FLAG_FACTOR_3M = 1024
+HELM_FLAG_FACTOR_4M = 1024
 HELM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 

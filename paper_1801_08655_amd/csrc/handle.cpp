@@ -115,7 +115,7 @@ void Handle::set_profile(int flags) {
   if (flags & HELM_FLAG_PROFILE_FWD) profile_mask |= 1u << K_FWD_GEMM;
   // the product forms of the complex64 GEMMs; graphs and tile choices made
   // with the other substitution form are dropped
-  factor3m = prec == HELM_MIXED && (flags & HELM_FLAG_FACTOR_3M);
+  factor3m = prec == HELM_MIXED && !(flags & HELM_FLAG_FACTOR_4M);
   const bool m3 = prec == HELM_MIXED && !(flags & HELM_FLAG_GEMM_4M);
   if (m3 != gemm3m) {
     if (st) HELM_HIP(hipStreamSynchronize(st));

@@ -152,7 +152,7 @@ struct Handle {
   unsigned profile_mask = 0;
   void set_profile(int flags);
   // three-product complex64 GEMMs: substitutions (unless HELM_FLAG_GEMM_4M),
-  // factorization sweep (HELM_FLAG_FACTOR_3M)
+  // factorization sweep (unless HELM_FLAG_FACTOR_4M)
   bool gemm3m = false, factor3m = false;
   bool profile() const { return profile_mask != 0; }
   KStat kstats[K_NCLASS];

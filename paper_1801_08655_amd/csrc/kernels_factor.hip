@@ -198,6 +198,55 @@ constexpr int NBMAX = 64;
 constexpr int PB = 8;   // column block of the panel LU
 template <typename T> constexpr int panel_lds_rows() { return sizeof(T) == 4 ? 192 : 64; }
 
+// D = U^-1 L^-1 of the leading nbf x nbf block of the factored panel P
+// (R rows, column-major, in LDS when LDSP), in LDS: X = L^-1 by eliminating
+// below each unit pivot, then D = U^-1 X from the last row up.  Every step
+// updates all entries it touches in parallel.
+template <typename T, int NT, bool LDSP>
+__device__ __forceinline__ void panel_inverse(const C_t<T>* P, int R, int nbf, int nb,
+                                              C_t<T>* D) {
+  using C = C_t<T>;
+  const int t = threadIdx.x;
+  // (the factors are read in place when the panel is in LDS)
+  __shared__ C LUs[LDSP ? 1 : NBMAX][LDSP ? 1 : NBMAX + 1];
+  __shared__ C X[NBMAX][NBMAX + 1];
+  __shared__ C uinv[NBMAX];
+  auto LU = [&](int r, int c) -> C { return LDSP ? P[r + c * R] : LUs[r][c]; };
+  for (int e = t; e < nbf * nbf; e += NT) {
+    int r = e % nbf, c = e / nbf;
+    if (!LDSP) LUs[r][c] = P[r + (long long)c * R];
+    X[r][c] = cmake<C>(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (t < nbf) {
+    C u = LU(t, t);
+    if (cabs2(u) == 0.0) u = cmake<C>(1.0, 0.0);
+    uinv[t] = cdiv(cmake<C>(1.0, 0.0), u);
+  }
+  __syncthreads();
+  // X[i][j] -= L[i][q] X[q][j] for i > q, j <= q
+  for (int q = 0; q + 1 < nbf; ++q) {
+    const int rows = nbf - 1 - q, cols = q + 1;
+    for (int e = t; e < rows * cols; e += NT) {
+      const int i = q + 1 + e % rows, j = e / rows;
+      cfms(X[i][j], LU(i, q), X[q][j]);
+    }
+    __syncthreads();
+  }
+  // X[i][j] -= U[i][q] / U[q][q] X[q][j] for i < q; rows scaled at the end
+  for (int q = nbf - 1; q > 0; --q) {
+    for (int e = t; e < q * nbf; e += NT) {
+      const int i = e % q, j = e / q;
+      cfms(X[i][j], cmul(LU(i, q), uinv[q]), X[q][j]);
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < nbf * nbf; e += NT) {
+    int r = e % nbf, c = e / nbf;
+    st(D + r + c * nb, cmul(X[r][c], uinv[r]));
+  }
+}
+
 template <typename T, int NT, int PR>
 __global__ void __launch_bounds__(NT)
 k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
@@ -341,47 +390,280 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     atomicMin(&status->pmin, (unsigned long long)__double_as_longlong(pv_min));
     atomicMax(&status->pmax, (unsigned long long)__double_as_longlong(pv_max));
   }
-  // D = U^-1 L^-1 of the leading nbf x nbf block, in LDS: X = L^-1 by
-  // eliminating below each unit pivot, then D = U^-1 X from the last row up.
-  // Every step updates all entries it touches in parallel.
-  // (the factors are read in place when the panel is in LDS)
-  __shared__ C LUs[LDSP ? 1 : NBMAX][LDSP ? 1 : NBMAX + 1];
-  __shared__ C X[NBMAX][NBMAX + 1];
-  __shared__ C uinv[NBMAX];
-  auto LU = [&](int r, int c) -> C { return LDSP ? P[r + c * R] : LUs[r][c]; };
-  for (int e = t; e < nbf * nbf; e += NT) {
-    int r = e % nbf, c = e / nbf;
-    if (!LDSP) LUs[r][c] = P[r + (long long)c * R];
-    X[r][c] = cmake<C>(r == c ? 1.0 : 0.0, 0.0);
+  panel_inverse<T, NT, LDSP>(P, R, nbf, nb, D);
+}
+
+// Tall panels (more rows than the LDS holds): the same blocked LU with
+// partial pivoting, with the current column block of every row held in
+// registers.  Thread t owns the rows t, t + NT, ... (RPT of them); a column
+// step (pivot search, row exchange, scaling, rank-1 update of the block)
+// works on registers and LDS only, so the panel copy in global memory is
+// passed over once per block (the trailing update) instead of once per
+// column.  Pivots, swaps and arithmetic are those of k_panel.
+template <typename T, int NT, int RPT>
+__global__ void __launch_bounds__(NT)
+k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
+           int k, int nb, void* ws0, void* ws1, void* panel_base,
+           const long long* __restrict__ panel_off, void* D_base, int* ipiv_base,
+           int* perm_base, const long long* __restrict__ perm_off, FactorStatus* status) {
+  using C = C_t<T>;
+  constexpr int NW = NT / 64;
+  const int a = blockIdx.x;
+  const FrontDev f = fronts[ids[a]];
+  const int n = f.s + f.b;
+  const int R = f.s - k;
+  if (R <= 0) return;
+  const int nbf = R < nb ? R : nb;
+  const int t = threadIdx.x;
+  const C* F = front_ptr<T>(ws0, ws1, f);
+  C* P = reinterpret_cast<C*>(panel_base) + panel_off[a];
+  C* D = reinterpret_cast<C*>(D_base) + panel_off[a];
+  int* ipiv = ipiv_base + perm_off[a];
+  int* perm = perm_base + perm_off[a];
+  if (k == 0)
+    for (int i = t; i < f.s; i += NT) perm[i] = i;
+  // the panel's columns past the first block to the global copy (each
+  // thread its own rows, a group of columns' loads before their stores);
+  // the first block goes straight to registers
+  constexpr int CG = sizeof(T) == 4 ? PB : PB / 2;   // columns per load group
+  for (int cg = PB; cg < nbf; cg += CG) {
+    C v[RPT][CG];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = t + i * NT;
+#pragma unroll
+      for (int j = 0; j < CG; ++j)
+        v[i][j] = ld_or_zero(r < R && cg + j < nbf,
+                             F + (long long)(k + (r < R ? r : 0)) + (long long)(k + cg + j) * n);
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = t + i * NT;
+#pragma unroll
+      for (int j = 0; j < CG; ++j)
+        if (r < R && cg + j < nbf) P[r + (long long)(cg + j) * R] = v[i][j];
+    }
   }
-  __syncthreads();
-  if (t < nbf) {
-    C u = LU(t, t);
-    if (cabs2(u) == 0.0) u = cmake<C>(1.0, 0.0);
-    uinv[t] = cdiv(cmake<C>(1.0, 0.0), u);
-  }
-  __syncthreads();
-  // X[i][j] -= L[i][q] X[q][j] for i > q, j <= q
-  for (int q = 0; q + 1 < nbf; ++q) {
-    const int rows = nbf - 1 - q, cols = q + 1;
-    for (int e = t; e < rows * cols; e += NT) {
-      const int i = q + 1 + e % rows, j = e / rows;
-      cfms(X[i][j], LU(i, q), X[q][j]);
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ C xch[PB];      // row c's block values, for the pivot row's owner
+  __shared__ C prow[PB];     // the pivot row's block values
+  __shared__ int bsw[PB];    // the block's pivot rows (swap c0 + j <-> bsw[j])
+  __shared__ int src[2 * PB], dst[2 * PB];   // the block's composed row moves
+  __shared__ int nmove;
+  __shared__ C mv[NBMAX][2 * PB];            // staged values of the moves
+  __shared__ C L11[PB][PB];  // the block rows' factors (unit lower part used)
+  __shared__ C U12[PB][NBMAX];
+  double pv_min = INFINITY, pv_max = 0.0;
+  C x[RPT][PB];
+  for (int c0 = 0; c0 < nbf; c0 += PB) {
+    const int c1 = (c0 + PB < nbf) ? c0 + PB : nbf;
+    const int bw = c1 - c0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = t + i * NT;
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        const bool ok = r < R && j < bw;
+        x[i][j] = c0 == 0 ? ld_or_zero(ok, F + (long long)(k + (ok ? r : 0)) + (long long)(k + j) * n)
+                          : (ok ? P[r + (long long)(c0 + j) * R] : czero<C>());
+      }
+    }
+    if (c0 == 0) __syncthreads();   // the copy is complete before any row swap
+#pragma unroll
+    for (int jc = 0; jc < PB; ++jc) {
+      if (jc >= bw) break;
+      const int c = c0 + jc;
+      // arg max |P[r][c]|, r >= c (ties: smallest row): wave maxima to LDS,
+      // then every thread reduces them (no second barrier)
+      double best = -1.0;
+      int bi = R;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = t + i * NT;
+        if (r >= c && r < R) {
+          const double v = cabs2(x[i][jc]);
+          if (v > best) { best = v; bi = r; }
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_down(best, off);
+        int oi = __shfl_down(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if ((t & 63) == 0) { red_v[t >> 6] = best; red_i[t >> 6] = bi; }
+      __syncthreads();
+      double bv = red_v[0];
+      int p = red_i[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < p)) {
+          bv = red_v[w];
+          p = red_i[w];
+        }
+      if (!(bv > 0.0) || !isfinite(bv)) {
+        if (t == 0) atomicExch(&status->flag, 1);   // zero or non-finite pivot
+        p = c;
+      } else if (t == 0) {
+        pv_min = fmin(pv_min, bv);
+        pv_max = fmax(pv_max, bv);
+      }
+      if (t == 0) {
+        ipiv[c] = p;
+        bsw[jc] = p;
+      }
+      // rows c and p trade places: the pivot row's block values go to prow
+      // (every thread reads them), row c's to xch (for row p's owner)
+      const int tc = c % NT, ic = c / NT, tp = p % NT, ip = p / NT;
+      if (t == tp)
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == ip)
+#pragma unroll
+            for (int j = 0; j < PB; ++j) prow[j] = x[i][j];
+      if (t == tc && p != c)
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == ic)
+#pragma unroll
+            for (int j = 0; j < PB; ++j) xch[j] = x[i][j];
+      __syncthreads();
+      if (p != c) {
+        if (t == tc)
+#pragma unroll
+          for (int i = 0; i < RPT; ++i)
+            if (i == ic)
+#pragma unroll
+              for (int j = 0; j < PB; ++j) x[i][j] = prow[j];
+        if (t == tp)
+#pragma unroll
+          for (int i = 0; i < RPT; ++i)
+            if (i == ip)
+#pragma unroll
+              for (int j = 0; j < PB; ++j) x[i][j] = xch[j];
+      }
+      C piv = prow[jc];
+      if (cabs2(piv) == 0.0) piv = cmake<C>(1.0, 0.0);
+      const C ipv = cdiv(cmake<C>(1.0, 0.0), piv);
+      // scale the column below the pivot, rank-1 update of the block's
+      // remaining columns
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = t + i * NT;
+        if (r > c && r < R) {
+          const C l = cmul(x[i][jc], ipv);
+          x[i][jc] = l;
+#pragma unroll
+          for (int j = 0; j < PB; ++j)
+            if (j > jc && j < bw) cfms(x[i][j], l, prow[j]);
+        }
+      }
+    }
+    // the block's row swaps, composed into moves dst <- src (at most 2 PB
+    // rows), applied at once to the columns outside the block and to the
+    // row permutation: every value is loaded before any is stored
+    if (t == 0) {
+      // dst[q]: a touched row, src[q]: the row whose content ends there
+      int m = 0;
+      for (int j = 0; j < bw; ++j) {
+        const int ra = c0 + j, rb = bsw[j];
+        int qa = -1, qb = -1;
+        for (int q = 0; q < m; ++q) {
+          if (dst[q] == ra) qa = q;
+          if (dst[q] == rb) qb = q;
+        }
+        if (qa < 0) { qa = m; dst[m] = ra; src[m] = ra; ++m; }
+        if (qb < 0) { qb = m; dst[m] = rb; src[m] = rb; ++m; }
+        const int y = src[qa];
+        src[qa] = src[qb];
+        src[qb] = y;
+      }
+      int nm = 0;
+      for (int q = 0; q < m; ++q)
+        if (src[q] != dst[q]) { dst[nm] = dst[q]; src[nm] = src[q]; ++nm; }
+      nmove = nm;
+    }
+    __syncthreads();
+    const int nm = nmove;
+    if (nm > 0) {
+      // through LDS: every moved value is read before any is written
+      for (int e = t; e < nbf * nm; e += NT) {
+        const int cc = e / nm, q = e % nm;
+        if (cc < c0 || cc >= c1) mv[cc][q] = P[src[q] + (long long)cc * R];
+      }
+      int pv = 0;
+      if (t < nm) pv = perm[k + src[t]];
+      __syncthreads();
+      for (int e = t; e < nbf * nm; e += NT) {
+        const int cc = e / nm, q = e % nm;
+        if (cc < c0 || cc >= c1) P[dst[q] + (long long)cc * R] = mv[cc][q];
+      }
+      if (t < nm) perm[k + dst[t]] = pv;
+    }
+    // the block's columns back to the global copy; the block rows' factors
+    // to LDS for the trailing solve
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = t + i * NT;
+      if (r < R)
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+          if (j < bw) P[r + (long long)(c0 + j) * R] = x[i][j];
+      if (r >= c0 && r < c1)
+#pragma unroll
+        for (int j = 0; j < PB; ++j) L11[r - c0][j] = x[i][j];
+    }
+    __syncthreads();
+    if (c1 >= nbf) break;
+    const int W = nbf - c1;
+    // block rows of the trailing columns: U12 = L11^-1 A12 (unit lower),
+    // the column's block rows loaded together first
+    for (int cc = t; cc < W; cc += NT) {
+      const long long col = (long long)(c1 + cc) * R;
+      C u[PB];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) u[i] = i < bw ? P[c0 + i + col] : czero<C>();
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        if (i >= bw) break;
+        C y = u[i];
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+          if (j < i) cfms(y, L11[i][j], u[j]);
+        u[i] = y;
+        U12[i][cc] = y;
+        P[c0 + i + col] = y;
+      }
+    }
+    __syncthreads();
+    // rank-bw update of the trailing columns below the block (own rows),
+    // a group of columns' loads before their stores
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = t + i * NT;
+      if (r < c1 || r >= R) continue;
+      for (int cg = 0; cg < W; cg += CG) {
+        C y[CG];
+#pragma unroll
+        for (int q = 0; q < CG; ++q)
+          y[q] = cg + q < W ? P[r + (long long)(c1 + cg + q) * R] : czero<C>();
+#pragma unroll
+        for (int q = 0; q < CG; ++q) {
+          if (cg + q >= W) break;
+#pragma unroll
+          for (int j = 0; j < PB; ++j)
+            if (j < bw) cfms(y[q], x[i][j], U12[j][cg + q]);
+          P[r + (long long)(c1 + cg + q) * R] = y[q];
+        }
+      }
     }
     __syncthreads();
   }
-  // X[i][j] -= U[i][q] / U[q][q] X[q][j] for i < q; rows scaled at the end
-  for (int q = nbf - 1; q > 0; --q) {
-    for (int e = t; e < q * nbf; e += NT) {
-      const int i = e % q, j = e / q;
-      cfms(X[i][j], cmul(LU(i, q), uinv[q]), X[q][j]);
-    }
-    __syncthreads();
+  if (t == 0 && pv_max > 0.0) {
+    atomicMin(&status->pmin, (unsigned long long)__double_as_longlong(pv_min));
+    atomicMax(&status->pmax, (unsigned long long)__double_as_longlong(pv_max));
   }
-  for (int e = t; e < nbf * nbf; e += NT) {
-    int r = e % nbf, c = e / nbf;
-    st(D + r + c * nb, cmul(X[r][c], uinv[r]));
-  }
+  panel_inverse<T, NT, false>(P, R, nbf, nb, D);
 }
 
 // --------------------------------------------------------------------------
@@ -684,10 +966,26 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_
   hipLaunchKernelGGL((k_panel<T, NT, PR>), dim3(n_active), dim3(NT), 0, st,        \
                      fronts, ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm, \
                      perm_off, status)
+#define HELM_PANEL_RB(NT, RPT)                                                      \
+  hipLaunchKernelGGL((k_panel_rb<T, NT, RPT>), dim3(n_active), dim3(NT), 0, st,    \
+                     fronts, ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm, \
+                     perm_off, status)
+  // taller than the LDS holds: the column block in registers, 4 rows per
+  // thread at most (complex128 at 512 threads: at 1024 a lane's register
+  // share of 128 would spill), else the global copy alone
+  constexpr bool C64 = sizeof(T) == 4;
   if (max_rows <= 64) HELM_PANEL(64, 64);
   else if (max_rows <= panel_lds_rows<T>()) HELM_PANEL(256, panel_lds_rows<T>());
-  else if (max_rows <= 1024) HELM_PANEL(256, 0);
-  else HELM_PANEL(1024, 0);
+  else if (max_rows <= 1024) HELM_PANEL_RB(256, 4);
+  else if constexpr (C64) {
+    if (max_rows <= 2048) HELM_PANEL_RB(1024, 2);
+    else if (max_rows <= 4096) HELM_PANEL_RB(1024, 4);
+    else HELM_PANEL(1024, 0);
+  } else {
+    if (max_rows <= 2048) HELM_PANEL_RB(512, 4);
+    else HELM_PANEL(1024, 0);
+  }
+#undef HELM_PANEL_RB
 #undef HELM_PANEL
 }
 template <typename T>

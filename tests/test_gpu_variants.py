@@ -141,14 +141,14 @@ def test_product_forms_of_the_local_solve(k):
     print("k", k, "max rel err 3M", e["3M"].max(), "4M", e["4M"].max())
     assert e["3M"].max() <= 2e-4 and e["4M"].max() <= 2e-4
     d64 = _solver(wl, "fp64")
-    d64b = _solver(wl, "fp64", flags=pt._lib.HELM_FLAG_GEMM_4M | pt._lib.HELM_FLAG_FACTOR_3M)
+    d64b = _solver(wl, "fp64", flags=pt._lib.HELM_FLAG_GEMM_4M | pt._lib.HELM_FLAG_FACTOR_4M)
     a = d64.layer_solve(l, rt)
     b = d64b.layer_solve(l, rt)
     assert torch.equal(a, b)
     assert relative_error(a.cpu().numpy().reshape(k, -1).T, ref).max() <= 1e-11
 
 
-@pytest.mark.parametrize("flags", ["GEMM_4M", "FACTOR_3M", "GEMM_4M|FACTOR_3M"])
+@pytest.mark.parametrize("flags", ["GEMM_4M", "FACTOR_4M", "GEMM_4M|FACTOR_4M"])
 def test_product_forms_of_the_mixed_solve(flags):
     """The whole mixed-precision method with the other product forms of the
     complex64 GEMMs (the default form is covered by every other mixed test)
