@@ -114,7 +114,7 @@ void helm_default_options(helm_options* o) {
   o->leaf_size = 64;
   o->flags = 0;
   o->gmres_restart = 0;
-  o->inner_tol_final = 1e-2;
+  o->inner_tol_final = 1e-1;
 }
 
 int helm_plan(const helm_grid* g, int pml_width, int n_layers, const helm_options* opt,

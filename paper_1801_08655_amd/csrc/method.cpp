@@ -888,18 +888,18 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
 // |u|.  Guards:
 //  - q is the larger of the last two measured ratios (from the third step
 //    on);
-//  - a step whose GMRES reached a larger relative residual than the
-//    previous step's is taken to contract less in proportion (q scaled by
-//    tol / tol_prev, tol the residual GMRES reached): a step limited by its
-//    GMRES residual contracts in proportion to it, one limited by the
-//    complex64 rounding does not change;
+//  - a step contracts by no less than kResidualGain times the relative
+//    residual its GMRES reached (tol): the correction's error is the inverse
+//    of the preconditioned operator applied to that residual, and the
+//    polarized preconditioner leaves an operator close to the identity;
+//    a step limited by the complex64 rounding shows in the measured ratios;
 //  - an estimate with q > 1/2 (slow or erratic contraction) is not trusted
 //    (reported as 1, unknown).
 // Unknown (1) after the first step.
 double refinement_error(int step, RefineTrack& tr, double dcur, double unorm, double tol) {
-  const double dprev = tr.dprev, qprev = tr.qprev, tprev = tr.tprev;
+  constexpr double kResidualGain = 4.0;
+  const double dprev = tr.dprev, qprev = tr.qprev;
   tr.dprev = dcur;
-  tr.tprev = tol;
   double est = 1.0;
   if (unorm == 0) {
     est = 0.0;
@@ -907,7 +907,7 @@ double refinement_error(int step, RefineTrack& tr, double dcur, double unorm, do
     const double qk = dcur / dprev;
     tr.qprev = qk;
     double q = step >= 2 ? std::max(qk, qprev) : qk;
-    if (tprev > 0 && tol > tprev) q *= tol / tprev;
+    q = std::max(q, kResidualGain * tol);
     if (q <= 0.5) est = dcur / unorm * q / (1.0 - q);
   }
   tr.est = est;

@@ -90,7 +90,6 @@ struct Method {
 struct RefineTrack {
   double dprev = 0;   // |d| of the previous step
   double qprev = 0;   // contraction ratio measured at the previous step
-  double tprev = 0;   // GMRES tolerance of the previous step
   double est = 1;     // estimated error after the last step (1: unknown)
 };
 // Estimated relative error |u - H^-1 f| / |u| after a step whose correction
