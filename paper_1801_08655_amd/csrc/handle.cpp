@@ -90,6 +90,7 @@ Handle::~Handle() {
   for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto e : ev_free) (void)hipEventDestroy(e);
   sets.clear();
+  if (cap_st) (void)hipStreamDestroy(cap_st);
   if (own_stream && st) (void)hipStreamDestroy(st);
 }
 
@@ -585,6 +586,7 @@ const LayerSet& Handle::layer_set(const std::vector<int>& layers) {
 // Interface planes of layer l (local z of the extended layer): the top pair
 // (s - 1, s) and the bottom pair (e, e + 1), where they exist.
 static bool touches(const FrontHost& F, const LayerPlan& P, int mask, int l, int L) {
+  if (mask & kPruneAll) return true;
   int pl[4], n = 0;
   if ((mask & kPruneTop) && l >= 1) { pl[n++] = P.s - 1 - P.lo; pl[n++] = P.s - P.lo; }
   if ((mask & kPruneBottom) && l <= L - 2) { pl[n++] = P.e - P.lo; pl[n++] = P.e + 1 - P.lo; }
@@ -773,13 +775,31 @@ void Handle::solve_layers(const LayerSet& set, int k) {
     GraphKey key{&set, k};
     auto it = graphs.find(key);
     if (it == graphs.end()) {
-      hipGraph_t g;
+      // Captured on a stream of its own that does not synchronize with the
+      // legacy default stream: while a stream that does is capturing, work
+      // that another thread puts on the legacy stream (an allocation by the
+      // caller, say) is an error.  A capture records and runs nothing, so
+      // the stream it is recorded on needs no ordering with st.
+      if (!cap_st) HELM_HIP(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+      struct Restore {
+        hipStream_t& s;
+        hipStream_t keep;
+        ~Restore() { s = keep; }
+      } restore{st, st};
+      st = cap_st;
+      hipGraph_t g = nullptr;
       HELM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
+      try {
+        if (prec == HELM_FP64) solve_layers_t<double>(set, k); else solve_layers_t<float>(set, k);
+      } catch (...) {
+        if (hipStreamEndCapture(st, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+        throw;
+      }
       HELM_HIP(hipStreamEndCapture(st, &g));
       hipGraphExec_t ex;
-      HELM_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-      HELM_HIP(hipGraphDestroy(g));
+      const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HELM_HIP(ie);
       it = graphs.emplace(key, ex).first;
     }
     HELM_HIP(hipGraphLaunch(it->second, st));

@@ -71,6 +71,7 @@ struct PendingEvent {
 };
 // Interface-plane masks of a pruned local solve.
 constexpr int kPruneTop = 1, kPruneBottom = 2;
+constexpr int kPruneAll = 4;   // sources anywhere in the layer (no forward pruning)
 
 struct LayerSet {
   std::vector<int> layers;
@@ -98,6 +99,7 @@ struct Handle {
   size_t elem = 8;                // bytes of one complex element of the factors
   hipStream_t st = nullptr;
   bool own_stream = false;
+  hipStream_t cap_st = nullptr;   // graph captures (non-blocking, see solve_layers)
   int device = 0;
   int nb = kPivotBlock;           // pivot block of the Gauss-Jordan sweep
 

@@ -123,17 +123,18 @@ void Method::apply_P(const double2* vd, const double2* vu, double2* od, double2*
   double2* kp = keep.as<double2>();
   // z_down_0 = -v_down_0
   readout(0, 1, 0.0, terms(pair(vd, 0), -1, -1), pair(od, 0));
+  constexpr int T = kPruneTop, B = kPruneBottom;
   for (int l = 1; l <= L - 2; ++l) {
     zero_X(l);
     jump(l, pair(od, l - 1), nullptr, 0);
-    solve_single(l);
+    solve_planes(l, T, T | B);
     readout(l, 1, 1.0, terms(pair(vd, l), -1, -1), pair(od, l));
     readout(l, 0, 1.0, terms(), pair(kp, l - 1));
   }
   // last layer: only the reflection term is needed
   zero_X(L - 1);
   jump(L - 1, pair(od, L - 2), nullptr, 0);
-  solve_single(L - 1);
+  solve_planes(L - 1, T, T);
   readout(L - 1, 0, 1.0, terms(), pair(kp, L - 2));
   // upward: z_up_{L-2} = keep_{L-1} - (0, z_down_{L-2,b}) - v_up_{L-2}
   readout(L - 1, 0, 0.0,
@@ -143,7 +144,7 @@ void Method::apply_P(const double2* vd, const double2* vu, double2* od, double2*
   for (int j = L - 3; j >= 0; --j) {
     zero_X(j + 1);
     jump(j + 1, pair(ou, j + 1), pair(od, j + 1), 1);
-    solve_single(j + 1);
+    solve_planes(j + 1, B, T);
     readout(j + 1, 0, 1.0,
             terms(pair(kp, j), 1, 1, pair(od, j), 0, -1, vu ? pair(vu, j) : nullptr, -1, -1),
             pair(ou, j));
@@ -245,6 +246,7 @@ void Method::polarized_rhs(const double2* f, double2* fd, double2* fu) {
 // batched solve over all layers.
 void Method::precondition_source(const double2* f, double2* od, double2* ou) {
   const int L = H.G.L;
+  constexpr int T = kPruneTop, B = kPruneBottom;
   double2* kp = keep.as<double2>();
   for (int l = 0; l <= L - 1; ++l) {
     zero_X(l);
@@ -253,7 +255,7 @@ void Method::precondition_source(const double2* f, double2* od, double2* ou) {
     else
       kern::launch_scatter_source<float>(H.layers_h[l], f, H.G.nx, H.G.ny, N, k, H.st);
     if (l >= 1) jump(l, pair(od, l - 1), nullptr, 0);
-    solve_single(l);
+    solve_planes(l, kPruneAll, T | B);   // volume source: every front forward
     if (l <= L - 2) readout(l, 1, 1.0, terms(), pair(od, l));
     if (l >= 1) readout(l, 0, 1.0, terms(), pair(kp, l - 1));   // keep_{l-1} - f_up_{l-1}
   }
@@ -261,7 +263,7 @@ void Method::precondition_source(const double2* f, double2* od, double2* ou) {
   for (int j = L - 3; j >= 0; --j) {
     zero_X(j + 1);
     jump(j + 1, pair(ou, j + 1), pair(od, j + 1), 1);
-    solve_single(j + 1);
+    solve_planes(j + 1, B, T);
     readout(j + 1, 0, 1.0, terms(pair(kp, j), 1, 1, pair(od, j), 0, -1), pair(ou, j));
   }
 }
