@@ -207,3 +207,28 @@ def test_entry_points_reject_null_handles():
     assert L.helm_tile_choices(None, None, 0, None) == pt.HELM_EINVAL
     assert L.helm_set_solve_options(None, None) == pt.HELM_EINVAL
     assert L.helm_free(None) == pt.HELM_OK
+
+
+def test_binding_constants_match_the_header():
+    """Every HELM_* integer macro of the headers (flags, status codes,
+    precisions, limits) has the same value in the binding."""
+    inc = os.path.join(ROOT, "include")
+    found = 0
+    for f in sorted(os.listdir(inc)):
+        if not f.endswith(".h"):
+            continue
+        with open(os.path.join(inc, f)) as fh:
+            text = fh.read()
+        for name, val in re.findall(r"#define\s+(HELM_[A-Z0-9_]+)\s+\(?(-?\d+)", text):
+            if hasattr(_lib, name):
+                found += 1
+                assert getattr(_lib, name) == int(val) or name == "HELM_NOALLOC_SCRATCH_BYTES", name
+    assert found >= 15
+    assert _lib.HELM_NOALLOC_SCRATCH_BYTES == 128 << 20
+
+
+def test_default_refinement_options():
+    """Defaults of the refinement stop rule (documented in helm.h)."""
+    o = pt.options()
+    assert o.inner_tol == pytest.approx(1e-3) and o.inner_tol_refine == pytest.approx(1e-4)
+    assert o.inner_tol_final == pytest.approx(1e-1) and o.gmres_restart == 0
