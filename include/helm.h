@@ -30,6 +30,11 @@
  * All entry points return a status code (HELM_OK on success) and never throw.
  * helm_last_error() gives a human-readable description of the last failure
  * on the calling thread.
+ * The solve entry points capture their launch sequences into HIP graphs on
+ * the calling thread (on a private stream) the first time a layer set meets
+ * a batch width: another thread that synchronizes the whole device while
+ * such a capture lasts gets an error from HIP (HELM_FLAG_NO_GRAPHS avoids
+ * captures; the request server's lanes never capture).
  */
 #ifndef HELM_H
 #define HELM_H

@@ -9,7 +9,9 @@
  *
  *  - Every model has a lane: a fixed number of column slots, its own HIP
  *    stream and a host thread.  Lanes of different models run concurrently
- *    on the device.
+ *    on the device.  A lane launches its kernels one by one (no HIP graph
+ *    capture on the lane's thread), so the caller may allocate, compute and
+ *    synchronize the device from its own threads while requests run.
  *  - A request is a set of point sources for one model.  Its columns wait
  *    in the model's FIFO queue and enter free slots of the lane between
  *    refinement steps, while the columns already in the lane continue;

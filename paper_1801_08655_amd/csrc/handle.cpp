@@ -770,7 +770,7 @@ void Handle::solve_layers(const LayerSet& set, int k) {
   // (layer set, width) into a HIP graph and replayed; the sequence holds no
   // memset or host work.  Event timing needs the launches one by one.
   (void)tile_plan(set, k);   // measured choices, if asked for, are taken here
-  const bool use_graph = !profile() && !(opt.flags & HELM_FLAG_NO_GRAPHS);
+  const bool use_graph = capture && !profile() && !(opt.flags & HELM_FLAG_NO_GRAPHS);
   if (use_graph) {
     GraphKey key{&set, k};
     auto it = graphs.find(key);

@@ -100,6 +100,11 @@ struct Handle {
   hipStream_t st = nullptr;
   bool own_stream = false;
   hipStream_t cap_st = nullptr;   // graph captures (non-blocking, see solve_layers)
+  // Launch sequences are captured into graphs unless a server lane drives
+  // the handle: a lane's capture on its own thread would make the caller's
+  // device-wide synchronizations fail while it lasts (measured: the lanes
+  // run at the same rate without graphs).
+  bool capture = true;
   int device = 0;
   int nb = kPivotBlock;           // pivot block of the Gauss-Jordan sweep
 

@@ -246,6 +246,7 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   for (DevMem* d : {&ln->F, &ln->U, &ln->R}) HELM_HIP(hipMemsetAsync(d->p, 0, vol, H.st));
   HELM_HIP(hipStreamSynchronize(H.st));
   h->method.reset();   // the lane's Methods own the solve workspace from here
+  H.capture = false;   // launched one by one while the lane's thread drives it
   H.ensure_workspace(K);
   ln->methods.emplace(K, std::make_unique<Method>(H, K));
   ln->slots.assign(K, Slot{});
@@ -322,6 +323,7 @@ void Server::remove_model(int model) {
   (void)hipSetDevice(H.device);
   HELM_HIP(hipStreamSynchronize(H.st));
   ln->methods.clear();
+  H.capture = true;
   for (DevMem* d : {&ln->F, &ln->U, &ln->R, &ln->D, &ln->nodes_d, &ln->amps_d}) d->release();
   std::lock_guard<std::mutex> lk(mu);
   reserved -= ln->bytes;

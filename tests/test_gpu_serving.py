@@ -173,3 +173,35 @@ def test_server_admission_and_errors(layered):
     assert inf["status"] == 0 and u.shape[0] == 0
     srv.close()
     s.close()
+
+
+def test_caller_allocations_during_lane_graph_captures(layered):
+    """The caller keeps allocating and computing with torch on its default
+    stream, and synchronizes the whole device, while the server's lane runs
+    requests of new widths (every request size below is a new narrowest
+    width, 1 to 8 columns): the lane launches its kernels without graph
+    captures, so none of this is an error, and every request still matches
+    the oracle."""
+    from paper_1801_08655_amd.serving import Server
+    wl, refs = layered
+    s = _solver(wl, "mixed", err_target=1e-6)
+    srv = Server(slots=8)
+    mid = srv.add_model(s)
+    nodes = REQS["c"] + REQS["a"]
+    reqs = []
+    for n in (1, 2, 3, 5, 8):
+        reqs.append((n, srv.submit(mid, nodes[:n])))
+        for _ in range(20):   # default-stream work while the lane runs
+            x = torch.empty((1 << 18,), dtype=torch.complex128, device="cuda")
+            x.fill_(1.0)
+            y = (x * 2).sum()
+        torch.cuda.synchronize()
+    ref_all = np.concatenate([refs["c"], refs["a"]], axis=1)
+    for n, r in reqs:
+        u, _ = r.wait()
+        err = relative_error(_cols(u), ref_all[:, :n])
+        print(n, "columns: max err", err.max())
+        assert err.max() <= 1e-6
+    assert float(y.real) == 2.0 * (1 << 18)
+    srv.close()
+    s.close()
