@@ -208,7 +208,7 @@ def same_input_gpu(pt, torch, U_oracle):
     R = len(wl.sources)
     for prec in ("mixed", "fp64"):
         kw = dict(gmres_tol=1e-10) if prec == "fp64" else dict(
-            ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4, err_target=1e-6,
+            ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=2e-4, err_target=1e-6,
             ir_max_steps=4)
         # one untimed run first: code objects loaded, device warm
         s = pt.Solver(wl.m(), wl.h, wl.omega, wl.pml, wl.n_layers, precision=prec,
@@ -251,7 +251,7 @@ def serve_bench(args, torch, pt):
         t0 = time.perf_counter()
         s = pt.Solver(w.m(), w.h, w.omega, w.pml, w.n_layers, precision="mixed",
                       pml_local=w.pml_local, pml_C=w.pml_C, ir_tol=1e-10, inner_tol=1e-3,
-                      inner_tol_refine=1e-4, err_target=1e-6, ir_max_steps=4)
+                      inner_tol_refine=2e-4, err_target=1e-6, ir_max_steps=4)
         torch.cuda.synchronize()
         factor_s.append(time.perf_counter() - t0)
         srv.add_model(s)
@@ -332,7 +332,7 @@ def rhs_scaling_bench(args, torch, pt):
     m = wl.m()
     log(f"[rhs-scaling] factorize {wl.name}")
     s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
-                  ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4, err_target=1e-6,
+                  ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=2e-4, err_target=1e-6,
                   ir_max_steps=4, pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64,
                   flags=0 if args.no_autotune else pt._lib.HELM_FLAG_AUTOTUNE)
     points = []
@@ -369,7 +369,7 @@ def batch_bench(args, torch, pt):
     log("[batch] solving")
     res, summ = solve_batch(probs, slots=args.slots, max_resident=args.batch_resident,
                             host_output=True, precision="mixed",
-                            pml_local=4, ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=1e-4,
+                            pml_local=4, ir_tol=1e-10, inner_tol=1e-3, inner_tol_refine=2e-4,
                             err_target=1e-6, ir_max_steps=4,
                             flags=pt._lib.HELM_FLAG_AUTOTUNE)
     infos = [r[1] for r in res]
@@ -439,7 +439,7 @@ def main():
     step_flags = tune
     prof_flags = (pt._lib.HELM_FLAG_PROFILE_FWD if args.profile else 0) | tune
     common = dict(pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64, flags=flags)
-    mixed_kw = dict(ir_tol=1e-10, inner_tol=args.inner_tol, inner_tol_refine=1e-4,
+    mixed_kw = dict(ir_tol=1e-10, inner_tol=args.inner_tol, inner_tol_refine=2e-4,
                     err_target=1e-6, ir_max_steps=4)
     extra = {}
 
