@@ -393,6 +393,154 @@ k_panel(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   panel_inverse<T, NT, LDSP>(P, R, nbf, nb, D);
 }
 
+// Panels of at most 64 NW rows, complex64: NW waves per front, thread r
+// holding row r of the panel in registers.  Gauss-Jordan elimination with
+// partial pivoting turns the panel into the inverse of its pivoted diagonal
+// block in place: at column c the chosen row is scaled by the pivot's
+// inverse and removed from every other row, and column c's slot, no longer
+// needed, takes column c of the inverse (the eliminated unit column carried
+// along).  Rows never leave their threads; each thread tracks the index its
+// row would have if rows were exchanged as in the LU, which gives the pivot
+// choice of the LU with partial pivoting (largest |entry| among the rows not
+// yet chosen, ties to the smallest index), the same exchange record ipiv and
+// the same permutation.  One wave broadcasts the pivot row with lane reads;
+// several exchange the wave maxima and the pivot row through LDS (two
+// barriers per column).
+template <typename T, int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_panel_regs(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
+             int k, int nb, void* ws0, void* ws1, void* D_base, int* ipiv_base,
+             int* perm_base, const long long* __restrict__ perm_off,
+             const long long* __restrict__ panel_off, FactorStatus* status) {
+  using C = C_t<T>;
+  const int a = blockIdx.x;
+  const FrontDev f = fronts[ids[a]];
+  const int n = f.s + f.b;
+  const int R = f.s - k;
+  if (R <= 0) return;
+  const int nbf = R < nb ? R : nb;
+  const int t = threadIdx.x, lane = t & 63;
+  const bool row = t < R;
+  const C* F = front_ptr<T>(ws0, ws1, f);
+  C* D = reinterpret_cast<C*>(D_base) + panel_off[a];
+  int* ipiv = ipiv_base + perm_off[a];
+  int* perm = perm_base + perm_off[a];
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ C prow[NW > 1 ? NBMAX : 1];
+  C x[NBMAX];
+#pragma unroll
+  for (int j = 0; j < NBMAX; ++j)
+    x[j] = ld_or_zero(row && j < nbf,
+                      F + (long long)(k + (row ? t : 0)) + (long long)(k + (j < nbf ? j : 0)) * n);
+  // the permutation entry of this thread's row, read before any is written
+  const int pold = k == 0 ? t : (row ? ld(perm + k + t) : 0);
+  int pos = t;           // the row's index were rows exchanged as in the LU
+  bool chosen = false;   // the row is the pivot row of an earlier column
+  double pv_min = INFINITY, pv_max = 0.0;
+  for (int c = 0; c < nbf; ++c) {
+    C xc = x[0];
+#pragma unroll
+    for (int j = 1; j < NBMAX; ++j)
+      if (j == c) xc = x[j];
+    // arg max over the rows not yet chosen, the key (|x|^2, smallest
+    // index): within the wave, then over the waves' maxima
+    const bool cand = row && !chosen;
+    double v = cand ? cabs2(xc) : -1.0;
+    int bi = cand ? pos : R;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
+    }
+    double bv;
+    int P;
+    if (NW == 1) {
+      bv = __shfl(v, 0, 64);
+      P = __builtin_amdgcn_readfirstlane(bi);
+    } else {
+      if (lane == 0) { red_v[t >> 6] = v; red_i[t >> 6] = bi; }
+      __syncthreads();
+      bv = red_v[0];
+      P = red_i[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < P)) {
+          bv = red_v[w];
+          P = red_i[w];
+        }
+    }
+    // a zero or non-finite maximum: flagged, the row at index c taken
+    const bool bad = !(bv > 0.0) || !isfinite(bv);
+    if (bad) {
+      P = c;
+      if (t == 0) atomicExch(&status->flag, 1);
+    } else {
+      pv_min = fmin(pv_min, bv);
+      pv_max = fmax(pv_max, bv);
+    }
+    if (t == 0) ipiv[c] = P;
+    const bool win = cand && pos == P;
+    C w_c;   // the pivot row's entries come from its lane (one wave) or LDS
+    int pl = 0;
+    if (NW == 1) {
+      pl = __builtin_amdgcn_readfirstlane(__ffsll((long long)__ballot(win)) - 1);
+      w_c.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc.x), pl));
+      w_c.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc.y), pl));
+    } else {
+      if (win)
+#pragma unroll
+        for (int j = 0; j < NBMAX; ++j)
+          if (j < nbf) prow[j] = x[j];
+      __syncthreads();
+      w_c = xc;
+#pragma unroll
+      for (int j = 0; j < NBMAX; ++j)
+        if (j == c) w_c = prow[j];
+    }
+    // exchange of indices c and P: the row at c moves to P, the pivot row to c
+    if (pos == c) pos = P;
+    if (win) {
+      pos = c;
+      chosen = true;
+    }
+    C piv = w_c;
+    if (cabs2(piv) == 0.0) piv = cmake<C>(1.0, 0.0);
+    const C ipv = cdiv(cmake<C>(1.0, 0.0), piv);
+    // pivot row w (column c read as 1) scaled by ipv; every other row loses
+    // g w' with g its column-c entry (that slot read as 0)
+    const C g = win ? czero<C>() : xc;
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j) {
+      if (j < nbf) {
+        C w;
+        if (NW == 1) {
+          w.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[j].x), pl));
+          w.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[j].y), pl));
+        } else {
+          w = prow[j];
+        }
+        if (j == c) w = cmake<C>(1.0, 0.0);
+        const C ws = cmul(w, ipv);
+        C y = win ? ws : (j == c ? czero<C>() : x[j]);
+        cfms(y, g, ws);
+        x[j] = y;
+      }
+    }
+  }
+  if (t == 0 && pv_max > 0.0) {
+    atomicMin(&status->pmin, (unsigned long long)__double_as_longlong(pv_min));
+    atomicMax(&status->pmax, (unsigned long long)__double_as_longlong(pv_max));
+  }
+  if (row) perm[k + pos] = pold;
+  if (row && pos < nbf) {
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j)
+      if (j < nbf) st(D + pos + (long long)j * nb, x[j]);
+  }
+}
+
 // Tall panels (more rows than the LDS holds): the same blocked LU with
 // partial pivoting, with the current column block of every row held in
 // registers.  Thread t owns the rows t, t + NT, ... (RPT of them); a column
@@ -636,24 +784,33 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       }
     }
     __syncthreads();
-    // rank-bw update of the trailing columns below the block (own rows),
-    // a group of columns' loads before their stores
+    // rank-bw update of the trailing columns below the block (own rows):
+    // a group of TG columns of all the thread's rows loaded before any of
+    // their stores, so that RPT x TG loads are in flight per thread
+    constexpr int TG = CG < (NT >= 1024 ? 16 : 32) / RPT ? CG : (NT >= 1024 ? 16 : 32) / RPT;
+    for (int cg = 0; cg < W; cg += TG) {
+      C y[RPT][TG];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = t + i * NT;
-      if (r < c1 || r >= R) continue;
-      for (int cg = 0; cg < W; cg += CG) {
-        C y[CG];
+      for (int i = 0; i < RPT; ++i) {
+        const int r = t + i * NT;
+        const bool ok = r >= c1 && r < R;
 #pragma unroll
-        for (int q = 0; q < CG; ++q)
-          y[q] = cg + q < W ? P[r + (long long)(c1 + cg + q) * R] : czero<C>();
+        for (int q = 0; q < TG; ++q) {
+          const bool in = ok && cg + q < W;
+          y[i][q] = ld_or_zero(in, P + (in ? r + (long long)(c1 + cg + q) * R : 0));
+        }
+      }
 #pragma unroll
-        for (int q = 0; q < CG; ++q) {
+      for (int i = 0; i < RPT; ++i) {
+        const int r = t + i * NT;
+        if (r < c1 || r >= R) continue;
+#pragma unroll
+        for (int q = 0; q < TG; ++q) {
           if (cg + q >= W) break;
 #pragma unroll
           for (int j = 0; j < PB; ++j)
-            if (j < bw) cfms(y[q], x[i][j], U12[j][cg + q]);
-          P[r + (long long)(c1 + cg + q) * R] = y[q];
+            if (j < bw) cfms(y[i][q], x[i][j], U12[j][cg + q]);
+          P[r + (long long)(c1 + cg + q) * R] = y[i][q];
         }
       }
     }
@@ -736,13 +893,21 @@ k_swap_JO(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     const bool ok = r < no && gc < n;
     w[i] = ld_or_zero(ok, F + (ok ? (long long)srcO[r] + (long long)gc * n : 0));
   }
-  for (int e = t; e < nbf * GT; e += 256) {
-    const int r = e % nbf, c = e / nbf, gc = c0 + c;
-    V[r][c] = ld_or_zero(gc < n, F + (gc < n ? (long long)srcJ[r] + (long long)gc * n : 0));
+  // the rows J of the tile and D: every load issued before the first store
+  C vj[WPT], dw[WPT];
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    const int e = t + 256 * i, r = e % NBMAX, c = e / NBMAX, gc = c0 + c;
+    const bool ok = r < nbf && gc < n;
+    vj[i] = ld_or_zero(ok, F + (ok ? (long long)srcJ[r] + (long long)gc * n : 0));
+    const bool dok = r < nbf && c < nbf;
+    dw[i] = ld_or_zero(dok, D + (dok ? r + c * nb : 0));
   }
-  for (int e = t; e < nbf * nbf; e += 256) {
-    const int r = e % nbf, q = e / nbf;
-    DsT[q][r] = ld(D + r + q * nb);
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    const int e = t + 256 * i, r = e % NBMAX, c = e / NBMAX;
+    V[r][c] = vj[i];
+    DsT[c][r] = dw[i];
   }
   __syncthreads();
 #pragma unroll
@@ -864,13 +1029,23 @@ k_update_OJ(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   __shared__ C V[GT][NBMAX + 1];
   __shared__ C Ds[NBMAX][NBMAX + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < GT * nbf; e += 256) {
-    int r = e % GT, c = e / GT;
-    V[r][c] = (r0 + r < n) ? F[(long long)(r0 + r) + (long long)(k + c) * n] : czero<C>();
+  // every load of the tile and of D issued before the first LDS store
+  constexpr int WPT = NBMAX * GT / 256;
+  C w[WPT], dw[WPT];
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    const int e = t + 256 * i, r = e % GT, c = e / GT;
+    const bool ok = r0 + r < n && c < nbf;
+    w[i] = ld_or_zero(ok, F + (ok ? (long long)(r0 + r) + (long long)(k + c) * n : 0));
+    const int dr = e % NBMAX, dc = e / NBMAX;
+    const bool dok = dr < nbf && dc < nbf;
+    dw[i] = ld_or_zero(dok, D + (dok ? dr + dc * nb : 0));
   }
-  for (int e = t; e < nbf * nbf; e += 256) {
-    int r = e % nbf, c = e / nbf;
-    Ds[r][c] = D[r + c * nb];
+#pragma unroll
+  for (int i = 0; i < WPT; ++i) {
+    const int e = t + 256 * i;
+    V[e % GT][e / GT] = w[i];
+    Ds[e % NBMAX][e / NBMAX] = dw[i];
   }
   __syncthreads();
   // thread (rg, cg) owns rows rg + 16 i and columns cg + 16 j (i, j < 4)
@@ -970,10 +1145,24 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_
   hipLaunchKernelGGL((k_panel_rb<T, NT, RPT>), dim3(n_active), dim3(NT), 0, st,    \
                      fronts, ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm, \
                      perm_off, status)
+  // complex64 up to 512 rows: a row per thread, the panel in registers;
   // taller than the LDS holds: the column block in registers, 4 rows per
   // thread at most (complex128 at 512 threads: at 1024 a lane's register
   // share of 128 would spill), else the global copy alone
   constexpr bool C64 = sizeof(T) == 4;
+#define HELM_PANEL_REGS(NW)                                                         \
+  hipLaunchKernelGGL((k_panel_regs<T, NW>), dim3(n_active), dim3(64 * NW), 0, st,  \
+                     fronts, ids, k, nb, ws0, ws1, D, ipiv, perm, perm_off, panel_off, status)
+  if constexpr (C64) {
+    if (max_rows <= 512) {
+      if (max_rows <= 64) HELM_PANEL_REGS(1);
+      else if (max_rows <= 128) HELM_PANEL_REGS(2);
+      else if (max_rows <= 192) HELM_PANEL_REGS(3);
+      else if (max_rows <= 256) HELM_PANEL_REGS(4);
+      else HELM_PANEL_REGS(8);
+      return;
+    }
+  }
   if (max_rows <= 64) HELM_PANEL(64, 64);
   else if (max_rows <= panel_lds_rows<T>()) HELM_PANEL(256, panel_lds_rows<T>());
   else if (max_rows <= 1024) HELM_PANEL_RB(256, 4);
@@ -985,6 +1174,7 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_
     if (max_rows <= 2048) HELM_PANEL_RB(512, 4);
     else HELM_PANEL(1024, 0);
   }
+#undef HELM_PANEL_REGS
 #undef HELM_PANEL_RB
 #undef HELM_PANEL
 }
