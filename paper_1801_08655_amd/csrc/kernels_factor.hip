@@ -212,9 +212,24 @@ __device__ __forceinline__ void panel_inverse(const C_t<T>* P, int R, int nbf, i
   __shared__ C X[NBMAX][NBMAX + 1];
   __shared__ C uinv[NBMAX];
   auto LU = [&](int r, int c) -> C { return LDSP ? P[r + c * R] : LUs[r][c]; };
+  if (!LDSP) {
+    // the factors from the global panel, every load before the first store
+    constexpr int PER = (NBMAX * NBMAX + NT - 1) / NT;
+    C w[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = t + NT * i, r = e % NBMAX, c = e / NBMAX;
+      const bool ok = r < nbf && c < nbf;
+      w[i] = ld_or_zero(ok, P + (ok ? r + (long long)c * R : 0));
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = t + NT * i, r = e % NBMAX, c = e / NBMAX;
+      if (r < nbf && c < nbf) LUs[r][c] = w[i];
+    }
+  }
   for (int e = t; e < nbf * nbf; e += NT) {
     int r = e % nbf, c = e / nbf;
-    if (!LDSP) LUs[r][c] = P[r + (long long)c * R];
     X[r][c] = cmake<C>(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
@@ -548,7 +563,7 @@ k_panel_regs(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 // works on registers and LDS only, so the panel copy in global memory is
 // passed over once per block (the trailing update) instead of once per
 // column.  Pivots, swaps and arithmetic are those of k_panel.
-template <typename T, int NT, int RPT>
+template <typename T, int NT, int RPT, int BW>
 __global__ void __launch_bounds__(NT)
 k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
            int k, int nb, void* ws0, void* ws1, void* panel_base,
@@ -573,8 +588,8 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   // the panel's columns past the first block to the global copy (each
   // thread its own rows, a group of columns' loads before their stores);
   // the first block goes straight to registers
-  constexpr int CG = sizeof(T) == 4 ? PB : PB / 2;   // columns per load group
-  for (int cg = PB; cg < nbf; cg += CG) {
+  constexpr int CG = sizeof(T) == 4 ? BW : BW / 2;   // columns per load group
+  for (int cg = BW; cg < nbf; cg += CG) {
     C v[RPT][CG];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -594,24 +609,24 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
   }
   __shared__ double red_v[NW];
   __shared__ int red_i[NW];
-  __shared__ C xch[PB];      // row c's block values, for the pivot row's owner
-  __shared__ C prow[PB];     // the pivot row's block values
-  __shared__ int bsw[PB];    // the block's pivot rows (swap c0 + j <-> bsw[j])
-  __shared__ int src[2 * PB], dst[2 * PB];   // the block's composed row moves
+  __shared__ C xch[BW];      // row c's block values, for the pivot row's owner
+  __shared__ C prow[BW];     // the pivot row's block values
+  __shared__ int bsw[BW];    // the block's pivot rows (swap c0 + j <-> bsw[j])
+  __shared__ int src[2 * BW], dst[2 * BW];   // the block's composed row moves
   __shared__ int nmove;
-  __shared__ C mv[NBMAX][2 * PB];            // staged values of the moves
-  __shared__ C L11[PB][PB];  // the block rows' factors (unit lower part used)
-  __shared__ C U12[PB][NBMAX];
+  __shared__ C mv[NBMAX][2 * BW];            // staged values of the moves
+  __shared__ C L11[BW][BW];  // the block rows' factors (unit lower part used)
+  __shared__ C U12[BW][NBMAX];
   double pv_min = INFINITY, pv_max = 0.0;
-  C x[RPT][PB];
-  for (int c0 = 0; c0 < nbf; c0 += PB) {
-    const int c1 = (c0 + PB < nbf) ? c0 + PB : nbf;
+  C x[RPT][BW];
+  for (int c0 = 0; c0 < nbf; c0 += BW) {
+    const int c1 = (c0 + BW < nbf) ? c0 + BW : nbf;
     const int bw = c1 - c0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = t + i * NT;
 #pragma unroll
-      for (int j = 0; j < PB; ++j) {
+      for (int j = 0; j < BW; ++j) {
         const bool ok = r < R && j < bw;
         x[i][j] = c0 == 0 ? ld_or_zero(ok, F + (long long)(k + (ok ? r : 0)) + (long long)(k + j) * n)
                           : (ok ? P[r + (long long)(c0 + j) * R] : czero<C>());
@@ -619,7 +634,7 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     }
     if (c0 == 0) __syncthreads();   // the copy is complete before any row swap
 #pragma unroll
-    for (int jc = 0; jc < PB; ++jc) {
+    for (int jc = 0; jc < BW; ++jc) {
       if (jc >= bw) break;
       const int c = c0 + jc;
       // arg max |P[r][c]|, r >= c (ties: smallest row): wave maxima to LDS,
@@ -668,13 +683,13 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
         for (int i = 0; i < RPT; ++i)
           if (i == ip)
 #pragma unroll
-            for (int j = 0; j < PB; ++j) prow[j] = x[i][j];
+            for (int j = 0; j < BW; ++j) prow[j] = x[i][j];
       if (t == tc && p != c)
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
           if (i == ic)
 #pragma unroll
-            for (int j = 0; j < PB; ++j) xch[j] = x[i][j];
+            for (int j = 0; j < BW; ++j) xch[j] = x[i][j];
       __syncthreads();
       if (p != c) {
         if (t == tc)
@@ -682,13 +697,13 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
           for (int i = 0; i < RPT; ++i)
             if (i == ic)
 #pragma unroll
-              for (int j = 0; j < PB; ++j) x[i][j] = prow[j];
+              for (int j = 0; j < BW; ++j) x[i][j] = prow[j];
         if (t == tp)
 #pragma unroll
           for (int i = 0; i < RPT; ++i)
             if (i == ip)
 #pragma unroll
-              for (int j = 0; j < PB; ++j) x[i][j] = xch[j];
+              for (int j = 0; j < BW; ++j) x[i][j] = xch[j];
       }
       C piv = prow[jc];
       if (cabs2(piv) == 0.0) piv = cmake<C>(1.0, 0.0);
@@ -702,12 +717,12 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
           const C l = cmul(x[i][jc], ipv);
           x[i][jc] = l;
 #pragma unroll
-          for (int j = 0; j < PB; ++j)
+          for (int j = 0; j < BW; ++j)
             if (j > jc && j < bw) cfms(x[i][j], l, prow[j]);
         }
       }
     }
-    // the block's row swaps, composed into moves dst <- src (at most 2 PB
+    // the block's row swaps, composed into moves dst <- src (at most 2 BW
     // rows), applied at once to the columns outside the block and to the
     // row permutation: every value is loaded before any is stored
     if (t == 0) {
@@ -734,10 +749,20 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     __syncthreads();
     const int nm = nmove;
     if (nm > 0) {
-      // through LDS: every moved value is read before any is written
-      for (int e = t; e < nbf * nm; e += NT) {
-        const int cc = e / nm, q = e % nm;
-        if (cc < c0 || cc >= c1) mv[cc][q] = P[src[q] + (long long)cc * R];
+      // through LDS: every moved value is read before any is written (all
+      // of a thread's loads issued before its first LDS store)
+      constexpr int MV = (NBMAX * 2 * BW + NT - 1) / NT;
+      C mvv[MV];
+#pragma unroll
+      for (int i = 0; i < MV; ++i) {
+        const int e = t + NT * i, cc = e / nm, q = e % nm;
+        const bool ok = e < nbf * nm && (cc < c0 || cc >= c1);
+        mvv[i] = ld_or_zero(ok, P + (ok ? src[q] + (long long)cc * R : 0));
+      }
+#pragma unroll
+      for (int i = 0; i < MV; ++i) {
+        const int e = t + NT * i, cc = e / nm, q = e % nm;
+        if (e < nbf * nm && (cc < c0 || cc >= c1)) mv[cc][q] = mvv[i];
       }
       int pv = 0;
       if (t < nm) pv = perm[k + src[t]];
@@ -755,11 +780,11 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
       const int r = t + i * NT;
       if (r < R)
 #pragma unroll
-        for (int j = 0; j < PB; ++j)
+        for (int j = 0; j < BW; ++j)
           if (j < bw) P[r + (long long)(c0 + j) * R] = x[i][j];
       if (r >= c0 && r < c1)
 #pragma unroll
-        for (int j = 0; j < PB; ++j) L11[r - c0][j] = x[i][j];
+        for (int j = 0; j < BW; ++j) L11[r - c0][j] = x[i][j];
     }
     __syncthreads();
     if (c1 >= nbf) break;
@@ -768,15 +793,15 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
     // the column's block rows loaded together first
     for (int cc = t; cc < W; cc += NT) {
       const long long col = (long long)(c1 + cc) * R;
-      C u[PB];
+      C u[BW];
 #pragma unroll
-      for (int i = 0; i < PB; ++i) u[i] = i < bw ? P[c0 + i + col] : czero<C>();
+      for (int i = 0; i < BW; ++i) u[i] = i < bw ? P[c0 + i + col] : czero<C>();
 #pragma unroll
-      for (int i = 0; i < PB; ++i) {
+      for (int i = 0; i < BW; ++i) {
         if (i >= bw) break;
         C y = u[i];
 #pragma unroll
-        for (int j = 0; j < PB; ++j)
+        for (int j = 0; j < BW; ++j)
           if (j < i) cfms(y, L11[i][j], u[j]);
         u[i] = y;
         U12[i][cc] = y;
@@ -808,7 +833,7 @@ k_panel_rb(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
         for (int q = 0; q < TG; ++q) {
           if (cg + q >= W) break;
 #pragma unroll
-          for (int j = 0; j < PB; ++j)
+          for (int j = 0; j < BW; ++j)
             if (j < bw) cfms(y[i][q], x[i][j], U12[j][cg + q]);
           P[r + (long long)(c1 + cg + q) * R] = y[i][q];
         }
@@ -1141,8 +1166,8 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_
   hipLaunchKernelGGL((k_panel<T, NT, PR>), dim3(n_active), dim3(NT), 0, st,        \
                      fronts, ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm, \
                      perm_off, status)
-#define HELM_PANEL_RB(NT, RPT)                                                      \
-  hipLaunchKernelGGL((k_panel_rb<T, NT, RPT>), dim3(n_active), dim3(NT), 0, st,    \
+#define HELM_PANEL_RB(NT, RPT, BW)                                                  \
+  hipLaunchKernelGGL((k_panel_rb<T, NT, RPT, BW>), dim3(n_active), dim3(NT), 0, st, \
                      fronts, ids, k, nb, ws0, ws1, panel, panel_off, D, ipiv, perm, \
                      perm_off, status)
   // complex64 up to 512 rows: a row per thread, the panel in registers;
@@ -1165,13 +1190,14 @@ void launch_panel(const FrontDev* fronts, const int* ids, int n_active, int max_
   }
   if (max_rows <= 64) HELM_PANEL(64, 64);
   else if (max_rows <= panel_lds_rows<T>()) HELM_PANEL(256, panel_lds_rows<T>());
-  else if (max_rows <= 1024) HELM_PANEL_RB(256, 4);
+  else if (max_rows <= 1024) HELM_PANEL_RB(256, 4, PB);
   else if constexpr (C64) {
-    if (max_rows <= 2048) HELM_PANEL_RB(1024, 2);
-    else if (max_rows <= 4096) HELM_PANEL_RB(1024, 4);
+    if (max_rows <= 2048) HELM_PANEL_RB(1024, 2, PB);
+    else if (max_rows <= 4096) HELM_PANEL_RB(1024, 4, PB);
+    else if (max_rows <= 6144) HELM_PANEL_RB(1024, 6, PB / 2);
     else HELM_PANEL(1024, 0);
   } else {
-    if (max_rows <= 2048) HELM_PANEL_RB(512, 4);
+    if (max_rows <= 2048) HELM_PANEL_RB(512, 4, PB);
     else HELM_PANEL(1024, 0);
   }
 #undef HELM_PANEL_REGS
