@@ -511,26 +511,45 @@ k_bwd_gemv(const FrontDev* __restrict__ fronts, const int* __restrict__ ids,
 #pragma unroll
       for (int c = 0; c < KC; ++c) cfma(acc[r][c], fa[r], xv[c]);
   }
+  // reduce-scatter over the group: each halving step trades half of the
+  // lane's row sums with the partner lane (offset GW/2, GW/4, ...), so
+  // that after log2(RPG) steps the lane holds one row's partial sum (the
+  // row given by its high bits); a butterfly over the GW/RPG lanes that
+  // share the row completes it (RPG = 8: 18 exchanges per column instead
+  // of 80 for a butterfly per row)
+  static_assert((RPG & (RPG - 1)) == 0 && RPG <= GW && KC <= GW / RPG, "group shape");
+  int rsel = 0;
 #pragma unroll
-  for (int r = 0; r < RPG; ++r) {
+  for (int h = RPG / 2, off = GW / 2; h >= 1; h >>= 1, off >>= 1) {
+    const bool up = (gl & off) != 0;
 #pragma unroll
-    for (int c = 0; c < KC; ++c) {
+    for (int i = 0; i < h; ++i)
 #pragma unroll
-      for (int off = GW / 2; off > 0; off >>= 1) {
-        acc[r][c].x += shfl_xor_t(acc[r][c].x, off);
-        acc[r][c].y += shfl_xor_t(acc[r][c].y, off);
+      for (int c = 0; c < KC; ++c) {
+        const C send = up ? acc[i][c] : acc[i + h][c];
+        const C keep = up ? acc[i + h][c] : acc[i][c];
+        acc[i][c].x = keep.x + shfl_xor_t(send.x, off);
+        acc[i][c].y = keep.y + shfl_xor_t(send.y, off);
       }
-    }
-    if (row_ok[r] && gl < KC) {
-      const int m = m0 + g + NG * r;
-      C z = acc[r][0];
+    if (up) rsel += h;
+  }
 #pragma unroll
-      for (int c = 1; c < KC; ++c)
-        if (gl == c) z = acc[r][c];
-      const long long idx = (long long)(f.off + m) * KC + gl;
-      if (tk.nch_b > 1) st(S + (tk.scr_b + (long long)chunk * f.s + m) * KC + gl, z);
-      else st(X + idx, cadd(ld_or_zero(!(raw & kZeroZ), Z + idx), z));
+  for (int c = 0; c < KC; ++c)
+#pragma unroll
+    for (int off = GW / (2 * RPG); off > 0; off >>= 1) {
+      acc[0][c].x += shfl_xor_t(acc[0][c].x, off);
+      acc[0][c].y += shfl_xor_t(acc[0][c].y, off);
     }
+  const int lo = gl & (GW / RPG - 1);
+  const int m = m0 + g + NG * rsel;
+  if (m < f.s && lo < KC) {
+    C z = acc[0][0];
+#pragma unroll
+    for (int c = 1; c < KC; ++c)
+      if (lo == c) z = acc[0][c];
+    const long long idx = (long long)(f.off + m) * KC + lo;
+    if (tk.nch_b > 1) st(S + (tk.scr_b + (long long)chunk * f.s + m) * KC + lo, z);
+    else st(X + idx, cadd(ld_or_zero(!(raw & kZeroZ), Z + idx), z));
   }
 }
 
