@@ -80,6 +80,21 @@ def read_trace(d):
     return [(n, t) for _, n, t in rows]
 
 
+def _short(name):
+    """A kernel name without its namespace prefix and argument list."""
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("helm::kern::(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and i > 0:
+            return n[:i]
+    return n[:90]
+
+
 def cmd_stats(a):
     if a.last:
         # the last N dispatches of the matching kernels: the timed steps of a
@@ -244,6 +259,17 @@ def cmd_timeline(a):
         tot = sum(e - s for s, e in sel)
         rate = f"{512.0 * mops[label] / cov / 1e3:.1f}" if label in mops else "-"
         print(f"| {label} | {len(sel)} | {tot / 1e6:.1f} | {cov / 1e6:.1f} | {tot / cov:.2f} | {rate} |")
+    if a.top > 0:
+        # the kernels with the most summed time in the trace (or window)
+        per = {}
+        for s0, e0, n, _ in rows:
+            c, t = per.get(n, (0, 0))
+            per[n] = (c + 1, t + e0 - s0)
+        print()
+        print("| kernel | dispatches | summed ms | share of the summed time |")
+        print("|---|---|---|---|")
+        for n, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:a.top]:
+            print(f"| `{_short(n)}` | {c} | {t / 1e6:.1f} | {t / summed:.3f} |")
 
 
 def read_traffic(path):
@@ -297,6 +323,8 @@ def main(argv=None):
                     help="restrict to a window delimited by dispatches matching this regex")
     tl.add_argument("--window-from", type=int, default=0)
     tl.add_argument("--window-to", type=int, default=0)
+    tl.add_argument("--top", type=int, default=0,
+                    help="also list the N kernels with the most summed time")
     a = ap.parse_args(argv)
     {"stats": cmd_stats, "traffic": cmd_traffic, "mfma": cmd_mfma,
      "timeline": cmd_timeline}[a.cmd](a)
