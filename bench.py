@@ -548,7 +548,11 @@ def main():
         "sweep_gemm_lu_share_tflops": sw.get("flops", 0.0) / max(sw.get("total_ms", 0.0)
                                                                  * 1e-3, 1e-12) / 1e12,
         "pivot_min": finfo["pivot_min"], "pivot_max": finfo["pivot_max"],
-        "pivot_growth": finfo["pivot_growth"]}
+        "pivot_growth": finfo["pivot_growth"],
+        # wall time of helm_factorize by phase (host plans, device set-up,
+        # numeric factorization, single-layer launch lists)
+        "phases_s": {"symbolic": finfo["symbolic_seconds"], "setup": finfo["setup_seconds"],
+                     "numeric": finfo["seconds"], "lists": finfo["lists_seconds"]}}
     out = {
         "metric": METRIC,
         "value": value,

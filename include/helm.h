@@ -312,13 +312,23 @@ int helm_set_solve_options(helm_handle* h, const helm_options* opt);
  *                   front;
  *   diag_max     -- largest |diagonal entry| of the assembled operators;
  *                   pivot_max / diag_max is the pivot growth;
- *   factor_bytes -- resident factors; n_fronts, max_front -- over layers. */
+ *   factor_bytes -- resident factors; n_fronts, max_front -- over layers;
+ *   seconds      -- wall time of the numeric factorization (assembly and
+ *                   elimination of every front);
+ *   symbolic_seconds -- the layers' nested-dissection plans and PML
+ *                   profiles (host);
+ *   setup_seconds -- device allocation and upload of the model, the plans
+ *                   and the front tables;
+ *   lists_seconds -- launch lists of the single-layer solves.
+ * The four times add up to the wall time of helm_factorize(_dev) apart
+ * from the model's copy and checks. */
 typedef struct {
   double seconds;
   double lu_flops, gj_flops;
   double pivot_min, pivot_max, diag_max;
   size_t factor_bytes;
   long long n_fronts, max_front;
+  double symbolic_seconds, setup_seconds, lists_seconds;
 } helm_factor_info;
 
 int helm_get_factor_info(const helm_handle* h, helm_factor_info* out);

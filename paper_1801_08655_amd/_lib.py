@@ -124,7 +124,8 @@ class helm_factor_info(ctypes.Structure):
                 ("gj_flops", ctypes.c_double), ("pivot_min", ctypes.c_double),
                 ("pivot_max", ctypes.c_double), ("diag_max", ctypes.c_double),
                 ("factor_bytes", ctypes.c_size_t), ("n_fronts", ctypes.c_longlong),
-                ("max_front", ctypes.c_longlong)]
+                ("max_front", ctypes.c_longlong), ("symbolic_seconds", ctypes.c_double),
+                ("setup_seconds", ctypes.c_double), ("lists_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

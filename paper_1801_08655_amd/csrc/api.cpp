@@ -1,5 +1,6 @@
 // C ABI of the library (declarations and contracts in include/helm.h).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -71,14 +72,23 @@ int factorize_common(const helm_grid* g, const double* m, bool on_device, double
   double C = o.pml_C > 0 ? o.pml_C : 20.0 * max_velocity(mh);
   std::unique_ptr<helm_handle> h(new helm_handle);
   Handle& H = h->impl;
+  using clk = std::chrono::steady_clock;
+  auto since = [](clk::time_point t) { return std::chrono::duration<double>(clk::now() - t).count(); };
+  auto t0 = clk::now();
   build_geometry(H.G, *g, omega, pml_width, n_layers, o.pml_local, C, o.leaf_size);
+  H.symbolic_seconds = since(t0);
+  t0 = clk::now();
   H.init_device(o);
   (void)noalloc_scratch(H.device);   // set-up of the allocation-free entry point
   H.upload_geometry(mh.data(), false);
   H.build_fronts();
+  HELM_HIP(hipStreamSynchronize(H.st));
+  H.setup_seconds = since(t0);
   H.factorize();
   // the launch lists of every single-layer solve (the sweeps' unit of work)
+  t0 = clk::now();
   for (int l = 0; l < H.G.L; ++l) H.single_sets.push_back(&H.layer_set({l}));
+  H.lists_seconds = since(t0);
   *out = h.release();
   return HELM_OK;
 }
@@ -369,6 +379,9 @@ int helm_get_factor_info(const helm_handle* h, helm_factor_info* out) {
     long long mf = 0;
     for (const auto& P : H.G.layers) mf = std::max(mf, P.max_front);
     out->max_front = mf;
+    out->symbolic_seconds = H.symbolic_seconds;
+    out->setup_seconds = H.setup_seconds;
+    out->lists_seconds = H.lists_seconds;
     return HELM_OK;
   });
 }

@@ -174,6 +174,9 @@ struct Handle {
 
   // statistics
   double factor_seconds = 0;
+  // wall time of the other phases of helm_factorize (host plans, device
+  // set-up, single-layer launch lists)
+  double symbolic_seconds = 0, setup_seconds = 0, lists_seconds = 0;
   double factor_flops = 0;        // LU count of every front (algorithmic)
   double factor_gj_flops = 0;     // flops the Gauss-Jordan sweep executes
   // pivot statistics of the last factorization (device: status flag, then

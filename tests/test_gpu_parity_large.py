@@ -124,8 +124,11 @@ def test_factor_info_counts_and_pivots():
     for t in tlc._layer_planes(nz, wl.pml, wl.n_layers, wl.pml_local):
         for s_, b in tlc._nd_count(nx, ny, t, 64):
             lu += 4.0 * (2.0 / 3.0 * s_ ** 3 + 2.0 * s_ ** 2 * b + 2.0 * s_ * b * b)
+    import time
     for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
         s = _solver(wl, prec)
+        wall = time.perf_counter() - t0
         fi = s.factor_info()
         print(prec, fi)
         assert fi["lu_flops"] == pytest.approx(lu, rel=1e-12)
@@ -133,6 +136,10 @@ def test_factor_info_counts_and_pivots():
         assert 0 < fi["pivot_min"] <= fi["pivot_max"] < np.inf
         assert 0 < fi["pivot_growth"] < 1e3
         assert fi["seconds"] > 0 and fi["factor_bytes"] > 0
+        # the phases of the factorization call are timed and fit in its wall time
+        phases = [fi["symbolic_seconds"], fi["setup_seconds"], fi["seconds"], fi["lists_seconds"]]
+        assert all(p > 0 for p in phases)
+        assert sum(phases) <= wall
         s.close()
 
 
