@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--fp64-warmup", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--fp64-loose-tol", type=float, default=1e-7,
-                    help="GMRES tolerance of the FP64 run at the mixed path's accuracy")
+    ap.add_argument("--fp64-loose-tol", default="1e-6,1e-7",
+                    help="GMRES tolerances of the FP64 runs compared at equal accuracy: "
+                         "the fastest whose error meets the mixed path's target counts")
     ap.add_argument("--inner-tol", type=float, default=1e-3,
                     help="GMRES tolerance of the first mixed-precision solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -343,7 +344,8 @@ def rhs_scaling_bench(args, torch, pt):
                "ms_per_step": 1e3 * total / args.steps,
                "layer_solves_per_step": info["layer_solves"],
                "ms_per_layer_solve": 1e3 * total / args.steps / max(1, info["layer_solves"]),
-               "gmres_iters": info["gmres_iters"], "est_error_max": info["est_error_max"]}
+               "gmres_iters": info["gmres_iters"], "est_error_max": info["est_error_max"],
+               "ir_width": info["ir_width"]}
         log(f"[rhs-scaling] {pt_}")
         points.append(pt_)
     s.close()
@@ -437,7 +439,10 @@ def main():
     tune = 0 if args.no_autotune else pt._lib.HELM_FLAG_AUTOTUNE
     flags = (pt._lib.HELM_FLAG_PROFILE if args.profile else 0) | tune
     step_flags = tune
-    prof_flags = (pt._lib.HELM_FLAG_PROFILE_FWD if args.profile else 0) | tune
+    # (every refinement step of the profiled pass at the full batch width, so
+    # that the timed class holds the 64-column launches only)
+    prof_flags = (pt._lib.HELM_FLAG_PROFILE_FWD if args.profile else 0) | tune | \
+        pt._lib.HELM_FLAG_NO_NARROW
     common = dict(pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=64, flags=flags)
     mixed_kw = dict(ir_tol=1e-10, inner_tol=args.inner_tol, inner_tol_refine=2e-4,
                     err_target=1e-6, ir_max_steps=4)
@@ -510,16 +515,23 @@ def main():
                 "gmres_iters": info64["gmres_iters"],
                 "rel_residual_max": info64["rel_residual_max"]}
         log(f"[fp64] {fp64}")
-        # the FP64 path stopped as soon as its error meets the mixed path's
-        # target: the speed-up of the precision alone, at equal accuracy
-        s64.set_options(gmres_tol=args.fp64_loose_tol)
-        u_l, info_l, tot_l, _ = timed_solves(s64, srcs, 1, 0, torch)
-        d = (u_l - u_ref).reshape(R, -1).norm(dim=1) / u_ref.reshape(R, -1).norm(dim=1)
-        fp64_loose = {"value": R / tot_l, "gmres_tol": args.fp64_loose_tol,
-                      "gmres_iters": info_l["gmres_iters"],
-                      "err_vs_fp64_max": float(d.max())}
-        log(f"[fp64 loose] {fp64_loose}")
-        del u_l
+        # the FP64 path stopped early: the fastest such run whose error still
+        # meets the mixed path's target (1e-6 for every column) gives the
+        # speed-up of the precision alone, at equal accuracy
+        loose = []
+        for tol in (float(x) for x in args.fp64_loose_tol.split(",")):
+            s64.set_options(gmres_tol=tol)
+            u_l, info_l, tot_l, _ = timed_solves(s64, srcs, 1, 0, torch)
+            d = (u_l - u_ref).reshape(R, -1).norm(dim=1) / u_ref.reshape(R, -1).norm(dim=1)
+            loose.append({"value": R / tot_l, "gmres_tol": tol,
+                          "gmres_iters": info_l["gmres_iters"],
+                          "err_vs_fp64_max": float(d.max())})
+            log(f"[fp64 loose] {loose[-1]}")
+            del u_l
+        ok = [x for x in loose if x["err_vs_fp64_max"] <= mixed_kw["err_target"]]
+        fp64_loose = max(ok, key=lambda x: x["value"]) if ok else \
+            min(loose, key=lambda x: x["gmres_tol"])
+        extra["fp64_at_tolerances"] = loose
         s64.close()
         del s64
         torch.cuda.empty_cache()
@@ -585,6 +597,7 @@ def main():
         "est_error_max": info["est_error_max"],
         "ir_residual": info["ir_residual"],
         "ir_gmres_iters": info["ir_gmres_iters"],
+        "ir_width": info["ir_width"],
         "layer_solves_per_step": info["layer_solves"],
         "pcie_inclusive": pcie,
         "roofline": rl,

@@ -98,6 +98,12 @@ extern "C" {
                                 products (default: three, as the
                                 substitutions).  No effect on HELM_FP64
                                 handles                                      */
+#define HELM_FLAG_NO_NARROW 2048 /* mixed: every refinement step runs at the
+                                batch's full width.  By default a column that
+                                meets the target leaves the refinement, and a
+                                later step whose remaining columns fit in half
+                                the width or less runs them, gathered, at the
+                                narrowest power-of-two width that holds them  */
 #define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
                                 the factorization leaves one leaf front of
                                 layer 0 unassembled, so its pivots are exactly
@@ -161,14 +167,14 @@ typedef struct {
   double ir_residual[8];     /* max over columns of |f - H u| / |f| after each
                                 refinement step (first 8 steps)              */
   double est_error_max;      /* mixed: max over columns of the estimated
-                                relative error |u - H^-1 f| / |u|, from the
-                                contraction of successive corrections:
-                                |d_k|/|u| * q/(1-q), q = |d_k|/|d_{k-1}|
-                                (from the third step the larger of the last
-                                two ratios; scaled by res_k/res_{k-1} when
-                                step k's GMRES stopped at a larger relative
-                                residual res_k); 1 when only one step was
-                                taken or q > 1/2                             */
+                                relative error |u - H^-1 f| / |u| when the
+                                column stopped: |d_k|/|u| * q/(1-q) with d_k
+                                the last correction and q the larger of the
+                                last two measured contractions |d_k|/|d_{k-1}|
+                                (one after the second step) and of 4 times
+                                the relative residual the step's GMRES
+                                reached; 1 (unknown) after a single step or
+                                when q > 1/2                                 */
   int    ir_gmres_iters[8];  /* GMRES iterations of each refinement step     */
   /* Per right-hand side: arrays of n_rhs entries owned by the caller, each
    * may be NULL; set them before the call (they survive the call's reset of
@@ -183,6 +189,8 @@ typedef struct {
                                 still active, summed over refinement steps   */
   double krylov_bytes;       /* device bytes of the Krylov vectors (basis or
                                 Bi-CGSTAB work vectors) the solve held       */
+  int    ir_width[8];        /* columns each refinement step ran at (first 8
+                                steps; the widest over the internal batches) */
 } helm_solve_info;
 
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,

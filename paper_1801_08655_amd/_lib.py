@@ -43,6 +43,7 @@ HELM_FLAG_UNPOLARIZED = 128
 HELM_FLAG_NO_PRUNE = 256
 HELM_FLAG_GEMM_4M = 512
 HELM_FLAG_FACTOR_4M = 1024
+HELM_FLAG_NO_NARROW = 2048
 HELM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
@@ -95,6 +96,7 @@ class helm_solve_info(ctypes.Structure):
         ("rhs_ir_steps", ctypes.c_void_p),
         ("rhs_gmres_iters", ctypes.c_void_p),
         ("krylov_bytes", ctypes.c_double),
+        ("ir_width", ctypes.c_int * 8),
     ]
     PER_RHS = ("rhs_rel_residual", "rhs_est_error", "rhs_ir_steps", "rhs_gmres_iters")
 
@@ -114,6 +116,7 @@ class helm_solve_info(ctypes.Structure):
         n = max(1, min(8, self.ir_steps))
         d["ir_residual"] = list(self.ir_residual[:n])
         d["ir_gmres_iters"] = list(self.ir_gmres_iters[:n])
+        d["ir_width"] = list(self.ir_width[:n])
         for name, a in getattr(self, "_arrays", {}).items():
             d[name] = a.tolist()
         return d

@@ -791,6 +791,28 @@ int Method::refine_step(const double2* F, double2* U, double2* R, double2* D,
   return s;
 }
 
+// The cached batch of width w for narrowed refinement steps, with its
+// gathered volumes; none (and no further attempts) when device memory
+// refuses it.
+Method* Method::narrower(int w) {
+  if (!narrow_ok) return nullptr;
+  if (!child || child->k != w) {
+    child.reset();
+    try {
+      std::unique_ptr<Method> c(new Method(H, w));
+      c->ensure_volumes();
+      c->vf.alloc((size_t)N * w * sizeof(double2));
+      c->vu.alloc((size_t)N * w * sizeof(double2));
+      child = std::move(c);
+    } catch (const Error& e) {
+      if (e.code != HELM_ENOMEM) throw;
+      narrow_ok = false;
+      return nullptr;
+    }
+  }
+  return child.get();
+}
+
 void Method::ensure_volumes() {
   if (!vr.p) {
     vr.alloc((size_t)N * k * sizeof(double2));
@@ -818,6 +840,7 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
     residual(f, u, r, rel);
     if (info) {
       info->ir_steps = std::max(info->ir_steps, 1);
+      info->ir_width[0] = std::max(info->ir_width[0], k);
       info->t_residual_ms += now_ms() - tr;
       double mx = 0;
       for (double v : rel) mx = std::max(mx, v);
@@ -825,45 +848,117 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
       info->ir_gmres_iters[0] = std::max(info->ir_gmres_iters[0], info->gmres_iters - it0);
     }
   } else {
-    // iterative refinement: u <- u + solve_c64(f - H u), FP64 residuals
+    // iterative refinement: u <- u + solve_c64(f - H u), FP64 residuals.  A
+    // column that meets the target is final and takes no further part.  When
+    // the columns a later step still has to refine fit in half the batch or
+    // less, they are gathered into the first slots of a batch of the
+    // narrowest power-of-two width that holds them (its layer solves stream
+    // the same factors with fewer columns), and the results scattered back.
     HELM_HIP(hipMemsetAsync(u, 0, (size_t)N * k * sizeof(double2), H.st));
     HELM_HIP(hipMemcpyAsync(r, f, (size_t)N * k * sizeof(double2), hipMemcpyDeviceToDevice,
                             H.st));
     int steps = 0;
     status = HELM_ENOCONV;
     std::vector<RefineTrack> track(k);
-    StepNorms nm;
+    std::vector<char> met(k, 0);
+    rel.assign(k, 0.0);
+    const size_t col = (size_t)N * sizeof(double2);
+    double emx_last = 0;
     for (int it = 0; it < std::max(1, o.ir_max_steps); ++it) {
       int it0 = info ? info->gmres_iters : 0;
-      std::vector<double> tol(k);
-      for (int c = 0; c < k; ++c) tol[c] = refinement_tol(it, track[c], o);
-      refine_step(f, u, r, vd.as<double2>(), tol, nm, info);
-      rel = nm.rel;
+      std::vector<int> todo;
+      for (int c = 0; c < k; ++c)
+        if (!met[c]) todo.push_back(c);
+      const int m = (int)todo.size();
+      std::vector<double> tol(k, 0.0), teff(k, 0.0);
+      std::vector<int> citer(k, 0);
+      for (int c : todo) tol[c] = refinement_tol(it, track[c], o);
+      int w = 1;
+      while (w < m) w *= 2;
+      Method* S = (it > 0 && 2 * w <= k && !(o.flags & HELM_FLAG_NO_NARROW)) ? narrower(w)
+                                                                               : nullptr;
+      StepNorms nm;
+      if (S) {
+        // slot j < m holds column todo[j]; the slots past m hold zero
+        // columns (a zero source: converged at once, zero correction)
+        double2* fc = S->vf.as<double2>();
+        double2* uc = S->vu.as<double2>();
+        double2* rc = S->vr.as<double2>();
+        for (int j = 0; j < w; ++j) {
+          if (j < m) {
+            const size_t src = (size_t)todo[j] * N;
+            HELM_HIP(hipMemcpyAsync(fc + (size_t)j * N, f + src, col, hipMemcpyDeviceToDevice, H.st));
+            HELM_HIP(hipMemcpyAsync(uc + (size_t)j * N, u + src, col, hipMemcpyDeviceToDevice, H.st));
+            HELM_HIP(hipMemcpyAsync(rc + (size_t)j * N, r + src, col, hipMemcpyDeviceToDevice, H.st));
+          } else {
+            HELM_HIP(hipMemsetAsync(fc + (size_t)j * N, 0, col, H.st));
+            HELM_HIP(hipMemsetAsync(uc + (size_t)j * N, 0, col, H.st));
+            HELM_HIP(hipMemsetAsync(rc + (size_t)j * N, 0, col, H.st));
+          }
+        }
+        std::vector<double> tol_w(w, 0.0);
+        for (int j = 0; j < m; ++j) tol_w[j] = tol[todo[j]];
+        StepNorms nw;
+        S->refine_step(fc, uc, rc, S->vd.as<double2>(), tol_w, nw, info);
+        nm.rel.assign(k, 0.0);
+        nm.dn.assign(k, 0.0);
+        nm.un.assign(k, 0.0);
+        for (int j = 0; j < m; ++j) {
+          const int c = todo[j];
+          const size_t dst = (size_t)c * N;
+          HELM_HIP(hipMemcpyAsync(u + dst, uc + (size_t)j * N, col, hipMemcpyDeviceToDevice, H.st));
+          HELM_HIP(hipMemcpyAsync(r + dst, rc + (size_t)j * N, col, hipMemcpyDeviceToDevice, H.st));
+          nm.rel[c] = nw.rel[j];
+          nm.dn[c] = nw.dn[j];
+          nm.un[c] = nw.un[j];
+          teff[c] = S->last_resid.size() == (size_t)w ? S->last_resid[j] : tol[c];
+          citer[c] = S->col_iters.size() == (size_t)w ? S->col_iters[j] : 0;
+        }
+      } else {
+        // the final columns get a zero residual: converged at once for the
+        // Krylov solver, and a zero correction
+        for (int c = 0; c < k; ++c)
+          if (met[c]) HELM_HIP(hipMemsetAsync(r + (size_t)c * N, 0, col, H.st));
+        refine_step(f, u, r, vd.as<double2>(), tol, nm, info);
+        for (int c : todo) {
+          teff[c] = last_resid.size() == (size_t)k ? last_resid[c] : tol[c];
+          citer[c] = col_iters.size() == (size_t)k ? col_iters[c] : 0;
+        }
+      }
       ++steps;
+      for (int c : todo) {
+        rel[c] = nm.rel[c];
+        // the relative residual GMRES reached stands for the step's tolerance
+        est_c[c] = refinement_error(it, track[c], nm.dn[c], nm.un[c], teff[c]);
+        iters_c[c] += citer[c];
+        if (refinement_met(rel[c], est_c[c], o)) {
+          met[c] = 1;
+          steps_c[c] = steps;
+        }
+      }
       double mx = 0, emx = 0;
+      bool all = true;
       for (int c = 0; c < k; ++c) {
         mx = std::max(mx, std::isfinite(rel[c]) ? rel[c] : 1e300);
-        // the relative residual GMRES reached stands for the step's tolerance
-        const double teff = last_resid.size() == (size_t)k ? last_resid[c] : tol[c];
-        double est = refinement_error(it, track[c], nm.dn[c], nm.un[c], teff);
-        emx = std::max(emx, est);
-        est_c[c] = est;
-        if (col_iters.size() == (size_t)k) iters_c[c] += col_iters[c];
-        if (steps_c[c] == 0 && refinement_met(rel[c], est, o)) steps_c[c] = steps;
+        emx = std::max(emx, est_c[c]);
+        all = all && met[c];
       }
       if (info && it < 8) {
         info->ir_residual[it] = std::max(info->ir_residual[it], mx);
         info->ir_gmres_iters[it] = std::max(info->ir_gmres_iters[it], info->gmres_iters - it0);
+        info->ir_width[it] = std::max(info->ir_width[it], S ? w : k);
       }
-      if (info) info->est_error_max = emx;
-      bool all = true;
-      for (int c = 0; c < k; ++c) all = all && refinement_met(rel[c], est_c[c], o);
+      emx_last = emx;
       if (all) {
         status = HELM_OK;
         break;
       }
     }
-    if (info) info->ir_steps = std::max(info->ir_steps, steps);
+    if (info) {
+      info->ir_steps = std::max(info->ir_steps, steps);
+      // the columns' final estimates (max over the internal batches)
+      info->est_error_max = std::max(info->est_error_max, emx_last);
+    }
     for (int c = 0; c < k; ++c)
       if (steps_c[c] == 0) steps_c[c] = steps;
   }

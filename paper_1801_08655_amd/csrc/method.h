@@ -2,6 +2,7 @@
 #pragma once
 
 #include <functional>
+#include <memory>
 #include <vector>
 
 #include "handle.h"
@@ -15,6 +16,11 @@ struct Method {
   DevMem y, zd, zu, keep, dot_partial, hcol, norm_partial, norm_out, scale;
   DevMem fpol, bpol, xpol;   // polarized right-hand side, P b and the iterate
   DevMem vr, vd;             // FP64 volumes: residual and correction
+  DevMem vf, vu;             // gathered source and solution (narrowed steps)
+  // a narrower batch for the refinement steps that only some columns need
+  std::unique_ptr<Method> child;
+  bool narrow_ok = true;     // cleared when device memory refused one
+  Method* narrower(int w);
   const LayerSet* set_all = nullptr;
   const LayerSet* set_lower = nullptr;
   std::vector<const LayerSet*> single;

@@ -143,6 +143,48 @@ def test_factor_info_counts_and_pivots():
         s.close()
 
 
+def test_narrowed_refinement_steps_match_full_width():
+    """A column that meets the target leaves the refinement, and a later
+    step whose remaining columns fit in half the batch runs them gathered at
+    the narrowest power-of-two width.  err_target is placed in the widest gap
+    between the columns' estimates after two steps, so that 4 to 7 of the 8
+    columns stop there: the third step runs at the narrower width, every
+    column matches the same solve with every step at full width
+    (HELM_FLAG_NO_NARROW), and both are within err_target of the oracle."""
+    import paper_1801_08655_amd as pt
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12), (11, 17, 15), (5, 20, 9), (16, 6, 18),
+            (12, 12, 21), (18, 18, 7)]
+    wl, srcs, ref = _reference("layered-28", srcs)
+    k = len(srcs)
+    # the estimates after two steps (nothing stops on them: err_target tiny)
+    s = _solver(wl, "mixed", ir_tol=1e-300, err_target=1e-300, ir_max_steps=2)
+    _, info = s.solve_points(srcs, info=True)
+    s.close()
+    e2 = np.sort(np.array(info["rhs_est_error"]))
+    j = max(range(k // 2, k), key=lambda i: e2[i] / e2[i - 1])
+    t = float(np.sqrt(e2[j] * e2[j - 1]))
+    m = k - j
+    w = 1 << (m - 1).bit_length()
+    print("estimates after two steps", e2, "stop below", t, "remaining", m, "width", w)
+    assert e2[j] > 1.05 * e2[j - 1]
+    out = {}
+    for label, flags in (("narrow", 0), ("full", pt._lib.HELM_FLAG_NO_NARROW)):
+        s = _solver(wl, "mixed", ir_tol=1e-300, err_target=2 * t, ir_max_steps=6, flags=flags)
+        u, inf = s.solve_points(srcs, info=True)
+        out[label] = (u.cpu().numpy().reshape(k, -1).T, inf)
+        print(label, "widths", inf["ir_width"], "steps", inf["rhs_ir_steps"],
+              "gmres per step", inf["ir_gmres_iters"], "layer solves", inf["layer_solves"])
+        s.close()
+    un, infn = out["narrow"]
+    uf, inff = out["full"]
+    assert infn["ir_width"][:3] == [k, k, w]
+    assert all(x == k for x in inff["ir_width"])
+    assert sorted(infn["rhs_ir_steps"]) == sorted(inff["rhs_ir_steps"])
+    assert sum(1 for x in infn["rhs_ir_steps"] if x == 2) == j
+    assert relative_error(un, uf).max() <= 1e-12
+    assert relative_error(un, ref).max() <= 2 * t
+
+
 @pytest.mark.parametrize("name", ["homogeneous-25", "smooth-24", "layered-28", "layered-40"])
 def test_refinement_stops_on_the_estimate_only_when_the_error_is_met(name):
     """The mixed path with the FP64 residual test switched off (ir_tol far
