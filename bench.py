@@ -598,6 +598,7 @@ def main():
         "ir_residual": info["ir_residual"],
         "ir_gmres_iters": info["ir_gmres_iters"],
         "ir_width": info["ir_width"],
+        "narrow_products": info["narrow_products"],
         "layer_solves_per_step": info["layer_solves"],
         "pcie_inclusive": pcie,
         "roofline": rl,

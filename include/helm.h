@@ -98,12 +98,17 @@ extern "C" {
                                 products (default: three, as the
                                 substitutions).  No effect on HELM_FP64
                                 handles                                      */
-#define HELM_FLAG_NO_NARROW 2048 /* mixed: every refinement step runs at the
-                                batch's full width.  By default a column that
-                                meets the target leaves the refinement, and a
-                                later step whose remaining columns fit in half
-                                the width or less runs them, gathered, at the
-                                narrowest power-of-two width that holds them  */
+#define HELM_FLAG_NO_NARROW 2048 /* every refinement step and every GMRES
+                                iteration runs at the batch's full width.  By
+                                default (mixed) a column that meets the target
+                                leaves the refinement, and a later step whose
+                                remaining columns fit in half the width or
+                                less runs them, gathered, at the narrowest
+                                power-of-two width that holds them; and (both
+                                precisions) a GMRES iteration whose running
+                                columns fit in half the width applies the
+                                operator to those columns only, gathered the
+                                same way                                      */
 #define HELM_FLAG_TEST_ZERO_FRONT 32 /* test hook of the zero-pivot status:
                                 the factorization leaves one leaf front of
                                 layer 0 unassembled, so its pivots are exactly
@@ -191,6 +196,8 @@ typedef struct {
                                 Bi-CGSTAB work vectors) the solve held       */
   int    ir_width[8];        /* columns each refinement step ran at (first 8
                                 steps; the widest over the internal batches) */
+  int    narrow_products;    /* GMRES operator products applied to the
+                                running columns at a narrower width          */
 } helm_solve_info;
 
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,

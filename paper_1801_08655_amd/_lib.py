@@ -97,6 +97,7 @@ class helm_solve_info(ctypes.Structure):
         ("rhs_gmres_iters", ctypes.c_void_p),
         ("krylov_bytes", ctypes.c_double),
         ("ir_width", ctypes.c_int * 8),
+        ("narrow_products", ctypes.c_int),
     ]
     PER_RHS = ("rhs_rel_residual", "rhs_est_error", "rhs_ir_steps", "rhs_gmres_iters")
 

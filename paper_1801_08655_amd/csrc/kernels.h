@@ -127,6 +127,18 @@ void launch_dot(const double2* x, const double2* y, long long V, int k,
                 double2* partial, double2* out, hipStream_t st);
 void launch_axpy_cols(double2* y, const double2* x, const double2* alpha,
                       double sign, long long V, int k, hipStream_t st);
+// Column selection of a batch of k interleaved columns (element e of column
+// c at e k + c), at most kMaxGatherCols columns.
+constexpr int kMaxGatherCols = 64;
+struct ColMap {
+  int col[kMaxGatherCols];
+};
+// out[e w + j] = in[e k + map.col[j]] for j < m, zero for m <= j < w
+void launch_gather_cols(double2* out, const double2* in, long long V, int k, int w, int m,
+                        const ColMap& map, hipStream_t st);
+// out[e k + c] = in[e w + slot.col[c]] where slot.col[c] >= 0, else zero
+void launch_scatter_cols(double2* out, const double2* in, long long V, int k, int w,
+                         const ColMap& slot, hipStream_t st);
 void launch_scale_cols(double2* y, const double2* x, const double* s, long long V,
                        int k, hipStream_t st);
 void launch_add(double2* y, const double2* x, const double2* z, long long n,

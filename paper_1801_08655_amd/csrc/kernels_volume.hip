@@ -296,6 +296,30 @@ __global__ void k_scale_cols(double2* y, const double2* x, const double* __restr
   }
 }
 
+// the columns map.col[0..m) of an interleaved batch of k into a batch of w
+__global__ void k_gather_cols(double2* __restrict__ out, const double2* __restrict__ in,
+                              long long V, int k, int w, int m, ColMap map) {
+  const long long total = V * w;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long e = i / w;
+    const int j = (int)(i % w);
+    out[i] = j < m ? in[e * k + map.col[j]] : make_double2(0.0, 0.0);
+  }
+}
+
+// back: column c of the batch of k from slot slot.col[c] of the batch of w
+__global__ void k_scatter_cols(double2* __restrict__ out, const double2* __restrict__ in,
+                               long long V, int k, int w, ColMap slot) {
+  const long long total = V * k;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long e = i / k;
+    const int s = slot.col[i % k];
+    out[i] = s >= 0 ? in[e * w + s] : make_double2(0.0, 0.0);
+  }
+}
+
 // y = x + z (elementwise); y may be x or z
 __global__ void k_add(double2* y, const double2* x, const double2* z, long long n) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
@@ -493,6 +517,16 @@ void launch_axpy_cols(double2* y, const double2* x, const double2* alpha,
                       double sign, long long V, int k, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy_cols, dim3(grid_for(V * k)), dim3(256), 0, st, y, x, alpha,
                      sign, V, k);
+}
+void launch_gather_cols(double2* out, const double2* in, long long V, int k, int w, int m,
+                        const ColMap& map, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(V * w)), dim3(256), 0, st, out, in, V, k, w,
+                     m, map);
+}
+void launch_scatter_cols(double2* out, const double2* in, long long V, int k, int w,
+                         const ColMap& slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_cols, dim3(grid_for(V * k)), dim3(256), 0, st, out, in, V, k, w,
+                     slot);
 }
 void launch_scale_cols(double2* y, const double2* x, const double* s, long long V,
                        int k, hipStream_t st) {

@@ -308,7 +308,8 @@ void Method::dot(const double2* a, const double2* b, long long V, double2* out) 
 // The same driver solves any KrylovSystem: the unpolarized SIE uses it with
 // one pair vector per column and no block structure.
 int Method::gmres(const KrylovSystem& S, const double2* b, double2* x,
-                  const std::vector<double>& tol, int max_iter, int restart, int* iters_out) {
+                  const std::vector<double>& tol, int max_iter, int restart, int* iters_out,
+                  helm_solve_info* info) {
   const long long V = S.V;                    // vector length per column
   const int m = std::max(1, std::min(restart, max_iter));
   const bool up = S.block;
@@ -379,7 +380,8 @@ int Method::gmres(const KrylovSystem& S, const double2* b, double2* x,
     int j = 0;
     for (; j < m && total < max_iter; ++j) {
       double2* vj = basis_vec(j);
-      S.apply(vj, w.as<double2>());
+      // (a column that stopped has a zero basis vector from here on)
+      apply_running(S, vj, w.as<double2>(), run, info);
       // K_down v_j into the down half of v_j (no longer an operand of P M)
       if (up)
         HELM_HIP(hipMemcpyAsync(vj, w.p, (size_t)off * sizeof(double2),
@@ -487,8 +489,55 @@ Method::KrylovSystem Method::polarized_system() {
   S.block = !(H.opt.flags & HELM_FLAG_FULL_KRYLOV);
   S.off = S.block ? Vp : 0;
   S.Vs = S.block ? S.V / 2 : S.V;
+  S.polarized = true;
   S.apply = [this](const double2* v, double2* w) { apply_A(v, w); };
   return S;
+}
+
+// The cached batch of width w for the operator products of narrowed GMRES
+// iterations, with its gathered operand and product (V elements per
+// column); none (and no further attempts) when device memory refuses it.
+Method* Method::krylov_narrower(int w, long long V) {
+  if (!krylov_narrow_ok || !narrow_allowed) return nullptr;
+  auto it = krylov_narrow.find(w);
+  if (it != krylov_narrow.end()) return it->second.get();
+  try {
+    std::unique_ptr<Method> c(new Method(H, w));
+    c->kv_in.alloc((size_t)V * w * sizeof(double2));
+    c->kv_out.alloc((size_t)V * w * sizeof(double2));
+    return krylov_narrow.emplace(w, std::move(c)).first->second.get();
+  } catch (const Error& e) {
+    if (e.code != HELM_ENOMEM) throw;
+    krylov_narrow_ok = false;
+    return nullptr;
+  }
+}
+
+void Method::apply_running(const KrylovSystem& S, const double2* v, double2* out,
+                           const std::vector<char>& run, helm_solve_info* info) {
+  int m = 0;
+  for (char r : run) m += r ? 1 : 0;
+  int w = 1;
+  while (w < m) w *= 2;
+  Method* C = nullptr;
+  if (S.polarized && m > 0 && 2 * w <= k && k <= kern::kMaxGatherCols &&
+      !(H.opt.flags & HELM_FLAG_NO_NARROW))
+    C = krylov_narrower(w, S.V);
+  if (!C) {
+    S.apply(v, out);
+    return;
+  }
+  kern::ColMap g{}, slot{};
+  for (int c = 0; c < kern::kMaxGatherCols; ++c) slot.col[c] = -1;
+  for (int c = 0, j = 0; c < k; ++c)
+    if (run[c]) {
+      g.col[j] = c;
+      slot.col[c] = j++;
+    }
+  kern::launch_gather_cols(C->kv_in.as<double2>(), v, S.V, k, w, m, g, H.st);
+  C->apply_A(C->kv_in.as<double2>(), C->kv_out.as<double2>());
+  kern::launch_scatter_cols(out, C->kv_out.as<double2>(), S.V, k, w, slot, H.st);
+  if (info) ++info->narrow_products;
 }
 
 // The unpolarized SIE (I - GJ) x = v on one pair vector per column.
@@ -730,7 +779,7 @@ int Method::polarized_solve(const double2* f, double2* u, const std::vector<doub
                   &iters);
   else
     st = gmres(polarized_system(), bpol.as<double2>(), xpol.as<double2>(), tol, max_iter,
-               restart, &iters);
+               restart, &iters, info);
   HELM_HIP(hipStreamSynchronize(H.st));
   double t2 = now_ms();
   // traces u_j = u_down_j + u_up_j (the unpolarized SIE solves for them)
@@ -795,7 +844,7 @@ int Method::refine_step(const double2* F, double2* U, double2* R, double2* D,
 // gathered volumes; none (and no further attempts) when device memory
 // refuses it.
 Method* Method::narrower(int w) {
-  if (!narrow_ok) return nullptr;
+  if (!narrow_ok || !narrow_allowed) return nullptr;
   if (!child || child->k != w) {
     child.reset();
     try {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <functional>
+#include <map>
 #include <memory>
 #include <vector>
 
@@ -20,7 +21,17 @@ struct Method {
   // a narrower batch for the refinement steps that only some columns need
   std::unique_ptr<Method> child;
   bool narrow_ok = true;     // cleared when device memory refused one
+  // narrower batches may be created (off for the request server's lanes,
+  // whose device memory is planned per slot)
+  bool narrow_allowed = true;
   Method* narrower(int w);
+  // narrower batches for the operator products of the GMRES iterations
+  // whose running columns fit in half the width, by width, with their
+  // gathered operand and product
+  std::map<int, std::unique_ptr<Method>> krylov_narrow;
+  DevMem kv_in, kv_out;
+  bool krylov_narrow_ok = true;
+  Method* krylov_narrower(int w, long long V);
   const LayerSet* set_all = nullptr;
   const LayerSet* set_lower = nullptr;
   std::vector<const LayerSet*> single;
@@ -65,12 +76,19 @@ struct Method {
   struct KrylovSystem {
     long long V = 0, off = 0, Vs = 0;
     bool block = false;
+    bool polarized = false;   // P M (a narrower batch can apply it)
     std::function<void(const double2*, double2*)> apply;
   };
+  // S.apply to the columns with run[c] set; the others' products are zero
+  // (their operands are zero).  Gathered into a narrower batch when they fit
+  // in half the width.
+  void apply_running(const KrylovSystem& S, const double2* v, double2* out,
+                     const std::vector<char>& run, helm_solve_info* info);
   KrylovSystem polarized_system();
   KrylovSystem sie_system();
   int gmres(const KrylovSystem& S, const double2* b, double2* x,
-            const std::vector<double>& tol, int max_iter, int restart, int* iters);
+            const std::vector<double>& tol, int max_iter, int restart, int* iters,
+            helm_solve_info* info = nullptr);
   int bicgstab(const KrylovSystem& S, const double2* b, double2* x,
                const std::vector<double>& tol, int max_iter, int* iters);
   void apply_sie(const double2* x, double2* out);

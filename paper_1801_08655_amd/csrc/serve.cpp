@@ -50,7 +50,10 @@ Method& Lane::method_for(int occ) {
   while (w < occ) w *= 2;
   w = std::min(w, K);
   auto it = methods.find(w);
-  if (it == methods.end()) it = methods.emplace(w, std::make_unique<Method>(h->impl, w)).first;
+  if (it == methods.end()) {
+    it = methods.emplace(w, std::make_unique<Method>(h->impl, w)).first;
+    it->second->narrow_allowed = false;   // the lane's memory is planned per slot
+  }
   return *it->second;
 }
 
@@ -248,7 +251,8 @@ int Server::add_model(helm_handle* h, int max_slots, int* slots_out) {
   h->method.reset();   // the lane's Methods own the solve workspace from here
   H.capture = false;   // launched one by one while the lane's thread drives it
   H.ensure_workspace(K);
-  ln->methods.emplace(K, std::make_unique<Method>(H, K));
+  ln->methods.emplace(K, std::make_unique<Method>(H, K))
+      .first->second->narrow_allowed = false;
   ln->slots.assign(K, Slot{});
   ln->node_h.assign(K, 0);
   ln->amp_h.assign(K, make_double2(0, 0));

@@ -150,7 +150,8 @@ def test_narrowed_refinement_steps_match_full_width():
     between the columns' estimates after two steps, so that 4 to 7 of the 8
     columns stop there: the third step runs at the narrower width, every
     column matches the same solve with every step at full width
-    (HELM_FLAG_NO_NARROW), and both are within err_target of the oracle."""
+    (HELM_FLAG_NO_NARROW) to the complex64 rounding of the corrections, and
+    both are within err_target of the oracle."""
     import paper_1801_08655_amd as pt
     srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12), (11, 17, 15), (5, 20, 9), (16, 6, 18),
             (12, 12, 21), (18, 18, 7)]
@@ -173,16 +174,52 @@ def test_narrowed_refinement_steps_match_full_width():
         u, inf = s.solve_points(srcs, info=True)
         out[label] = (u.cpu().numpy().reshape(k, -1).T, inf)
         print(label, "widths", inf["ir_width"], "steps", inf["rhs_ir_steps"],
-              "gmres per step", inf["ir_gmres_iters"], "layer solves", inf["layer_solves"])
+              "gmres per step", inf["ir_gmres_iters"], "layer solves", inf["layer_solves"],
+              "narrowed products", inf["narrow_products"])
         s.close()
     un, infn = out["narrow"]
     uf, inff = out["full"]
     assert infn["ir_width"][:3] == [k, k, w]
     assert all(x == k for x in inff["ir_width"])
+    assert infn["narrow_products"] > 0 and inff["narrow_products"] == 0
     assert sorted(infn["rhs_ir_steps"]) == sorted(inff["rhs_ir_steps"])
     assert sum(1 for x in infn["rhs_ir_steps"] if x == 2) == j
-    assert relative_error(un, uf).max() <= 1e-12
+    # the narrowed operator products round differently in complex64 (at one
+    # or two columns the substitutions take the vector kernels): about 1e-7
+    # of a refinement correction that is itself 1e-4 to 1e-3 of u
+    assert relative_error(un, uf).max() <= 1e-10
     assert relative_error(un, ref).max() <= 2 * t
+
+
+def test_narrowed_gmres_products_match_full_width_fp64():
+    """The complex128 path: a GMRES iteration whose running columns fit in
+    half the batch applies the operator to them alone, gathered at a narrower
+    width.  Eight sources plus eight zero-amplitude columns (converged from
+    the start) make every product a narrowed one; the eight solutions equal
+    the full-width ones (HELM_FLAG_NO_NARROW) to 1e-12 and the oracle's to
+    1e-9, and the zero columns stay zero."""
+    import paper_1801_08655_amd as pt
+    srcs = [(8, 9, 6), (14, 14, 9), (20, 8, 12), (11, 17, 15), (5, 20, 9), (16, 6, 18),
+            (12, 12, 21), (18, 18, 7)]
+    wl, srcs, ref = _reference("layered-28", srcs)
+    k = len(srcs)
+    amps = np.r_[np.ones(k), np.zeros(k)].astype(np.complex128)
+    out = {}
+    for label, flags in (("narrow", 0), ("full", pt._lib.HELM_FLAG_NO_NARROW)):
+        s = _solver(wl, "fp64", gmres_tol=1e-10, flags=flags)
+        u, inf = s.solve_points(srcs + srcs, amplitudes=amps, info=True)
+        out[label] = (u.cpu().numpy().reshape(2 * k, -1).T, inf)
+        print(label, "iterations", inf["gmres_iters"], "narrowed products",
+              inf["narrow_products"])
+        s.close()
+    un, infn = out["narrow"]
+    uf, inff = out["full"]
+    assert infn["narrow_products"] == infn["gmres_iters"] > 0
+    assert inff["narrow_products"] == 0
+    assert infn["gmres_iters"] == inff["gmres_iters"]
+    assert not np.any(un[:, k:]) and not np.any(uf[:, k:])
+    assert relative_error(un[:, :k], uf[:, :k]).max() <= 1e-12
+    assert relative_error(un[:, :k], ref).max() <= 1e-9
 
 
 @pytest.mark.parametrize("name", ["homogeneous-25", "smooth-24", "layered-28", "layered-40"])
