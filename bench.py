@@ -65,6 +65,9 @@ def parse():
                     help="at most this many problems resident at once (0: as many as "
                          "memory admits; 1: one after the other, no overlap)")
     ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--depth-rates", action="store_true",
+                    help="per-depth substitution GEMM rates of one interior layer's solve "
+                         "(the measured tile-width launches against each depth's flops)")
     ap.add_argument("--rhs-scaling", action="store_true",
                     help="RHS/s against the number of right-hand sides R = 1, 2, ..., 64 "
                          "on one factorization of the workload")
@@ -323,6 +326,50 @@ def serve_bench(args, torch, pt):
     print(json.dumps(out), flush=True)
 
 
+def depth_rates_bench(args, torch, pt):
+    """Per-depth rates of the substitution GEMMs in one interior layer's
+    local solve of R columns: the first solve of the layer measures every
+    tile width of each depth's launches (HELM_FLAG_AUTOTUNE, start and stop
+    events recorded by each launch); the kept width's time against the
+    depth's algorithmic flops (8 real flops per complex multiply-add:
+    sum (s + b) s forward, sum b s backward, times R)."""
+    from helm_inputs import workload
+    wl = workload(args.workload)
+    s = pt.Solver(wl.m(), wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
+                  pml_local=wl.pml_local, pml_C=wl.pml_C, max_rhs=args.rhs,
+                  flags=pt._lib.HELM_FLAG_AUTOTUNE)
+    layer = wl.n_layers // 4
+    _, _, lo, hi = s.layer_info(layer)
+    r = torch.randn((args.rhs, hi - lo + 1, wl.n[1], wl.n[0]), dtype=torch.complex128,
+                    device="cuda")
+    s.layer_solve(layer, r)   # the first solve of the layer set measures the widths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        s.layer_solve(layer, r)
+    torch.cuda.synchronize()
+    solve_ms = (time.perf_counter() - t0) / 3 * 1e3
+    col = {1: 0, 16: 1, 32: 2, 64: 3}
+    rows = []
+    for c in sorted(s.tile_choices(), key=lambda c: c["depth"]):
+        if c["set_layers"] != 1 or c["k"] != args.rhs:
+            continue
+        tf = c["t_fwd_us"][col[c["fwd_bn"]]]
+        tb = c["t_bwd_us"][col[c["bwd_bn"]]]
+        gf = 8.0 * args.rhs * c["fwd_elems"] / 1e9
+        gb = 8.0 * args.rhs * c["bwd_elems"] / 1e9
+        rows.append({"depth": c["depth"], "fronts": c["fronts"], "mean_s": c["mean_s"],
+                     "mean_b": c["mean_b"], "fwd_bn": c["fwd_bn"], "fwd_us": tf,
+                     "fwd_gflop": gf, "fwd_tflops": gf / tf * 1e3 if tf > 0 else None,
+                     "bwd_bm": c["bwd_bm"], "bwd_bn": c["bwd_bn"], "bwd_us": tb,
+                     "bwd_gflop": gb, "bwd_tflops": gb / tb * 1e3 if tb > 0 else None,
+                     "tuned": c["tuned"]})
+    s.close()
+    print(json.dumps({"metric": "per-depth substitution GEMM rates of one layer solve",
+                      "workload": wl.name, "layer": layer, "rhs": args.rhs,
+                      "layer_solve_ms": solve_ms, "depths": rows}), flush=True)
+
+
 def rhs_scaling_bench(args, torch, pt):
     """Throughput against the batch width R on one mixed-precision
     factorization: R columns share every layer solve (the substitution GEMMs
@@ -413,6 +460,9 @@ def main():
         return
     if args.rhs_scaling:
         rhs_scaling_bench(args, torch, pt)
+        return
+    if args.depth_rates:
+        depth_rates_bench(args, torch, pt)
         return
     if args.batch:
         if args.slots == 32:

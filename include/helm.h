@@ -293,6 +293,11 @@ typedef struct {
   double mean_s, mean_b;   /* mean pivot / boundary size of the depth's fronts */
   int    fwd_bn, bwd_bn, bwd_bm, tuned;
   double t_fwd_us[4], t_bwd_us[4];
+  double fwd_elems;        /* sum of (s + b) s over the forward list: the
+                              forward product's complex multiply-adds per
+                              column */
+  double bwd_elems;        /* sum of b s over the backward list (the same
+                              for the backward product) */
 } helm_tile_choice;
 
 int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count);

@@ -146,7 +146,8 @@ class helm_tile_choice(ctypes.Structure):
                 ("fronts", ctypes.c_int), ("mean_s", ctypes.c_double),
                 ("mean_b", ctypes.c_double), ("fwd_bn", ctypes.c_int),
                 ("bwd_bn", ctypes.c_int), ("bwd_bm", ctypes.c_int), ("tuned", ctypes.c_int),
-                ("t_fwd_us", ctypes.c_double * 4), ("t_bwd_us", ctypes.c_double * 4)]
+                ("t_fwd_us", ctypes.c_double * 4), ("t_bwd_us", ctypes.c_double * 4),
+                ("fwd_elems", ctypes.c_double), ("bwd_elems", ctypes.c_double)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}

@@ -333,6 +333,8 @@ int helm_tile_choices(helm_handle* h, helm_tile_choice* out, int max, int* count
             o.t_fwd_us[w] = c.t_fwd[w];
             o.t_bwd_us[w] = c.t_bwd[w];
           }
+          o.fwd_elems = D.fl_sbs;
+          o.bwd_elems = D.sum_bs;
         }
         ++n;
       }
