@@ -831,13 +831,14 @@ void Handle::launch_fwd(const DepthList& D, const FrontDev* fr, const LayerDev* 
 }
 template <typename T>
 void Handle::launch_bwd(const DepthList& D, const FrontDev* fr, const LayerDev* ld, int k,
-                        void* scr, int bn) {
+                        void* scr, int bn, hipEvent_t t0, hipEvent_t t1) {
   if (bn == 1)
     kern::launch_bwd_gemv<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
-                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, st);
+                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, st, t0, t1);
   else
     kern::launch_bwd_gemm<T>(fr, D.ids.as<int>(), D.tasks.as<SolveTask>(), D.n,
-                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, bn, gemm3m, st);
+                             D.pBw.as<int2>(), D.tBw, ld, k, scr, D.bwd_bm, bn, gemm3m, st,
+                             t0, t1);
 }
 
 const std::vector<Handle::TileChoice>& Handle::tile_plan(const LayerSet& set, int k) {
@@ -990,13 +991,19 @@ void Handle::run_layers_t(const LayerSet& set, int k, const LayerDev* ld, void* 
     if (D.n == 0) continue;
     const int* ids = D.ids.as<int>();
     const SolveTask* tk = D.tasks.as<SolveTask>();
-    hipEvent_t a = prof_begin(K_BWD_GEMM);
-    launch_bwd<T>(D, fr, ld, k, scr, bwd_bn(d));
+    // timed by the launch itself, as the forward GEMM
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (timing && timed(K_BWD_GEMM)) {
+      t0 = take_event();
+      t1 = take_event();
+    }
+    launch_bwd<T>(D, fr, ld, k, scr, bwd_bn(d), t0, t1);
     // factor block read once; X(B) rows read, Z(S) read, X(S) written
-    prof_end(K_BWD_GEMM, a, 8.0 * D.sum_bs * kk,
-             D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e);
+    if (t0)
+      pending.push_back(PendingEvent{K_BWD_GEMM, t0, t1, 8.0 * D.sum_bs * kk,
+                                     D.sum_bs * e + (D.sum_b + 2.0 * D.sum_s) * kk * e});
     if (D.tRB > 0) {
-      a = prof_begin(K_BWD_REDUCE);
+      hipEvent_t a = prof_begin(K_BWD_REDUCE);
       kern::launch_bwd_reduce<T>(fr, ids, tk, D.n, D.rB.as<int2>(), D.tRB, ld, k, scr, st);
       prof_end(K_BWD_REDUCE, a, 0, 0);
     }

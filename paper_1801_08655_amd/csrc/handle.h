@@ -152,7 +152,8 @@ struct Handle {
                                         const LayerDev* ld, int k, void* scr, int bn,
                                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
   template <typename T> void launch_bwd(const DepthList& D, const FrontDev* fr,
-                                        const LayerDev* ld, int k, void* scr, int bn);
+                                        const LayerDev* ld, int k, void* scr, int bn,
+                                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
   // kernel timing (HELM_FLAG_PROFILE: every class; HELM_FLAG_PROFILE_FWD:
   // the forward substitution GEMM only), one bit per KClass

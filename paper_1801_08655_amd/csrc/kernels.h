@@ -85,7 +85,8 @@ void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
 template <typename T>
 void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, hipStream_t st);
+                     void* scratch, int bm, hipStream_t st, hipEvent_t t0 = nullptr,
+                     hipEvent_t t1 = nullptr);
 template <typename T>
 void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int2* tmap, int total, const LayerDev* layers, int k,
@@ -93,7 +94,8 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, int bn, bool m3, hipStream_t st);
+                     void* scratch, int bm, int bn, bool m3, hipStream_t st,
+                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 template <typename T>
 void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                        const int2* tmap, int total, const LayerDev* layers, int k,

@@ -578,15 +578,21 @@ void launch_fwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
 template <typename T>
 void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, hipStream_t st) {
+                     void* scratch, int bm, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (total_tiles <= 0) return;
-#define HELM_BWDV(KC_)                                                                     \
-  if (bm == 32)                                                                            \
-    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 4, 32>), dim3(total_tiles), dim3(256), 0, st,   \
-                       fr, ids, tasks, n, tmap, layers, k, scratch);                       \
+#define HELM_BWDV1(RPG_, KC_)                                                              \
+  if (t0)                                                                                  \
+    hipExtLaunchKernelGGL((k_bwd_gemv<T, KC_, RPG_, 32>), dim3(total_tiles), dim3(256), 0, \
+                          st, t0, t1, 0, fr, ids, tasks, n, tmap, layers, k, scratch);     \
   else                                                                                     \
-    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, 8, 32>), dim3(total_tiles), dim3(256), 0, st,   \
-                       fr, ids, tasks, n, tmap, layers, k, scratch)
+    hipLaunchKernelGGL((k_bwd_gemv<T, KC_, RPG_, 32>), dim3(total_tiles), dim3(256), 0,    \
+                       st, fr, ids, tasks, n, tmap, layers, k, scratch)
+#define HELM_BWDV(KC_)                                                                     \
+  if (bm == 32) {                                                                          \
+    HELM_BWDV1(4, KC_);                                                                    \
+  } else {                                                                                 \
+    HELM_BWDV1(8, KC_);                                                                    \
+  }
   switch (k) {
     case 1: HELM_BWDV(1); break;
     case 2: HELM_BWDV(2); break;
@@ -594,6 +600,7 @@ void launch_bwd_gemv(const FrontDev* fr, const int* ids, const SolveTask* tasks,
     default: HELM_BWDV(4); break;
   }
 #undef HELM_BWDV
+#undef HELM_BWDV1
 }
 
 template <typename T>
@@ -646,22 +653,27 @@ void launch_fwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
 template <typename T>
 void launch_bwd_gemm(const FrontDev* fr, const int* ids, const SolveTask* tasks, int n,
                      const int2* tmap, int total_tiles, const LayerDev* layers, int k,
-                     void* scratch, int bm, int bn, bool m3, hipStream_t st) {
+                     void* scratch, int bm, int bn, bool m3, hipStream_t st, hipEvent_t t0,
+                     hipEvent_t t1) {
   if (total_tiles <= 0) return;
   // a 32 x 16 tile has fewer MFMA blocks than waves: use 32 columns there
   if (bm == 32 && bn == 16) bn = 32;
   const int ntn = (k + bn - 1) / bn;
   const dim3 grid(total_tiles * ntn);
 #define HELM_BWD(BM_, BN_, M3_)                                                              \
-  hipLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_, M3_>), grid, dim3(256), 0, st, fr, ids, tasks, \
-                     n, tmap, layers, k, scratch)
+  if (t0)                                                                                    \
+    hipExtLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_, M3_>), grid, dim3(256), 0, st, t0, t1, 0, \
+                          fr, ids, tasks, n, tmap, layers, k, scratch);                      \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_bwd_gemm<T, BM_, BN_, M3_>), grid, dim3(256), 0, st, fr, ids,      \
+                       tasks, n, tmap, layers, k, scratch)
 #define HELM_BWD_ALL(M3_)                                                                   \
   if (bm == 32) {                                                                           \
-    if (bn == 32) HELM_BWD(32, 32, M3_); else HELM_BWD(32, 64, M3_);                        \
+    if (bn == 32) { HELM_BWD(32, 32, M3_); } else { HELM_BWD(32, 64, M3_); }                \
   } else {                                                                                  \
-    if (bn == 16) HELM_BWD(64, 16, M3_);                                                    \
-    else if (bn == 32) HELM_BWD(64, 32, M3_);                                               \
-    else HELM_BWD(64, 64, M3_);                                                             \
+    if (bn == 16) { HELM_BWD(64, 16, M3_); }                                                \
+    else if (bn == 32) { HELM_BWD(64, 32, M3_); }                                           \
+    else { HELM_BWD(64, 64, M3_); }                                                         \
   }
   constexpr bool C64 = sizeof(T) == 4;   // the three-product form is for complex64
   if (C64 && m3) {
@@ -697,7 +709,8 @@ void launch_bwd_reduce(const FrontDev* fr, const int* ids, const SolveTask* task
                                      const void*, hipStream_t);                      \
   template void launch_bwd_gemm<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
-                                   void*, int, int, bool, hipStream_t);              \
+                                   void*, int, int, bool, hipStream_t, hipEvent_t,    \
+                                   hipEvent_t);                                      \
   template void launch_bwd_reduce<T>(const FrontDev*, const int*, const SolveTask*,  \
                                      int, const int2*, int, const LayerDev*, int,     \
                                      const void*, hipStream_t);
@@ -710,7 +723,7 @@ HELM_INST_SOLVE(double)
                                    void*, hipStream_t, hipEvent_t, hipEvent_t);      \
   template void launch_bwd_gemv<T>(const FrontDev*, const int*, const SolveTask*,    \
                                    int, const int2*, int, const LayerDev*, int,       \
-                                   void*, int, hipStream_t);
+                                   void*, int, hipStream_t, hipEvent_t, hipEvent_t);
 HELM_INST_GEMV(float)
 HELM_INST_GEMV(double)
 
