@@ -138,9 +138,12 @@ typedef struct {
   double inner_tol;        /* mixed: GMRES tolerance of the first solve      */
   double inner_tol_refine; /* mixed: GMRES tolerance of later refinement steps
                               (<= 0: same as inner_tol)                      */
-  double err_target;       /* mixed: also stop once the estimated error of
-                              every column is at most half of this (a factor
-                              2 margin against the estimate; <= 0: off)      */
+  double err_target;       /* mixed: a column also stops once its estimated
+                              error is at most a quarter of this after the
+                              second solve (the estimate then rests on one
+                              measured contraction) or at most half of it
+                              from the third on (a factor 4 / 2 margin
+                              against the estimate; <= 0: off)              */
   size_t hbm_budget_bytes; /* 0 = 90% of free device memory                  */
   int    device;           /* HIP device ordinal                             */
   void*  stream;           /* hipStream_t for the *_dev entry points (NULL = default) */
@@ -153,7 +156,7 @@ typedef struct {
                               bound still caps it                           */
   double inner_tol_final;  /* mixed: GMRES tolerance of a step taken when a
                               column's estimated error is already within
-                              err_target but not within the half of it that
+                              err_target but not within the part of it that
                               stops the column (<= 0: inner_tol_refine)     */
 } helm_options;
 

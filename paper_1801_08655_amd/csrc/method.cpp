@@ -980,7 +980,7 @@ int Method::solve(const double2* f, double2* u, helm_solve_info* info, int col0)
         // the relative residual GMRES reached stands for the step's tolerance
         est_c[c] = refinement_error(it, track[c], nm.dn[c], nm.un[c], teff[c]);
         iters_c[c] += citer[c];
-        if (refinement_met(rel[c], est_c[c], o)) {
+        if (refinement_met(it, rel[c], est_c[c], o)) {
           met[c] = 1;
           steps_c[c] = steps;
         }
@@ -1061,7 +1061,7 @@ double refinement_error(int step, RefineTrack& tr, double dcur, double unorm, do
 }
 
 // Tolerance of a column's next step: inner_tol for the first solve; once the
-// estimated error is within err_target (but not yet within the half of it
+// estimated error is within err_target (but not yet within the part of it
 // that stops the column), the step only has to shrink the error by a modest
 // factor, and runs to the looser inner_tol_final; otherwise inner_tol_refine.
 double refinement_tol(int step, const RefineTrack& tr, const helm_options& o) {
@@ -1071,8 +1071,11 @@ double refinement_tol(int step, const RefineTrack& tr, const helm_options& o) {
   return o.inner_tol_refine;
 }
 
-bool refinement_met(double rel, double est, const helm_options& o) {
-  return rel <= o.ir_tol || (o.err_target > 0 && est <= 0.5 * o.err_target);
+bool refinement_met(int step, double rel, double est, const helm_options& o) {
+  // after the second solve (one measured contraction) a factor 4 against
+  // the estimate, from the third on a factor 2
+  const double margin = step <= 1 ? 0.25 : 0.5;
+  return rel <= o.ir_tol || (o.err_target > 0 && est <= margin * o.err_target);
 }
 
 // Restart length: the caller's gmres_restart when set, capped by what device

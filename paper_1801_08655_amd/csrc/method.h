@@ -122,8 +122,10 @@ struct RefineTrack {
 double refinement_error(int step, RefineTrack& tr, double dcur, double unorm, double tol);
 // GMRES tolerance of a column's next step (0-based step index).
 double refinement_tol(int step, const RefineTrack& tr, const helm_options& o);
-// Whether a column may stop: FP64 residual at ir_tol, or estimated error at
-// most half of err_target (a factor-2 margin against the estimate).
-bool refinement_met(double rel, double est, const helm_options& o);
+// Whether a column may stop after step `step` (0-based): FP64 residual at
+// ir_tol, or estimated error at most a quarter of err_target after the
+// second solve (the estimate rests on one measured contraction) and at most
+// half of it from the third on.
+bool refinement_met(int step, double rel, double est, const helm_options& o);
 
 }  // namespace helm

@@ -140,7 +140,7 @@ void Server::run_lane(Lane& ln) {
           if (H.G.L > 1 && !(M.last_resid.size() > (size_t)s && M.last_resid[s] <= H.opt.gmres_tol))
             status = HELM_ENOCONV;
         } else {
-          const bool ok = refinement_met(rel, est, H.opt);
+          const bool ok = refinement_met(st, rel, est, H.opt);
           f = ok || sl.steps >= std::max(1, H.opt.ir_max_steps);
           if (!ok) status = HELM_ENOCONV;
         }

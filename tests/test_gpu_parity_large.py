@@ -147,7 +147,8 @@ def test_narrowed_refinement_steps_match_full_width():
     """A column that meets the target leaves the refinement, and a later
     step whose remaining columns fit in half the batch runs them gathered at
     the narrowest power-of-two width.  err_target is placed in the widest gap
-    between the columns' estimates after two steps, so that 4 to 7 of the 8
+    between the columns' estimates after two steps (a stop there needs the
+    estimate within a quarter of err_target), so that 4 to 7 of the 8
     columns stop there: the third step runs at the narrower width, every
     column matches the same solve with every step at full width
     (HELM_FLAG_NO_NARROW) to the complex64 rounding of the corrections, and
@@ -170,7 +171,7 @@ def test_narrowed_refinement_steps_match_full_width():
     assert e2[j] > 1.05 * e2[j - 1]
     out = {}
     for label, flags in (("narrow", 0), ("full", pt._lib.HELM_FLAG_NO_NARROW)):
-        s = _solver(wl, "mixed", ir_tol=1e-300, err_target=2 * t, ir_max_steps=6, flags=flags)
+        s = _solver(wl, "mixed", ir_tol=1e-300, err_target=4 * t, ir_max_steps=6, flags=flags)
         u, inf = s.solve_points(srcs, info=True)
         out[label] = (u.cpu().numpy().reshape(k, -1).T, inf)
         print(label, "widths", inf["ir_width"], "steps", inf["rhs_ir_steps"],
@@ -188,7 +189,7 @@ def test_narrowed_refinement_steps_match_full_width():
     # or two columns the substitutions take the vector kernels): about 1e-7
     # of a refinement correction that is itself 1e-4 to 1e-3 of u
     assert relative_error(un, uf).max() <= 1e-10
-    assert relative_error(un, ref).max() <= 2 * t
+    assert relative_error(un, ref).max() <= 4 * t
 
 
 def test_narrowed_gmres_products_match_full_width_fp64():
