@@ -148,10 +148,13 @@ def roofline(stats, precision, workload):
             "traffic": traffic, "launches": st["launches"], "avg_launch_ms": avg_ms}
 
 
-def small_k_probe(s, wl, torch, layer=5, reps=3):
-    """One-column local solves of an interior layer (the HBM-bound regime of
-    the substitutions): algorithmic bytes of the forward / backward GEMM
-    classes per event-timed second, against the 8 TB/s HBM peak."""
+def small_k_probe(s, wl, torch, layer=None, reps=3):
+    """One-column local solves of an interior layer (layer 5, or the middle
+    one when there are fewer than 10; the HBM-bound regime of the
+    substitutions): algorithmic bytes of the forward / backward GEMM classes
+    per event-timed second, against the 8 TB/s HBM peak."""
+    if layer is None:
+        layer = min(5, wl.n_layers // 2)
     _, _, lo, hi = s.layer_info(layer)
     r = torch.randn((1, hi - lo + 1, wl.n[1], wl.n[0]), dtype=torch.complex128,
                     device="cuda")
