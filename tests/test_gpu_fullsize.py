@@ -3,7 +3,8 @@ the oracle supplying the operator:
 
 * the headline (200^3, L = 20, 64 sources, the launch configuration of
   bench.py) in mixed precision and on the complex128 path;
-* the smooth random medium at 100^3 (L = 10) on the complex128 path;
+* the smooth random medium at 100^3 (L = 10) on the complex128 path, and
+  in mixed precision against it;
 
 * the oracle's own assembly of H gives |f - H u| / |f| for sampled columns
   of the GPU solution; the mixed refinement stops at an estimated error of
@@ -76,6 +77,33 @@ def test_smooth_100_fp64_residual_and_reciprocity():
     cols = {c: u[c].cpu().numpy().ravel() for c in range(3)}
     s.close()
     _check(wl, m, srcs, cols, [0, 1, 2], ((0, 1), (0, 2), (1, 2)), 1e-9, 1e-8)
+
+
+def test_smooth_100_mixed_matches_the_complex128_path():
+    """The same medium and sources in mixed precision with the library's
+    default refinement settings and a 1e-6 error target: every column within
+    1e-6 of the complex128 path's solution (GMRES to 1e-10, itself pinned
+    by the residual test above), and every column's estimate within the
+    target."""
+    import paper_1801_08655_amd as pt
+    wl = workload("smooth-100")
+    m = wl.m()
+    srcs = list(wl.sources) + [(40, 57, 15), (61, 44, 52)]
+    out = {}
+    for prec, kw in (("mixed", dict(err_target=1e-6)), ("fp64", dict(gmres_tol=1e-10))):
+        s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision=prec,
+                      pml_local=wl.pml_local, pml_C=wl.pml_C, **kw)
+        u, info = s.solve_points(srcs, info=True)
+        out[prec] = (u.cpu().numpy().reshape(len(srcs), -1), info)
+        s.close()
+    um, info = out["mixed"]
+    ur, _ = out["fp64"]
+    err = np.linalg.norm(um - ur, axis=1) / np.linalg.norm(ur, axis=1)
+    print("error vs complex128", err, "estimates", info["rhs_est_error"],
+          "steps", info["rhs_ir_steps"], "gmres per step", info["ir_gmres_iters"])
+    assert info["ir_steps"] < 6   # stopped on the estimate, before the step limit
+    assert max(info["rhs_est_error"]) <= 1e-6
+    assert err.max() <= 1e-6
 
 
 def test_layered_200_residual_and_reciprocity():
