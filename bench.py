@@ -31,11 +31,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solved RHS/s at n=200³, rel.err≤1e-6, mixed vs FP64; p50/p99 latency"
 PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
-# Mixed-precision refinement settings of every mixed run here: GMRES to 7e-4
-# in the first solve and to 1e-4 in the refinement steps, FP64 residual
+# Mixed-precision refinement settings of every mixed run here: GMRES to 5e-4
+# in the first solve and to 2e-4 in the refinement steps, FP64 residual
 # tolerance 1e-10, stop on an estimated error of 1e-6 (at 200^3 every column
 # then stops after two solves; with 1e-3 / 2e-4 ten of 64 took a third)
-MIXED_KW = dict(ir_tol=1e-10, inner_tol=7e-4, inner_tol_refine=1e-4, err_target=1e-6,
+MIXED_KW = dict(ir_tol=1e-10, inner_tol=5e-4, inner_tol_refine=2e-4, err_target=1e-6,
                 ir_max_steps=4)
 
 

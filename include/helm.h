@@ -205,7 +205,7 @@ typedef struct {
 
 /* Fill `opt` with defaults: pml_local 4, pml_C 0 (auto), HELM_MIXED,
  * gmres_tol 1e-10, gmres_max_iter 40, ir_tol 1e-9, ir_max_steps 6,
- * inner_tol 7e-4, inner_tol_refine 1e-4, err_target 0 (off), hbm_budget 0
+ * inner_tol 5e-4, inner_tol_refine 2e-4, err_target 0 (off), hbm_budget 0
  * (auto), device 0, stream NULL, max_rhs 64, leaf_size 64, flags 0,
  * gmres_restart 0 (memory-bound, at most 60), inner_tol_final 1e-1. */
 void helm_default_options(helm_options* opt);

@@ -114,8 +114,8 @@ void helm_default_options(helm_options* o) {
   o->gmres_max_iter = 40;
   o->ir_tol = 1e-9;
   o->ir_max_steps = 6;
-  o->inner_tol = 7e-4;
-  o->inner_tol_refine = 1e-4;
+  o->inner_tol = 5e-4;
+  o->inner_tol_refine = 2e-4;
   o->err_target = 0.0;
   o->hbm_budget_bytes = 0;
   o->device = 0;

@@ -112,8 +112,8 @@ def test_layered_200_residual_and_reciprocity():
     m = wl.m()
     srcs = wl.point_sources(64)
     s = pt.Solver(m, wl.h, wl.omega, wl.pml, wl.n_layers, precision="mixed",
-                  pml_local=wl.pml_local, pml_C=wl.pml_C, ir_tol=1e-10, inner_tol=7e-4,
-                  inner_tol_refine=1e-4, err_target=1e-6, ir_max_steps=4,
+                  pml_local=wl.pml_local, pml_C=wl.pml_C, ir_tol=1e-10, inner_tol=5e-4,
+                  inner_tol_refine=2e-4, err_target=1e-6, ir_max_steps=4,
                   flags=pt._lib.HELM_FLAG_AUTOTUNE)
     u, info = s.solve_points(srcs, info=True)
     print(info)

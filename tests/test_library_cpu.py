@@ -230,5 +230,5 @@ def test_binding_constants_match_the_header():
 def test_default_refinement_options():
     """Defaults of the refinement stop rule (documented in helm.h)."""
     o = pt.options()
-    assert o.inner_tol == pytest.approx(7e-4) and o.inner_tol_refine == pytest.approx(1e-4)
+    assert o.inner_tol == pytest.approx(5e-4) and o.inner_tol_refine == pytest.approx(2e-4)
     assert o.inner_tol_final == pytest.approx(1e-1) and o.gmres_restart == 0
